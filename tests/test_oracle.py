@@ -1,0 +1,334 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test pins the oracle to something other than itself: hand-worked cases, a library
+routine for a special case, brute force over tiny alphabets, printed values of the paper,
+closed forms and invariants.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1201_3018_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- eq. (1), correlation
+def test_conv_hand_examples():
+    for case in _gold("hand_examples.json")["conv"]:
+        assert np.array_equal(O.conv_direct(case["s"], case["k"]), np.array(case["r"], dtype=float))
+        assert np.array_equal(O.conv_int_range(case["s"], case["k"], 0, len(case["r"])), case["r"])
+
+
+def test_conv_matches_library_routine():
+    rng = np.random.default_rng(7)
+    for L, N in [(1, 1), (5, 5), (100, 7), (1000, 64), (4097, 33)]:
+        s, k = rng.standard_normal(L), rng.standard_normal(N)
+        ref = np.convolve(s, k)
+        assert np.allclose(O.conv_direct(s, k), ref, rtol=0, atol=1e-12 * np.sum(np.abs(k)) * np.max(np.abs(s)))
+        si, ki = rng.integers(-1000, 1000, L), rng.integers(-1000, 1000, N)
+        assert np.array_equal(O.conv_int_range(si, ki, 0, L + N - 1), np.convolve(si, ki))
+        assert np.array_equal(O.conv_int_range(si, ki, 3, min(L + N - 1, 40)), np.convolve(si, ki)[3:min(L + N - 1, 40)])
+
+
+def test_xcorr_hand_and_library():
+    case = _gold("hand_examples.json")["xcorr"][0]
+    c = O.xcorr_direct(case["s"], case["k"])
+    assert np.array_equal(c, np.array(case["c"], dtype=float))
+    assert O.argmax_lag(c, len(case["k"]))[0] == case["argmax_lag"]
+    assert np.array_equal(O.xcorr(case["s"], case["k"]), c)
+    rng = np.random.default_rng(3)
+    s, k = rng.standard_normal(50), rng.standard_normal(9)
+    assert np.allclose(O.xcorr_direct(s, k), np.correlate(s, k, "full"), atol=1e-12)
+    assert np.allclose(O.xcorr(s, k), np.correlate(s, k, "full"), atol=1e-12)
+
+
+def test_argmax_ties_smallest_lag():
+    c = np.array([0.0, 3.0, 1.0, 3.0])
+    assert O.argmax_lag(c, 2) == (0, 3.0)
+
+
+# ---------------------------------------------------------------- partition and placement
+@pytest.mark.parametrize("L,N,Wb", [(65536, 64, 1024), (5000, 65, 1024), (3000, 7, 64), (131, 3, 32),
+                                    (40, 40, 200), (1, 1, 8), (958, 64, 1024), (959, 64, 1024)])
+def test_partition_identity_full_precision(L, N, Wb):
+    """Blocked full-precision overlap-save with the eq. (17) placement equals eq. (1)."""
+    rng = np.random.default_rng(L + N)
+    s, k = rng.standard_normal(L), rng.standard_normal(N)
+    ps = O.fixed_params(s, k, Wb, O.FULL, 0, 0)
+    r = O.conv_blocked(s, k, Wb, ps, out_dtype=np.float64)
+    ref = np.convolve(s, k)
+    assert r.size == L + N - 1
+    assert np.allclose(r, ref, rtol=0, atol=1e-11 * np.sum(np.abs(k)) * np.max(np.abs(s)))
+
+
+def test_partition_shapes_and_errors():
+    p = O.partition(65536, 64, 1024)
+    assert (p.N_odd, p.W, p.P) == (65, 958, 69)
+    assert list(p.starts[:3]) == [0, 956, 1914]
+    p = O.partition(1 << 22, 1024, 4096)
+    assert (p.N_odd, p.W, p.P) == (1025, 3070, 1367)
+    with pytest.raises(ValueError):
+        O.partition(1000, 64, 1025)   # W odd
+    with pytest.raises(ValueError):
+        O.partition(1000, 64, 100)    # W < 2N
+    with pytest.raises(ValueError):
+        O.partition(10, 11, 100)      # kernel longer than input
+
+
+# ---------------------------------------------------------------- companding, range, eps
+def test_compand():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(1000).astype(np.float32)
+    c, q = O.compand(x, 38)
+    assert c == 38.0 / float(np.max(np.abs(x)))
+    assert np.max(np.abs(q)) == 38 and np.all(np.abs(q) <= 38)
+    assert np.array_equal(q, np.rint(c * x.astype(np.float64)))
+    c0, q0 = O.compand(np.zeros(10), 5)
+    assert c0 == 0.0 and not np.any(q0)
+    _, qh = O.compand(np.array([0.5, 1.5, 2.5, -0.5, 4.0]), 4)  # c = 1: ties go to even
+    assert list(qh) == [0, 2, 2, 0, 4]
+
+
+def test_range_and_epsilon_closed_forms():
+    assert O.r_max(65, 38, 38) == 93860
+    assert O.r_max(1025, 205, 205) == 43075625
+    assert O.epsilon(12) == 1.0 / 24.0
+    g = _gold("paper_values.json")["companding_range_bound"]
+    assert (O.SYM_BOUND, O.ASYM2_BOUND, O.ASYM3_BOUND) == (g["sym"], g["asym2"], g["asym3"])
+    # three base-2R digits (symmetric) and two (asymmetric M=2) fill the same FP64 capacity
+    assert abs((2 * g["sym"]) ** 3 / (2 * g["asym2"]) ** 2 - 1.0) < 1e-4
+    assert (O.max_q(O.SYM, 65), O.max_q(O.SYM, 1025), O.max_q(O.ASYM2, 65), O.max_q(O.ASYM2, 1025)) == (38, 9, 814, 205)
+    for mode in O.PACKED_MODES:
+        for N in (3, 65, 801, 1025, 4097):
+            q = O.max_q(mode, N)
+            assert N * q * q <= O.BOUND[mode] < N * (q + 1) * (q + 1)
+
+
+# ---------------------------------------------------------------- symmetric packing
+def test_sym_hand_example():
+    g = _gold("hand_examples.json")["sym_pack"]
+    R = O.r_max(g["N"], g["S"], g["K"])
+    assert R == g["R"]
+    kbar = O.pack_sym_kernel(g["k_tilde"], 2 * R)
+    assert list(kbar) == g["k_bar"]
+    sbar = O.pack_sym_signal(g["s_tilde"], O.epsilon(R))
+    assert np.allclose(sbar * 24, g["s_bar_times_24"], atol=1e-12)
+    rbar = O.conv_direct(sbar, kbar)
+    assert abs(rbar[0] * 24 - g["r_bar0_times_24"]) < 1e-9
+    dec = O.unpack_sym(rbar, R, 0, 3)
+    assert list(dec) == g["r_tilde"][:6]
+    assert list(np.convolve(g["s_tilde"], g["k_tilde"])) == g["r_tilde"]
+
+
+def test_sym_brute_force_tiny_alphabet():
+    """N = 3, S = K = 2 (R = 12): every kernel in {-2..2}^3 and every 6-sample signal in
+    {-2..2}^6 (1,953,125 cases).  Decoded fields equal the integer convolution except exactly
+    where a base digit r~[2m+1] equals +R_max (every product extreme with one sign), the
+    overlap case of the packing."""
+    S = K = 2
+    N = 3
+    R = O.r_max(N, S, K)
+    vals = np.arange(-S, S + 1)
+    sig = np.array(list(itertools.product(vals, repeat=6)), dtype=np.int64)  # 15625 x 6
+    sbar = O.pack_sym_signal(sig, O.epsilon(R))                               # eq. (4), 3 words
+    total_bad = 0
+    for kq in itertools.product(vals, repeat=N):
+        kq = np.array(kq, dtype=np.int64)
+        kbar = O.pack_sym_kernel(kq, 2 * R)                                   # eq. (5), 2 words
+        rbar = np.zeros_like(sbar)                                            # eq. (9), in order
+        for m in range(3):
+            for n in range(2):
+                if m - n >= 0:
+                    rbar[:, m] = rbar[:, m] + sbar[:, m - n] * kbar[n]
+        got = O.unpack_sym(rbar, R, 0, 3)                                     # eqs. (11)-(15)
+        full = np.zeros((sig.shape[0], 6), dtype=np.int64)                    # brute force
+        for j in range(6):
+            for n in range(N):
+                if j - n >= 0:
+                    full[:, j] += sig[:, j - n] * kq[n]
+        bad = got != full
+        base = full[:, 1::2]
+        word_bad = bad[:, 0::2] | bad[:, 1::2]
+        allowed = base == R
+        allowed_prev = np.concatenate([np.zeros((base.shape[0], 1), bool), base[:, :-1] == R], axis=1)
+        assert not np.any(word_bad & ~(allowed | allowed_prev)), kq
+        total_bad += int(np.sum(bad))
+    assert total_bad > 0   # the +R_max pattern exists and is the only failure
+
+
+def test_sym_printed_eq5_is_correlation_form():
+    """Reading R1: with eps^-1 on the odd taps (eq. 5 as printed) the decoded fields are not
+    convolution outputs; they are the correlation fields (base c[2m], side c[2m-1])."""
+    rng = np.random.default_rng(11)
+    N, S, K = 9, 6, 6
+    R = O.r_max(N, S, K)
+    sq = rng.integers(-S, S + 1, 64)
+    kq = rng.integers(-K, K + 1, N)
+    eps = O.epsilon(R)
+    sbar = O.pack_sym_signal(sq, eps)
+    good = O.unpack_sym(O.conv_direct(sbar, O.pack_sym_kernel(kq, 2 * R))[:32], R, 0, 32)
+    assert np.array_equal(good, np.convolve(sq, kq)[:64])
+    bad = O.unpack_sym(O.conv_direct(sbar, O.pack_sym_kernel_printed(kq, 2 * R))[:32], R, 0, 32)
+    assert np.mean(bad == np.convolve(sq, kq)[:64]) < 0.5
+
+
+def test_asym_brute_force_tiny_alphabet():
+    """M = 2, N = 3, S = K = 2: all kernels and all 4-sample parts; digits decode to the
+    integer convolution except where a lower digit's neighbour digit is +-R_max."""
+    S = K = 2
+    N, M = 3, 2
+    R = O.r_max(N, S, K)
+    eps = O.epsilon(R)
+    vals = np.arange(-S, S + 1)
+    p = np.array(list(itertools.product(vals, repeat=3)), dtype=np.int64)     # 125 windows of 3
+    a = np.repeat(p, p.shape[0], axis=0)
+    b = np.tile(p, (p.shape[0], 1))
+    sbar = a + eps * b                                                        # eq. (7), 2 parts
+    nbad = 0
+    for kq in itertools.product(vals, repeat=N):
+        kq = np.array(kq[::-1], dtype=np.int64)
+        rbar = sbar[:, 2] * kq[0] + sbar[:, 1] * kq[1] + sbar[:, 0] * kq[2]   # output word 2
+        d = np.zeros((M, rbar.size), dtype=np.int64)
+        x = rbar.copy()
+        for q in range(M):
+            dq = np.rint(x)
+            d[q] = dq.astype(np.int64)
+            x = (x - dq) * (2.0 * R)
+        ref0 = a[:, 2] * kq[0] + a[:, 1] * kq[1] + a[:, 0] * kq[2]
+        ref1 = b[:, 2] * kq[0] + b[:, 1] * kq[1] + b[:, 0] * kq[2]
+        ok = (d[0] == ref0) & (d[1] == ref1)
+        assert np.all(ok | (np.abs(ref1) == R)), kq
+        nbad += int(np.sum(~ok))
+        assert np.array_equal(O.unpack_asym(rbar, R, M), d)
+    assert nbad > 0
+
+
+# ---------------------------------------------------------------- the method vs the plain definition
+@pytest.mark.parametrize("mode,S,core", [(O.SYM, 38, "td"), (O.SYM, 38, "fft"), (O.ASYM2, 127, "td"),
+                                         (O.ASYM2, 814, "fft"), (O.ASYM3, 38, "td"), (O.ASYM3, 38, "fft")])
+def test_method_reaches_plain_definition_c1(mode, S, core):
+    s, k = synth.gaussian(65536, 1001), synth.uniform(64, 1002)
+    r, f = O.conv_blocked_paper(s, k, 1024, mode, S, S, core=core)
+    r2, f2, _ = O.conv_blocked(s, k, 1024, O.fixed_params(s, k, 1024, mode, S, S), return_fields=True)
+    assert np.array_equal(f, f2)
+    assert np.array_equal(r, r2)
+
+
+@pytest.mark.parametrize("mode,S,core", [(O.SYM, 9, "td"), (O.SYM, 9, "fft"), (O.ASYM2, 205, "fft"), (O.ASYM2, 205, "td")])
+def test_method_reaches_plain_definition_c2_at_bound(mode, S, core):
+    s = synth.ar1(40 * 3070, 2001)
+    k = synth.hann_lowpass(1024)
+    _, f = O.conv_blocked_paper(s, k, 4096, mode, S, S, core=core)
+    f2 = O.int_fields(s, k, 4096, S, S)
+    assert np.array_equal(f, f2)
+
+
+def test_beyond_bound_decoding_fails():
+    """Symmetric packing at 8 bits per sample (S=K=127, N=65: R = 1,048,385 > 97,667) is
+    outside Table 1's range and decoding breaks; the plain definition is unaffected."""
+    s, k = synth.gaussian(8192, 1001), synth.uniform(64, 1002)
+    with pytest.raises(ValueError):
+        O.conv_blocked_paper(s, k, 1024, O.SYM, 127, 127)
+    _, f = O.conv_blocked_paper(s, k, 1024, O.SYM, 127, 127, allow_unsafe=True)
+    assert np.sum(f != O.int_fields(s, k, 1024, 127, 127)) > 100
+
+
+def test_plain_definition_invariants():
+    s, k = synth.gaussian(20000, 5), synth.uniform(33, 6)
+    ps = O.fixed_params(s, k, 512, O.SYM, 20, 20)
+    r = O.conv_blocked(s, k, 512, ps, out_dtype=np.float64)
+    # kernel scale equivariance: k -> a k leaves k~ unchanged and scales r by a
+    r2 = O.conv_blocked(s, 4.0 * k, 512, O.fixed_params(s, 4.0 * k, 512, O.SYM, 20, 20), out_dtype=np.float64)
+    assert np.allclose(r2, 4.0 * r, rtol=1e-15, atol=0)
+    # signal scale by a power of two leaves s~ unchanged
+    r3 = O.conv_blocked(2.0 * s, k, 512, O.fixed_params(2.0 * s, k, 512, O.SYM, 20, 20), out_dtype=np.float64)
+    assert np.array_equal(r3, 2.0 * r)
+    # a zero block yields zero output, a non-finite block yields NaN
+    z = s.copy()
+    z[: 2000] = 0.0
+    rz = O.conv_blocked(z, k, 512, O.fixed_params(z, k, 512, O.SYM, 20, 20), out_dtype=np.float64)
+    assert np.all(rz[:400] == 0.0)
+    n = s.copy()
+    n[5000] = np.nan
+    rn = O.conv_blocked(n, k, 512, O.fixed_params(n, k, 512, O.SYM, 20, 20), out_dtype=np.float64)
+    assert np.isnan(rn[5010]) and np.isfinite(rn[100])
+    # correlation = convolution with the reversed kernel, also in the quantized domain
+    f1 = O.int_fields(s, k[::-1].copy(), 512, 20, 20)
+    c = O.xcorr_direct(s[:300], k)
+    assert np.allclose(O.xcorr(s[:300], k), c, atol=1e-12)
+    assert f1.size == s.size + k.size - 1
+
+
+# ---------------------------------------------------------------- distortion model
+def test_snr_model_paper_values():
+    g = _gold("paper_values.json")["model_snr_db"]
+    sig, m = 128.0 / math.sqrt(3.0), 128.0
+    assert abs(O.snr_model_db(sig, m, sig, m, 16, 16) - g["S16_K16"]) < 0.05
+    assert abs(O.snr_model_db(sig, m, sig, m, 256, 256) - g["S256_K256"]) < 0.05
+
+
+def test_snr_model_closed_form_limits():
+    # quantization noise of one operand only: S -> infinity leaves 10 log10(12 K^2 sk^2 / km^2)
+    v = O.snr_model_db(1.0, 1.0, 0.5, 1.0, 10 ** 9, 10)
+    assert abs(v - 10 * math.log10(12 * 100 * 0.25)) < 1e-6
+    # +6.02 dB per doubling of both S and K once the cross term is negligible
+    a, b = O.snr_model_db(0.3, 1, 0.2, 1, 400, 400), O.snr_model_db(0.3, 1, 0.2, 1, 800, 800)
+    assert abs((b - a) - 20 * math.log10(2)) < 0.01
+    assert O.snr_model_db(0.0, 1.0, 1.0, 1.0, 8, 8) == math.inf
+
+
+def _uniform_case(S, L=1 << 17, N=800, Wb=2 * 1024 + 802):
+    s = synth.uniform(L, 77, -128.0, 128.0)
+    k = synth.uniform(N, 78, -128.0, 128.0)
+    r = O.conv_blocked(s, k, Wb, O.fixed_params(s, k, Wb, O.SYM, S, S), out_dtype=np.float64)
+    return O.measured_snr_db(r, O.conv_direct(s, k))
+
+
+def test_measured_snr_matches_table2():
+    """Section IV.A data (U[-128,128], N = 800): measured SNR within 0.5 dB of Table 2."""
+    g = _gold("paper_values.json")["table2_measured_snr_db"]
+    assert abs(_uniform_case(16) - g["sym_S16"]) < 0.5
+    assert abs(_uniform_case(256) - g["asym2_S256"]) < 0.5
+
+
+def test_snr_model_iid_gaussian_and_calibration():
+    s, k = synth.gaussian(1 << 16, 1001), synth.uniform(64, 1002)
+    ps = O.fixed_params(s, k, 1024, O.ASYM2, 127, 127)
+    r = O.conv_blocked(s, k, 1024, ps, out_dtype=np.float64)
+    meas = O.block_snr_db(s, k, 1024, r)
+    kmax, krms = O.kernel_stats(k)
+    model = np.array([O.snr_model_db(p.rms, p.smax, krms, kmax, 127, 127) for p in ps])
+    # iid data: eqs. (18)-(19) hold per full block (the last, zero-padded block is ragged)
+    assert abs(np.mean(meas[:-1] - model[:-1])) < 0.5
+    assert np.max(np.abs(meas[:-1] - model[:-1])) < 1.5
+    assert abs(O.calibrate(s, k, 1024)) < 1.5         # iid data: the model is already right
+    a = synth.ar1(1 << 16, 2001)
+    h = synth.hann_lowpass(1024)
+    assert O.calibrate(a, h, 4096) > 5.0               # correlated data: the model underestimates
+
+
+def test_selector_deterministic_cases():
+    N = 65
+    sym = O.snr_model_db(0.3, 1.0, 0.4, 1.0, 38, 38)
+    asym = O.snr_model_db(0.3, 1.0, 0.4, 1.0, 814, 814)
+    p = O.select_mode(1.0, 0.3, 1.0, 0.4, N, sym - 1.0)
+    assert (p.mode, p.S, p.K) == (O.SYM, 38, 38)
+    p = O.select_mode(1.0, 0.3, 1.0, 0.4, N, sym + 1.0)
+    assert (p.mode, p.S, p.K) == (O.ASYM2, 814, 814)
+    p = O.select_mode(1.0, 0.3, 1.0, 0.4, N, asym + 1.0)
+    assert p.mode == O.FULL and p.snr_pred_db == math.inf
+    p = O.select_mode(1.0, 0.3, 1.0, 0.4, N, asym + 1.0, calib_db=2.0)
+    assert p.mode == O.ASYM2
+    p = O.select_mode(0.0, 0.0, 1.0, 0.4, N, 200.0)
+    assert p.mode == O.SYM
