@@ -1,0 +1,136 @@
+/*
+ * apx -- packed approximate overlap-save convolution and cross-correlation on MI355X (gfx950).
+ *
+ * Method: Anam & Andreopoulos, "Throughput Scaling Of Convolution For Error-Tolerant
+ * Multimedia Applications" (arXiv 1201.3018).  The input is cut into overlapping blocks
+ * (Section II); each block is companded to integers with its own scale (eq. 2), packed several
+ * samples per FP64 word (symmetric packing eqs. 4-6, asymmetric packing eqs. 7-8), convolved on
+ * the packed words by a time-domain or FFT core (eq. 9), unpacked (eqs. 11-15), inverse-companded
+ * (eq. 16) and placed (eq. 17).  The packing per block can follow an SNR target (Section IV.D,
+ * eqs. 18-19).
+ *
+ * Conventions for every call below.
+ *   - Array pointers are DEVICE pointers unless the comment says "host".  The caller owns every
+ *     buffer it passes; the library keeps no caller pointer after the enqueued work completes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is enqueued on it
+ *     and the call returns without waiting, unless the comment says the call synchronizes.
+ *   - Return codes only; nothing throws across this boundary.  Shape and bound errors are found
+ *     on the host before anything is launched.  apx_last_error() gives a message for the last
+ *     failure on the calling thread.
+ *   - A context is used by one host thread at a time.
+ *   - Outputs are FP32.  Blocks whose window holds a NaN or infinity give NaN outputs and set
+ *     APX_FLAG_NONFINITE in their block report.
+ */
+#ifndef APX_H
+#define APX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    APX_OK = 0,
+    APX_E_INVALID = -1,      /* bad shape or argument */
+    APX_E_BOUND = -2,        /* explicit packed mode with R_max beyond Table 1's range */
+    APX_E_NOMEM = -3,        /* device allocation failed */
+    APX_E_DEVICE = -4,       /* a HIP call failed (also a fault surfacing from earlier work) */
+    APX_E_UNSUPPORTED = -5   /* valid request this build does not handle (e.g. size limits) */
+} apx_status;
+
+/* Packing per block (Section III.A options i-iii) */
+typedef enum {
+    APX_FULL_FP32 = 0,   /* no packing: FP32 overlap-save (option iii) */
+    APX_SYM = 1,         /* symmetric packing, eqs. (4)-(6), two samples per FP64 word */
+    APX_ASYM2 = 2,       /* asymmetric packing with M = 2, eq. (7) */
+    APX_ASYM3 = 3,       /* asymmetric packing with M = 3, eq. (7) */
+    APX_AUTO_SNR = 4,    /* per block: symmetric, else asymmetric M=2, else FP32, by the
+                            calibrated model SNR of eqs. (18)-(19) against snr_min_db */
+    APX_FULL_FP64 = 5    /* no packing, FP64 arithmetic (time-domain core only) */
+} apx_mode;
+
+typedef enum { APX_CORE_AUTO = 0, APX_CORE_TIME = 1, APX_CORE_FFT = 2 } apx_core;
+typedef enum { APX_CONV = 0, APX_XCORR = 1 } apx_op;
+
+typedef struct {
+    int32_t mode;         /* apx_mode */
+    int32_t core;         /* apx_core */
+    int32_t Sq, Kq;       /* companding ranges of eq. (2) for fixed packed modes; 0 = the
+                             largest S_q = K_q whose R_max = N S_q K_q (eq. 3) fits the mode */
+    double snr_min_db;    /* APX_AUTO_SNR: required SNR per block */
+    double calib_db;      /* APX_AUTO_SNR: offset added to the model SNR (apx_calibrate) */
+    int32_t allow_unsafe; /* 1: accept R_max beyond the bound (unpacking may then be wrong) */
+    int32_t reserved;
+} apx_params;
+
+#define APX_FLAG_NONFINITE 1
+#define APX_FLAG_ZERO 2
+
+/* Per-block report (one per overlap-save block), written by the device. */
+typedef struct {
+    int32_t mode;         /* apx_mode the block ran in */
+    int32_t flags;        /* APX_FLAG_* */
+    int32_t Sq, Kq;       /* companding ranges used (0 for full precision) */
+    int64_t rmax;         /* R_max of eq. (3) */
+    double cs;            /* block companding factor c_s of eq. (2) */
+    double smax;          /* ||s||_inf of the block window */
+    double rms;           /* root second moment of the block window */
+    double snr_pred_db;   /* calibrated model SNR (+inf for full precision) */
+} apx_block_info;
+
+typedef struct apx_ctx_s* apx_ctx;
+typedef struct apx_kernel_s* apx_kernel;
+
+/* Context on one HIP device (creates no stream).  Builds the twiddle tables.  Synchronizes. */
+apx_status apx_create(int device, apx_ctx* out);
+apx_status apx_destroy(apx_ctx ctx);
+
+/* Host only.  Overlap-save geometry of Section III: N_odd = N rounded up to odd (one zero tap
+ * appended, Section III opening), W = W_block - N_odd - 1 outputs per block (must be even and
+ * >= 2 N_odd), P = ceil(L / W) blocks.  Any output pointer may be NULL. */
+apx_status apx_geometry(int64_t L, int32_t N, int32_t W_block, int32_t* N_odd, int32_t* W, int64_t* P);
+
+/* Prepare a kernel k (device, N FP32 taps) for one operation and block size (Section IV,
+ * "Initialization"): ||k||_inf, companding of k (eq. 2) for every mode the parameters can use,
+ * symmetric packing of k (eq. 5, with eps^-1 = 2 R_max multiplying the even taps), and, for the
+ * FFT core, the kernel spectra, all kept on the device.  APX_XCORR stores the time-reversed
+ * taps: correlation c[l] = sum_n s[l+n] k[n] is the convolution with reversed k.  Copies k;
+ * the handle owns its buffers.  Enqueued on `stream`. */
+apx_status apx_kernel_create(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t W_block,
+                             const apx_params* params, void* stream, apx_kernel* out);
+apx_status apx_kernel_destroy(apx_kernel kern);
+
+/* Run the prepared operation on s_in (device, L FP32 samples, L >= N).
+ * r_out (device, L + N - 1 FP32): convolution r_out[m] = sum_n s_in[m-n] k[n] (eq. 1), or for
+ * APX_XCORR r_out[i] = c[i - (N-1)], lags -(N-1) .. L-1.
+ * info (device, nullable): one apx_block_info per block (P entries, apx_geometry). */
+apx_status apx_run(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t L, float* r_out,
+                   apx_block_info* info, void* stream);
+
+/* The integer fields r~ = s~ * k~ of Section III.B at every output position, as exact integers
+ * in FP64 (device, L + N - 1 entries), for a kernel prepared in a fixed packed mode.  Runs the
+ * same kernels as apx_run with the dequantization replaced by a store of r~. */
+apx_status apx_debug_fields(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t L, double* fields,
+                            void* stream);
+
+/* Calibration of the SNR model (Section IV.D): measures on block `block` of s_in the SNR of the
+ * companded convolution at S_q = K_q = Q against FP64, subtracts the model SNR of eqs. (18)-(19)
+ * at the same Q and stores the difference in the kernel (used by APX_AUTO_SNR when
+ * params.calib_db is NaN) and in *offset_db (host).  Synchronizes `stream`. */
+apx_status apx_calibrate(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t L, int32_t block, int32_t Q,
+                         void* stream, double* offset_db);
+
+/* One-shot convolution / correlation: kernel_create + run + kernel_destroy. Synchronizes. */
+apx_status apx_conv(apx_ctx ctx, const float* s_in, int64_t L, const float* k, int32_t N, int32_t W_block,
+                    const apx_params* params, float* r_out, apx_block_info* info, void* stream);
+apx_status apx_xcorr(apx_ctx ctx, const float* s_in, int64_t L, const float* k, int32_t N, int32_t W_block,
+                     const apx_params* params, float* r_out, apx_block_info* info, void* stream);
+
+const char* apx_status_str(apx_status st);
+const char* apx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APX_H */

@@ -1,0 +1,239 @@
+"""Python binding of libapx (ctypes).  Argument marshalling only: every step of the convolution
+runs in the HIP kernels of libapx.so.  PyTorch provides device memory and streams.
+
+The functions mirror the C ABI of include/apx.h with the same names; tensors are passed as
+device pointers.  The library must be built (paper_1201_3018_amd/build.py); importing this module
+without it raises, there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libapx.so")
+
+APX_OK, APX_E_INVALID, APX_E_BOUND, APX_E_NOMEM, APX_E_DEVICE, APX_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+APX_FULL_FP32, APX_SYM, APX_ASYM2, APX_ASYM3, APX_AUTO_SNR, APX_FULL_FP64 = 0, 1, 2, 3, 4, 5
+APX_CORE_AUTO, APX_CORE_TIME, APX_CORE_FFT = 0, 1, 2
+APX_CONV, APX_XCORR = 0, 1
+APX_FLAG_NONFINITE, APX_FLAG_ZERO = 1, 2
+
+MODE_NAMES = {APX_FULL_FP32: "full", APX_SYM: "sym", APX_ASYM2: "asym2", APX_ASYM3: "asym3",
+              APX_AUTO_SNR: "auto", APX_FULL_FP64: "full64"}
+
+# Every exported symbol of include/apx.h.
+EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "apx_kernel_destroy", "apx_run",
+           "apx_debug_fields", "apx_calibrate", "apx_conv", "apx_xcorr", "apx_status_str", "apx_last_error")
+
+
+class apx_params(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("core", ctypes.c_int32), ("Sq", ctypes.c_int32), ("Kq", ctypes.c_int32),
+                ("snr_min_db", ctypes.c_double), ("calib_db", ctypes.c_double), ("allow_unsafe", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class apx_block_info(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("flags", ctypes.c_int32), ("Sq", ctypes.c_int32), ("Kq", ctypes.c_int32),
+                ("rmax", ctypes.c_int64), ("cs", ctypes.c_double), ("smax", ctypes.c_double), ("rms", ctypes.c_double),
+                ("snr_pred_db", ctypes.c_double)]
+
+
+BLOCK_INFO_DTYPE = np.dtype([("mode", "<i4"), ("flags", "<i4"), ("Sq", "<i4"), ("Kq", "<i4"), ("rmax", "<i8"),
+                             ("cs", "<f8"), ("smax", "<f8"), ("rms", "<f8"), ("snr_pred_db", "<f8")])
+assert BLOCK_INFO_DTYPE.itemsize == ctypes.sizeof(apx_block_info)
+
+
+class ApxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"apx status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libapx.so (in-tree).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python {os.path.join(HERE, 'build.py')}`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.apx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        L.apx_destroy.argtypes = [vp]
+        L.apx_geometry.argtypes = [i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.apx_kernel_create.argtypes = [vp, vp, i32, i32, i32, ctypes.POINTER(apx_params), vp, ctypes.POINTER(vp)]
+        L.apx_kernel_destroy.argtypes = [vp]
+        L.apx_run.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.apx_debug_fields.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.apx_calibrate.argtypes = [vp, vp, vp, i64, i32, i32, vp, ctypes.POINTER(dp)]
+        L.apx_conv.argtypes = [vp, vp, i64, vp, i32, i32, ctypes.POINTER(apx_params), vp, vp, vp]
+        L.apx_xcorr.argtypes = [vp, vp, i64, vp, i32, i32, ctypes.POINTER(apx_params), vp, vp, vp]
+        L.apx_status_str.argtypes = [ctypes.c_int]
+        L.apx_status_str.restype = ctypes.c_char_p
+        L.apx_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("apx_status_str", "apx_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != APX_OK:
+        raise ApxError(st, lib().apx_last_error().decode(errors="replace"))
+
+
+def params(mode=APX_FULL_FP32, core=APX_CORE_AUTO, Sq=0, Kq=0, snr_min_db=0.0, calib_db=float("nan"),
+           allow_unsafe=False) -> apx_params:
+    return apx_params(int(mode), int(core), int(Sq), int(Kq), float(snr_min_db), float(calib_db),
+                      1 if allow_unsafe else 0, 0)
+
+
+def _dev_ptr(t, dtype_name: str):
+    import torch
+    want = {"float32": torch.float32, "float64": torch.float64, "uint8": torch.uint8}[dtype_name]
+    if not t.is_cuda or t.dtype != want or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype_name} device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------------------- C ABI mirror
+def apx_create(device: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().apx_create(device, ctypes.byref(h)))
+    return h
+
+
+def apx_destroy(ctx):
+    _check(lib().apx_destroy(ctx))
+
+
+def apx_geometry(L: int, N: int, W_block: int):
+    """(N_odd, W, P) of the overlap-save partition."""
+    no, w, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().apx_geometry(L, N, W_block, ctypes.byref(no), ctypes.byref(w), ctypes.byref(p)))
+    return no.value, w.value, p.value
+
+
+def apx_kernel_create(ctx, k, W_block: int, prm: apx_params, op: int = APX_CONV, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().apx_kernel_create(ctx, _dev_ptr(k, "float32"), k.numel(), op, W_block, ctypes.byref(prm),
+                                   _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def apx_kernel_destroy(kern):
+    _check(lib().apx_kernel_destroy(kern))
+
+
+def apx_run(ctx, kern, s, out, info=None, stream=None):
+    _check(lib().apx_run(ctx, kern, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(out, "float32"),
+                         None if info is None else _dev_ptr(info, "uint8"), _stream(stream)))
+
+
+def apx_debug_fields(ctx, kern, s, fields, stream=None):
+    _check(lib().apx_debug_fields(ctx, kern, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(fields, "float64"),
+                                  _stream(stream)))
+
+
+def apx_calibrate(ctx, kern, s, block: int = 0, Q: int = 8, stream=None) -> float:
+    off = ctypes.c_double()
+    _check(lib().apx_calibrate(ctx, kern, _dev_ptr(s, "float32"), s.numel(), block, Q, _stream(stream),
+                               ctypes.byref(off)))
+    return off.value
+
+
+def apx_conv(ctx, s, k, W_block: int, prm: apx_params, out, info=None, stream=None):
+    _check(lib().apx_conv(ctx, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(k, "float32"), k.numel(), W_block,
+                          ctypes.byref(prm), _dev_ptr(out, "float32"),
+                          None if info is None else _dev_ptr(info, "uint8"), _stream(stream)))
+
+
+def apx_xcorr(ctx, s, k, W_block: int, prm: apx_params, out, info=None, stream=None):
+    _check(lib().apx_xcorr(ctx, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(k, "float32"), k.numel(), W_block,
+                           ctypes.byref(prm), _dev_ptr(out, "float32"),
+                           None if info is None else _dev_ptr(info, "uint8"), _stream(stream)))
+
+
+# ------------------------------------------------------------------------------- conveniences
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.h = apx_create(device)
+
+    def close(self):
+        if self.h:
+            apx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Kernel:
+    """A prepared kernel (companded / packed taps and spectra resident on the device)."""
+
+    def __init__(self, ctx: Context, k, W_block: int, mode=APX_FULL_FP32, core=APX_CORE_AUTO, Sq=0, Kq=0,
+                 snr_min_db=0.0, calib_db=float("nan"), op=APX_CONV, allow_unsafe=False, stream=None):
+        self.ctx = ctx
+        self.N = int(k.numel())
+        self.W_block = W_block
+        self.op = op
+        self.prm = params(mode, core, Sq, Kq, snr_min_db, calib_db, allow_unsafe)
+        self.h = apx_kernel_create(ctx.h, k, W_block, self.prm, op, stream)
+
+    def geometry(self, L: int):
+        return apx_geometry(L, self.N, self.W_block)
+
+    def run(self, s, out=None, info: bool = False, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(s.numel() + self.N - 1, dtype=torch.float32, device=s.device)
+        inf = None
+        if info:
+            P = self.geometry(s.numel())[2]
+            inf = torch.empty(P * BLOCK_INFO_DTYPE.itemsize, dtype=torch.uint8, device=s.device)
+        apx_run(self.ctx.h, self.h, s, out, inf, stream)
+        return (out, inf) if info else out
+
+    def fields(self, s, stream=None):
+        import torch
+        f = torch.empty(s.numel() + self.N - 1, dtype=torch.float64, device=s.device)
+        apx_debug_fields(self.ctx.h, self.h, s, f, stream)
+        return f
+
+    def calibrate(self, s, block: int = 0, Q: int = 8, stream=None) -> float:
+        return apx_calibrate(self.ctx.h, self.h, s, block, Q, stream)
+
+    def close(self):
+        if self.h:
+            apx_kernel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def block_info(info_tensor) -> np.ndarray:
+    """Device block-report bytes -> numpy structured array (synchronizes)."""
+    return np.frombuffer(info_tensor.cpu().numpy().tobytes(), dtype=BLOCK_INFO_DTYPE)

@@ -1,0 +1,502 @@
+// Host engine and C ABI of libapx: validation, overlap-save geometry, per-kernel device state,
+// twiddle tables, launch planning.  Every arithmetic step of the convolution runs in the kernels
+// of kernels.hip; the host only plans and launches.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace apx;
+
+namespace {
+
+thread_local std::string g_err;
+
+apx_status fail(apx_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(APX_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int LOGF_MAX_TABLE = 14;  // twiddle tables up to F = 16384
+
+int64_t isqrt64(int64_t x) {
+    int64_t r = (int64_t)sqrt((double)x);
+    while (r * r > x) --r;
+    while ((r + 1) * (r + 1) <= x) ++r;
+    return r;
+}
+
+int64_t bound_of(int m) {
+    return m == MD_SYM ? SYM_BOUND : (m == MD_ASYM2 ? ASYM2_BOUND : ASYM3_BOUND);
+}
+
+int pad8(int n) { return (n + 7) / 8 * 8; }
+
+int ceil_log2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+}  // namespace
+
+struct apx_ctx_s {
+    int device = 0;
+    double2* twd = nullptr;
+    float2* twf = nullptr;
+    int max_lds = 65536;
+};
+
+struct apx_kernel_s {
+    apx_ctx ctx = nullptr;
+    int32_t N = 0;       // taps as given
+    int32_t N_odd = 0;
+    int32_t op = APX_CONV;
+    int32_t W_block = 0, W = 0;
+    apx_params params{};
+    int core = APX_CORE_TIME;
+    int logF = 0;
+    int32_t S[4] = {0, 0, 0, 0}, K[4] = {0, 0, 0, 0};
+    int64_t R[4] = {0, 0, 0, 0};
+    int32_t T[4] = {0, 0, 0, 0};
+    int32_t Fw[4] = {0, 0, 0, 0};
+    int32_t cand_mask = 0;
+    double calib_db = 0.0;
+    size_t td_lds = 0;
+    bool use[4] = {false, false, false, false};  // FP32, SYM, ASYM2, ASYM3 states needed
+    KState* ks = nullptr;
+    float* kf = nullptr;
+    double* kd = nullptr;
+    double* kq[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t kq_len[4] = {0, 0, 0, 0}, kq_pad[4] = {0, 0, 0, 0};
+    int32_t kf_pad = 0;
+    double2* spec[4] = {nullptr, nullptr, nullptr, nullptr};
+    float2* spec32 = nullptr;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename T>
+apx_status dalloc(apx_kernel k, T** p, size_t n) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) return fail(APX_E_NOMEM, "hipMalloc(%zu): %s", n * sizeof(T), hipGetErrorString(e));
+    k->allocs.push_back(q);
+    *p = (T*)q;
+    return APX_OK;
+}
+
+void free_kernel(apx_kernel k) {
+    for (void* p : k->allocs) (void)hipFree(p);
+    k->allocs.clear();
+}
+
+apx_status build_twiddles(apx_ctx c) {
+    const int Fmax = 1 << LOGF_MAX_TABLE;
+    std::vector<double2> hd(2 * (size_t)Fmax);
+    std::vector<float2> hf(2 * (size_t)Fmax);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int F = 2; F <= Fmax; F *= 2) {
+        for (int t = 0; t < F; ++t) {
+            // exp(-2 pi i t / F), angle reduced to the first octant by symmetry for accuracy
+            long double ang = two_pi * (long double)t / (long double)F;
+            long double cr = cosl(ang), si = -sinl(ang);
+            // exact values on the axes
+            if (4 * t == F) { cr = 0.0L; si = -1.0L; }
+            if (2 * t == F) { cr = -1.0L; si = 0.0L; }
+            if (4 * t == 3 * F) { cr = 0.0L; si = 1.0L; }
+            hd[F + t] = make_double2((double)cr, (double)si);
+            hf[F + t] = make_float2((float)cr, (float)si);
+        }
+    }
+    hd[0] = hd[1] = make_double2(1.0, 0.0);
+    hf[0] = hf[1] = make_float2(1.0f, 0.0f);
+    HIPCHK(hipMalloc((void**)&c->twd, hd.size() * sizeof(double2)));
+    HIPCHK(hipMalloc((void**)&c->twf, hf.size() * sizeof(float2)));
+    HIPCHK(hipMemcpy(c->twd, hd.data(), hd.size() * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->twf, hf.data(), hf.size() * sizeof(float2), hipMemcpyHostToDevice));
+    return APX_OK;
+}
+
+apx_status geometry(int64_t L, int32_t N, int32_t W_block, int32_t* N_odd, int32_t* W, int64_t* P) {
+    if (N < 1) return fail(APX_E_INVALID, "kernel length N = %d must be >= 1", N);
+    if (W_block < 4) return fail(APX_E_INVALID, "W_block = %d too small", W_block);
+    const int32_t no = (N % 2) ? N : N + 1;
+    const int32_t w = W_block - no - 1;
+    if (w < 2 * no || (w % 2) != 0)
+        return fail(APX_E_INVALID, "W = W_block - N - 1 = %d must be even and >= 2N = %d (N odd = %d)", w, 2 * no, no);
+    if (N_odd) *N_odd = no;
+    if (W) *W = w;
+    if (P) {
+        if (L < 1) return fail(APX_E_INVALID, "input length L = %lld must be >= 1", (long long)L);
+        *P = (L + w - 1) / w;
+    }
+    return APX_OK;
+}
+
+RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* fields, apx_block_info* info,
+                  int64_t P) {
+    RunArgs a;
+    memset(&a, 0, sizeof a);
+    a.s = s;
+    a.L = L;
+    a.out = out;
+    a.out_len = L + k->N - 1;
+    a.fields = fields;
+    a.info = info;
+    a.N = k->N_odd;
+    a.W_block = k->W_block;
+    a.W = k->W;
+    a.mode = k->params.mode;
+    a.P = P;
+    a.cand_mask = k->cand_mask;
+    for (int m = 0; m < 4; ++m) {
+        a.S[m] = k->S[m];
+        a.K[m] = k->K[m];
+        a.R[m] = k->R[m];
+        a.T[m] = k->T[m];
+        a.Fw[m] = k->Fw[m];
+        a.kq[m] = k->kq[m];
+        a.kq_len[m] = k->kq_len[m];
+        a.kq_pad[m] = k->kq_pad[m];
+        a.spec[m] = k->spec[m];
+    }
+    const double calib = isnan(k->params.calib_db) ? k->calib_db : k->params.calib_db;
+    a.calib_db = calib;
+    a.thr_lin = pow(10.0, (k->params.snr_min_db - calib) / 10.0);
+    a.ks = k->ks;
+    a.kf = k->kf;
+    a.kd = k->kd;
+    a.kf_pad = k->kf_pad;
+    a.spec32 = k->spec32;
+    a.twd = k->ctx->twd;
+    a.twf = k->ctx->twf;
+    return a;
+}
+
+apx_status run_impl(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, double* fields,
+                    apx_block_info* info, hipStream_t st) {
+    if (!ctx || !k) return fail(APX_E_INVALID, "null context or kernel");
+    if (!s || !out) return fail(APX_E_INVALID, "null input or output pointer");
+    if (L < k->N) return fail(APX_E_INVALID, "input length L = %lld shorter than the kernel N = %d", (long long)L, k->N);
+    int64_t P = 0;
+    apx_status r = geometry(L, k->N, k->W_block, nullptr, nullptr, &P);
+    if (r != APX_OK) return r;
+    if (P > (int64_t)0x7fffffff - 1) return fail(APX_E_UNSUPPORTED, "too many blocks");
+    HIPCHK(hipSetDevice(ctx->device));
+    RunArgs a = make_args(k, s, L, out, fields, info, P);
+    if (k->core == APX_CORE_FFT) {
+        HIPCHK(launch_fft(a, k->logF, st));
+    } else {
+        HIPCHK(launch_td(a, k->td_lds, st));
+    }
+    return APX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* apx_status_str(apx_status st) {
+    switch (st) {
+        case APX_OK: return "ok";
+        case APX_E_INVALID: return "invalid argument";
+        case APX_E_BOUND: return "companding range beyond the error-free packing bound";
+        case APX_E_NOMEM: return "device allocation failed";
+        case APX_E_DEVICE: return "HIP device error";
+        case APX_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* apx_last_error(void) { return g_err.c_str(); }
+
+apx_status apx_create(int device, apx_ctx* out) {
+    if (!out) return fail(APX_E_INVALID, "null output handle");
+    *out = nullptr;
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(APX_E_INVALID, "device %d not present (%d devices)", device, n);
+    HIPCHK(hipSetDevice(device));
+    apx_ctx c = new (std::nothrow) apx_ctx_s;
+    if (!c) return fail(APX_E_NOMEM, "host allocation failed");
+    c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_lds = lds;
+    apx_status r = build_twiddles(c);
+    if (r != APX_OK) {
+        apx_destroy(c);
+        return r;
+    }
+    *out = c;
+    return APX_OK;
+}
+
+apx_status apx_destroy(apx_ctx c) {
+    if (!c) return APX_OK;
+    (void)hipSetDevice(c->device);
+    if (c->twd) (void)hipFree(c->twd);
+    if (c->twf) (void)hipFree(c->twf);
+    delete c;
+    return APX_OK;
+}
+
+apx_status apx_geometry(int64_t L, int32_t N, int32_t W_block, int32_t* N_odd, int32_t* W, int64_t* P) {
+    return geometry(L, N, W_block, N_odd, W, P);
+}
+
+apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t op, int32_t W_block,
+                             const apx_params* params, void* stream, apx_kernel* out) {
+    if (!out) return fail(APX_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (!ctx || !k_in || !params) return fail(APX_E_INVALID, "null argument");
+    if (op != APX_CONV && op != APX_XCORR) return fail(APX_E_INVALID, "unknown op %d", op);
+    int32_t N_odd = 0, W = 0;
+    apx_status r = geometry(1, N, W_block, &N_odd, &W, nullptr);
+    if (r != APX_OK) return r;
+    const apx_params p = *params;
+    if (p.mode < APX_FULL_FP32 || p.mode > APX_FULL_FP64) return fail(APX_E_INVALID, "unknown mode %d", p.mode);
+    if (p.core < APX_CORE_AUTO || p.core > APX_CORE_FFT) return fail(APX_E_INVALID, "unknown core %d", p.core);
+    if (p.Sq < 0 || p.Kq < 0) return fail(APX_E_INVALID, "negative companding range");
+    if (p.mode == APX_AUTO_SNR && !isfinite(p.snr_min_db)) return fail(APX_E_INVALID, "snr_min_db must be finite");
+
+    apx_kernel k = new (std::nothrow) apx_kernel_s;
+    if (!k) return fail(APX_E_NOMEM, "host allocation failed");
+    k->ctx = ctx;
+    k->N = N;
+    k->N_odd = N_odd;
+    k->op = op;
+    k->W_block = W_block;
+    k->W = W;
+    k->params = p;
+    // companding ranges (eq. 3) per packed mode
+    for (int m = MD_SYM; m <= MD_ASYM3; ++m) {
+        const int64_t qmax = isqrt64(bound_of(m) / N_odd);
+        int64_t S = qmax, K = qmax;
+        if (p.mode == m) {
+            if (p.Sq) S = p.Sq;
+            if (p.Kq) K = p.Kq;
+        }
+        k->S[m] = (int32_t)S;
+        k->K[m] = (int32_t)K;
+        k->R[m] = (int64_t)N_odd * S * K;
+        k->T[m] = (m == MD_SYM) ? 0 : (W + (m == MD_ASYM2 ? 2 : 3) - 1) / (m == MD_ASYM2 ? 2 : 3);
+    }
+    if (p.mode >= APX_SYM && p.mode <= APX_ASYM3) {
+        const int m = p.mode;
+        if (k->S[m] < 1 || k->K[m] < 1) {
+            delete k;
+            return fail(APX_E_BOUND, "no companding range S_q = K_q >= 1 fits the bound for N = %d", N_odd);
+        }
+        if (k->R[m] > bound_of(m) && !p.allow_unsafe) {
+            int64_t Rm = k->R[m];
+            delete k;
+            return fail(APX_E_BOUND, "R_max = N S_q K_q = %lld exceeds the bound %lld (Table 1)", (long long)Rm,
+                        (long long)bound_of(m));
+        }
+        if (k->R[m] > ((int64_t)1 << 40)) {
+            delete k;
+            return fail(APX_E_UNSUPPORTED, "R_max too large");
+        }
+        k->use[m] = true;
+    } else if (p.mode == APX_AUTO_SNR) {
+        k->cand_mask = 0;
+        if (k->S[MD_SYM] >= 1) k->cand_mask |= 1 << MD_SYM;
+        if (k->S[MD_ASYM2] >= 1) k->cand_mask |= 1 << MD_ASYM2;
+        k->use[MD_SYM] = k->S[MD_SYM] >= 1;
+        k->use[MD_ASYM2] = k->S[MD_ASYM2] >= 1;
+        k->use[0] = true;
+    } else {
+        k->use[0] = true;
+    }
+    k->calib_db = 0.0;
+    // core choice
+    int core = p.core;
+    if (p.mode == APX_FULL_FP64) {
+        if (core == APX_CORE_FFT) {
+            delete k;
+            return fail(APX_E_UNSUPPORTED, "FP64 full precision runs on the time-domain core only");
+        }
+        core = APX_CORE_TIME;
+    }
+    if (core == APX_CORE_AUTO) core = (N_odd <= 129) ? APX_CORE_TIME : APX_CORE_FFT;
+    k->core = core;
+    if (core == APX_CORE_FFT) {
+        k->logF = std::max(ceil_log2(W_block), fft_min_logF());
+        if (k->logF > fft_max_logF()) {
+            delete k;
+            return fail(APX_E_UNSUPPORTED, "FFT core supports W_block <= %d", 1 << fft_max_logF());
+        }
+        const int F = 1 << k->logF;
+        k->Fw[0] = F;
+        k->Fw[MD_SYM] = F / 2;
+        k->Fw[MD_ASYM2] = F;
+        k->Fw[MD_ASYM3] = F;
+    } else {
+        k->td_lds = td_lds_bytes(p.mode, N_odd, W_block, k->T[MD_ASYM2], k->T[MD_ASYM3]);
+        if (k->td_lds > (size_t)ctx->max_lds) {
+            delete k;
+            return fail(APX_E_UNSUPPORTED, "time-domain block needs %zu bytes of LDS (> %d); use the FFT core",
+                        k->td_lds, ctx->max_lds);
+        }
+    }
+    // device state
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        delete k;
+        return fail(APX_E_DEVICE, "hipSetDevice failed");
+    }
+    k->kf_pad = pad8(N_odd);
+    const int nsym = (N_odd + 1) / 2;
+    k->kq_len[MD_SYM] = nsym;
+    k->kq_pad[MD_SYM] = pad8(nsym);
+    k->kq_len[MD_ASYM2] = k->kq_len[MD_ASYM3] = N_odd;
+    k->kq_pad[MD_ASYM2] = k->kq_pad[MD_ASYM3] = pad8(N_odd);
+    r = dalloc(k, &k->ks, 1);
+    if (r == APX_OK) r = dalloc(k, &k->kf, k->kf_pad + 8);
+    if (r == APX_OK) r = dalloc(k, &k->kd, k->kf_pad + 8);
+    if (r == APX_OK && k->use[MD_SYM]) r = dalloc(k, &k->kq[MD_SYM], k->kq_pad[MD_SYM] + 8);
+    if (r == APX_OK && k->use[MD_ASYM2]) r = dalloc(k, &k->kq[MD_ASYM2], k->kq_pad[MD_ASYM2] + 8);
+    if (r == APX_OK && k->use[MD_ASYM3]) r = dalloc(k, &k->kq[MD_ASYM3], k->kq_pad[MD_ASYM3] + 8);
+    if (r == APX_OK && core == APX_CORE_FFT) {
+        for (int m = MD_SYM; m <= MD_ASYM3 && r == APX_OK; ++m)
+            if (k->use[m]) r = dalloc(k, &k->spec[m], k->Fw[m] / 2 + 1);
+        if (r == APX_OK && k->use[0]) r = dalloc(k, &k->spec32, k->Fw[0] / 2 + 1);
+    }
+    if (r != APX_OK) {
+        free_kernel(k);
+        delete k;
+        return r;
+    }
+    hipError_t e = launch_prepare_kernel(k_in, N, N_odd, op == APX_XCORR, k->ks, k->kf, k->kd, k->kf_pad + 8,
+                                         k->kq[MD_SYM], k->kq[MD_ASYM2], k->kq[MD_ASYM3], k->K, k->R,
+                                         k->kq_pad[MD_SYM] + 8, k->kq_pad[MD_ASYM2] + 8, st);
+    if (e == hipSuccess && core == APX_CORE_FFT) {
+        for (int m = MD_SYM; m <= MD_ASYM3 && e == hipSuccess; ++m)
+            if (k->use[m]) e = launch_spectrum(k->kq[m], k->kq_len[m], k->Fw[m], ctx->twd, k->spec[m], st);
+        if (e == hipSuccess && k->use[0]) e = launch_spectrum32(k->kf, N_odd, k->Fw[0], ctx->twf, k->spec32, st);
+    }
+    if (e != hipSuccess) {
+        free_kernel(k);
+        delete k;
+        return fail(APX_E_DEVICE, "kernel preparation launch: %s", hipGetErrorString(e));
+    }
+    *out = k;
+    return APX_OK;
+}
+
+apx_status apx_kernel_destroy(apx_kernel k) {
+    if (!k) return APX_OK;
+    (void)hipSetDevice(k->ctx->device);
+    free_kernel(k);
+    delete k;
+    return APX_OK;
+}
+
+apx_status apx_run(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info,
+                   void* stream) {
+    return run_impl(ctx, k, s, L, out, nullptr, info, (hipStream_t)stream);
+}
+
+apx_status apx_debug_fields(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, double* fields, void* stream) {
+    if (!k || !fields) return fail(APX_E_INVALID, "null argument");
+    if (k->params.mode < APX_SYM || k->params.mode > APX_ASYM3)
+        return fail(APX_E_INVALID, "integer fields exist for fixed packed modes only");
+    float* tmp = nullptr;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipMalloc((void**)&tmp, (size_t)(L + k->N - 1) * sizeof(float)));
+    apx_status r = run_impl(ctx, k, s, L, tmp, fields, nullptr, (hipStream_t)stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(tmp);
+    if (r != APX_OK) return r;
+    if (e != hipSuccess) return fail(APX_E_DEVICE, "debug fields: %s", hipGetErrorString(e));
+    return APX_OK;
+}
+
+apx_status apx_calibrate(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, int32_t block, int32_t Q, void* stream,
+                         double* offset_db) {
+    if (!ctx || !k || !s) return fail(APX_E_INVALID, "null argument");
+    if (Q < 1) return fail(APX_E_INVALID, "Q must be >= 1");
+    int64_t P = 0;
+    apx_status r = geometry(L, k->N, k->W_block, nullptr, nullptr, &P);
+    if (r != APX_OK) return r;
+    if (L < k->N) return fail(APX_E_INVALID, "input shorter than the kernel");
+    if (block < 0 || block >= P) return fail(APX_E_INVALID, "block %d outside [0, %lld)", block, (long long)P);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    const int nparts = 64;
+    double* part = nullptr;
+    HIPCHK(hipMalloc((void**)&part, (2 * nparts + 2) * sizeof(double)));
+    RunArgs a = make_args(k, s, L, nullptr, nullptr, nullptr, P);
+    std::vector<double> h(2 * nparts + 2);
+    KState ks;
+    hipError_t e = launch_calib(a, block, Q, part, nparts, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ks, k->ks, sizeof ks, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(APX_E_DEVICE, "calibration: %s", hipGetErrorString(e));
+    double pr = 0.0, pe = 0.0;
+    for (int i = 0; i < nparts; ++i) {
+        pr += h[2 * i];
+        pe += h[2 * i + 1];
+    }
+    const double smax = h[2 * nparts], rms = h[2 * nparts + 1];
+    if (pe <= 0.0 || pr <= 0.0 || rms <= 0.0 || ks.krms <= 0.0)
+        return fail(APX_E_INVALID, "calibration block has no quantization error or no signal");
+    const double measured = 10.0 * log10(pr / pe);
+    const double r12 = sqrt(12.0);
+    const double svs = smax / (Q * r12), svk = ks.kmax / (Q * r12);
+    const double D = (rms * svk) * (rms * svk) + (ks.krms * svs) * (ks.krms * svs) + (svk * svs) * (svk * svs);
+    const double model = 10.0 * log10((rms * ks.krms) * (rms * ks.krms) / D);
+    k->calib_db = measured - model;
+    if (offset_db) *offset_db = k->calib_db;
+    return APX_OK;
+}
+
+static apx_status oneshot(apx_ctx ctx, int op, const float* s, int64_t L, const float* kk, int32_t N, int32_t W_block,
+                          const apx_params* params, float* out, apx_block_info* info, void* stream) {
+    apx_kernel k = nullptr;
+    apx_status r = apx_kernel_create(ctx, kk, N, op, W_block, params, stream, &k);
+    if (r != APX_OK) return r;
+    r = apx_run(ctx, k, s, L, out, info, stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    apx_kernel_destroy(k);
+    if (r != APX_OK) return r;
+    if (e != hipSuccess) return fail(APX_E_DEVICE, "%s", hipGetErrorString(e));
+    return APX_OK;
+}
+
+apx_status apx_conv(apx_ctx ctx, const float* s, int64_t L, const float* k, int32_t N, int32_t W_block,
+                    const apx_params* params, float* out, apx_block_info* info, void* stream) {
+    return oneshot(ctx, APX_CONV, s, L, k, N, W_block, params, out, info, stream);
+}
+
+apx_status apx_xcorr(apx_ctx ctx, const float* s, int64_t L, const float* k, int32_t N, int32_t W_block,
+                     const apx_params* params, float* out, apx_block_info* info, void* stream) {
+    return oneshot(ctx, APX_XCORR, s, L, k, N, W_block, params, out, info, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+// LDS-resident complex FFT for one workgroup (Stockham auto-sort, radix 8/4/2).
+//
+// Used by the FFT convolution core: a real sequence of F words is transformed as a complex
+// sequence of F/2 points (even words real, odd words imaginary), split into the real spectrum,
+// multiplied by a resident kernel spectrum, merged back and inverted.  Twiddles come from a
+// table exp(-2 pi i t / F), t < F, computed on the host in extended precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace apx {
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }  // a * i
+
+// a * (-i) for the forward transform, a * (+i) for the inverse.
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot(cx<T> a) {
+    return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+template <typename T>
+struct tw_of;
+template <>
+struct tw_of<double> {
+    using type = double2;
+};
+template <>
+struct tw_of<float> {
+    using type = float2;
+};
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+    cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>& v0, cx<T>& v1, cx<T>& v2, cx<T>& v3) {
+    cx<T> t0 = v0 + v2, t1 = v0 - v2, t2 = v1 + v3, t3 = rot<T, INV>(v1 - v3);
+    v0 = t0 + t2;
+    v2 = t0 - t2;
+    v1 = t1 + t3;
+    v3 = t1 - t3;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+    const T h = (T)0.70710678118654752440084436210484903928;
+    cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<T, INV>(e0, e1, e2, e3);
+    dft4<T, INV>(o0, o1, o2, o3);
+    // o_k *= w8^k, w8 = exp(-+ i pi / 4)
+    if (INV) {
+        o1 = {(o1.x - o1.y) * h, (o1.x + o1.y) * h};
+        o3 = {(-o3.x - o3.y) * h, (o3.x - o3.y) * h};
+    } else {
+        o1 = {(o1.x + o1.y) * h, (o1.y - o1.x) * h};
+        o3 = {(o3.y - o3.x) * h, (-o3.x - o3.y) * h};
+    }
+    o2 = rot<T, INV>(o2);
+    v[0] = e0 + o0;
+    v[4] = e0 - o0;
+    v[1] = e1 + o1;
+    v[5] = e1 - o1;
+    v[2] = e2 + o2;
+    v[6] = e2 - o2;
+    v[3] = e3 + o3;
+    v[7] = e3 - o3;
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v);
+    if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    if constexpr (R == 8) dft8<T, INV>(v);
+}
+
+// One Stockham pass of radix R over M complex points held in LDS (re[], im[]).
+// Ns = size of the sub-transforms already done.  tw = table for F = 2M.
+template <typename T, int M, int R, bool INV>
+__device__ __forceinline__ void stockham_pass(T* re, T* im, int Ns, const typename tw_of<T>::type* tw) {
+    constexpr int NB = M / R;
+    constexpr int PER = (NB + NT - 1) / NT;
+    constexpr int F = 2 * M;
+    cx<T> v[PER][R];
+    const int tstride = F / (Ns * R);
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+        const int j = threadIdx.x + b * NT;
+        if (NB % NT == 0 || j < NB) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = {re[j + r * NB], im[j + r * NB]};
+            const int k = j & (Ns - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                auto w = tw[r * k * tstride];
+                cx<T> c = {w.x, INV ? -w.y : w.y};
+                v[b][r] = cmul(v[b][r], c);
+            }
+            dftR<T, R, INV>(v[b]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+        const int j = threadIdx.x + b * NT;
+        if (NB % NT == 0 || j < NB) {
+            const int k = j & (Ns - 1);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                re[base + r * Ns] = v[b][r].x;
+                im[base + r * Ns] = v[b][r].y;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// Full complex FFT of M points in LDS.  Caller synchronizes before (data written by others);
+// the last pass ends with a barrier.  Forward: exp(-2 pi i ...); inverse: unnormalized.
+template <typename T, int M, bool INV>
+__device__ __forceinline__ void fft_lds(T* re, T* im, const typename tw_of<T>::type* tw) {
+    constexpr int L2 = ilog2(M);
+    constexpr int P8 = L2 / 3;
+    constexpr int REM = L2 % 3;
+    int Ns = 1;
+#pragma unroll
+    for (int p = 0; p < P8; ++p) {
+        stockham_pass<T, M, 8, INV>(re, im, Ns, tw);
+        Ns *= 8;
+    }
+    if constexpr (REM == 2) stockham_pass<T, M, 4, INV>(re, im, Ns, tw);
+    if constexpr (REM == 1) stockham_pass<T, M, 2, INV>(re, im, Ns, tw);
+}
+
+// Real-signal spectral step between the forward and the inverse transform.
+// In: Z = DFT_M(x_even + i x_odd).  For k in [0, M]: X2[k] = 2 X[k] (X = DFT_F(x)),
+// Y[k] = X2[k] H'[k] with H' = H / (2F) prescaled, and out V'[k] such that the unnormalized
+// inverse DFT_M of V' is y_even + i y_odd, y = x (*) h cyclic of length F = 2M.
+template <typename T, int M>
+__device__ __forceinline__ void spectral_step(T* re, T* im, const typename tw_of<T>::type* tw,
+                                              const typename tw_of<T>::type* H) {
+    for (int k = threadIdx.x; k <= M / 2; k += NT) {
+        const int kk = (M - k) & (M - 1);
+        cx<T> za = {re[k], im[k]};
+        cx<T> zb = {re[kk], im[kk]};
+        auto wt = tw[k];
+        cx<T> w = {wt.x, wt.y};
+        cx<T> A = za + conj(zb);
+        cx<T> Bd = za - conj(zb);
+        cx<T> wB = cmul(w, Bd);
+        cx<T> x_k = A - mul_i(wB);            // X2[k]
+        cx<T> x_mk = conj(A + mul_i(wB));     // X2[M-k]
+        auto h0 = H[k];
+        auto h1 = H[M - k];
+        cx<T> yk = cmul(x_k, cx<T>{h0.x, h0.y});
+        cx<T> ymk = cmul(x_mk, cx<T>{h1.x, h1.y});
+        cx<T> P = yk + conj(ymk);
+        cx<T> Q = yk - conj(ymk);
+        cx<T> cQ = mul_i(cmul(conj(w), Q));
+        cx<T> vk = P + cQ;
+        re[k] = vk.x;
+        im[k] = vk.y;
+        if (k != 0 && kk != k) {
+            cx<T> vmk = conj(P - cQ);
+            re[kk] = vmk.x;
+            im[kk] = vmk.y;
+        }
+    }
+    __syncthreads();
+}
+
+// Spectrum of a real sequence after fft_lds: H'[k] = X2[k] / (4F), k in [0, M].
+template <typename T, int M>
+__device__ __forceinline__ void real_spectrum_out(const T* re, const T* im, const typename tw_of<T>::type* tw,
+                                                  typename tw_of<T>::type* Hout) {
+    const T scale = (T)1 / (T)(8 * M);
+    for (int k = threadIdx.x; k <= M; k += NT) {
+        const int kk = (M - k) & (M - 1);
+        const int ka = k & (M - 1);
+        cx<T> za = {re[ka], im[ka]};
+        cx<T> zb = {re[kk], im[kk]};
+        cx<T> A = za + conj(zb);
+        cx<T> Bd = za - conj(zb);
+        cx<T> w;
+        if (k == M) {
+            w = {(T)-1, (T)0};
+        } else {
+            auto wt = tw[k];
+            w = {wt.x, wt.y};
+        }
+        cx<T> x = A - mul_i(cmul(w, Bd));
+        Hout[k] = {x.x * scale, x.y * scale};
+    }
+}
+
+}  // namespace apx

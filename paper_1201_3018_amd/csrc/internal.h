@@ -1,0 +1,81 @@
+// Shared between the device kernels and the host engine of libapx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "apx.h"
+
+namespace apx {
+
+constexpr int NT = 256;  // threads per workgroup for every block kernel
+
+// Table 1, "Companding range" row: largest R_max = N S_q K_q with error-free unpacking in FP64.
+constexpr int64_t SYM_BOUND = 97667;
+constexpr int64_t ASYM2_BOUND = 43165096;
+constexpr int64_t ASYM3_BOUND = 97667;
+
+// Mode indices used inside the library (same numbering as apx_mode).
+enum { MD_FULL32 = 0, MD_SYM = 1, MD_ASYM2 = 2, MD_ASYM3 = 3, MD_AUTO = 4, MD_FULL64 = 5 };
+
+// Device-resident statistics of a prepared kernel.
+struct KState {
+    double kmax;       // ||k||_inf over the N given taps
+    double krms;       // root second moment over the N given taps
+    double ck[4];      // c_k = K_q / ||k||_inf per packed mode (index = mode)
+    int32_t nonfinite; // k holds a NaN or infinity
+    int32_t pad;
+};
+
+// Everything one launch of a block kernel needs (passed by value).
+struct RunArgs {
+    const float* s;
+    int64_t L;
+    float* out;          // r_out, out_len entries
+    int64_t out_len;     // L + N - 1 with the N given by the caller
+    double* fields;      // debug: r~ at every output instead of r (nullable)
+    apx_block_info* info;
+    int32_t N;           // odd tap count (N_odd)
+    int32_t W_block;
+    int32_t W;
+    int32_t mode;        // MD_* (MD_AUTO = per-block choice)
+    int64_t P;           // blocks
+    int32_t cand_mask;   // MD_AUTO: bit m set = mode m is a candidate
+    int32_t S[4], K[4];  // companding ranges per packed mode
+    int64_t R[4];        // R_max per packed mode
+    int32_t T[4];        // asymmetric part stride per mode (W / M rounded up)
+    int32_t Fw[4];       // FFT length in words per mode (index 0 = FP32 full precision)
+    double thr_lin;      // MD_AUTO: SNR ratio that a candidate's model must reach
+    double calib_db;     // MD_AUTO: offset reported in the block info
+    const KState* ks;
+    const double* kq[4]; // [1] packed symmetric taps, [2], [3] companded taps (FP64, zero padded)
+    int32_t kq_len[4];   // taps per mode before padding
+    int32_t kq_pad[4];   // taps per mode after padding to a multiple of 8
+    const float* kf;     // FP32 taps, zero padded to kf_pad
+    const double* kd;    // FP64 taps, zero padded to kf_pad
+    int32_t kf_pad;
+    int32_t pad0;
+    const double2* spec[4];  // FFT-core kernel spectra per packed mode, Fw/2 + 1 entries
+    const float2* spec32;    // FFT-core FP32 kernel spectrum
+    const double2* twd;      // twiddle tables: exp(-2 pi i t / F), t < F, at twd + F
+    const float2* twf;
+};
+
+// Host launchers (kernels.hip).
+hipError_t launch_prepare_kernel(const float* k_in, int32_t N_given, int32_t N_odd, int32_t reverse,
+                                 KState* ks, float* kf, double* kd, int32_t kf_pad,
+                                 double* kq1, double* kq2, double* kq3, const int32_t* K, const int64_t* R,
+                                 int32_t kq1_pad, int32_t kq23_pad, hipStream_t st);
+hipError_t launch_spectrum(const double* taps, int32_t ntaps, int32_t Fw, const double2* twd,
+                           double2* spec, hipStream_t st);
+hipError_t launch_spectrum32(const float* taps, int32_t ntaps, int32_t Fw, const float2* twf,
+                             float2* spec, hipStream_t st);
+hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st);
+hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts,
+                        hipStream_t st);
+size_t td_lds_bytes(int mode, int N_odd, int W_block, int T2, int T3);
+int fft_max_logF();
+int fft_min_logF();
+
+}  // namespace apx

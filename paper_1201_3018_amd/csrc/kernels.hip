@@ -1,0 +1,778 @@
+// Device kernels of libapx (gfx950).
+//
+// Per overlap-save block (Section II) one workgroup of 256 threads:
+//   block statistics (||s||_inf, root second moment) by wave shuffles + LDS,
+//   mode / bit allocation (fixed, or the calibrated model of eqs. 18-19, Section IV.D),
+//   companding (eq. 2) fused with packing (eqs. 4, 7) into LDS,
+//   packed convolution core: register-blocked time-domain FMA loop, or LDS Stockham FFT with
+//   the resident kernel spectrum,
+//   unpacking (the digits of eq. 9 / eq. 8) fused with inverse companding (eq. 16) and the
+//   placement of eq. (17).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "fft.h"
+#include "internal.h"
+
+namespace apx {
+
+// ------------------------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T* p, int i) {
+    // read-only kernel data indexed uniformly across the wave: constant address space lets the
+    // compiler use scalar loads
+    return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+struct BlockStats {
+    double smax, sumsq;
+    int nonfinite;
+};
+
+// ||b||_inf, sum b^2 and a non-finite flag over s[start, start + n), all threads get the result.
+__device__ BlockStats block_stats(const float* __restrict__ s, int64_t start, int n) {
+    __shared__ double red_m[NT / 64], red_s[NT / 64];
+    __shared__ int red_f[NT / 64];
+    double m = 0.0, q = 0.0;
+    int nf = 0;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        float x = s[start + i];
+        if (!isfinite(x)) {
+            nf = 1;
+        } else {
+            double d = (double)x;
+            m = fmax(m, fabs(d));
+            q += d * d;
+        }
+    }
+    m = wave_max(m);
+    q = wave_sum(q);
+    nf = wave_or(nf);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red_m[wv] = m;
+        red_s[wv] = q;
+        red_f[wv] = nf;
+    }
+    __syncthreads();
+    BlockStats r;
+    r.smax = red_m[0];
+    r.sumsq = red_s[0];
+    r.nonfinite = red_f[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) {
+        r.smax = fmax(r.smax, red_m[i]);
+        r.sumsq += red_s[i];
+        r.nonfinite |= red_f[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// SNR of eqs. (18)-(19) as a ratio (the tap count cancels), uniform rounding noise
+// sigma_v = ||x||_inf / (Q sqrt 12).
+__device__ __forceinline__ double snr_ratio(double rms, double smax, double krms, double kmax, int S, int K) {
+    const double r12 = 3.4641016151377545870548926830117447;
+    double svs = smax / ((double)S * r12);
+    double svk = kmax / ((double)K * r12);
+    double a = rms * svk, b = krms * svs, c = svk * svs;
+    double D = a * a + b * b + c * c;
+    double p = rms * krms;
+    return (p * p) / D;
+}
+
+// One unit of work: a block (or the first outputs of block 0 for the FFT core).
+struct Item {
+    int64_t start;  // window start in s
+    int nwin;       // window samples present (W_block clipped at the input end)
+    int nvalid;     // samples used by the packing (window, or the prefix cut)
+    int j_lo, j_hi; // kept local outputs of the block convolution
+    int64_t o0;     // r_out index of local output j_lo
+    int64_t w;      // block index
+};
+
+__device__ __forceinline__ Item make_item(const RunArgs& a, int64_t item, bool fft) {
+    Item it;
+    const int N = a.N;
+    bool prefix = item >= a.P;
+    it.w = prefix ? 0 : item;
+    it.start = it.w == 0 ? 0 : (int64_t)a.W * it.w - 2;
+    int64_t rem = a.L - it.start;
+    it.nwin = (int)(rem < a.W_block ? rem : a.W_block);
+    it.nvalid = it.nwin;
+    if (prefix) {
+        // first N+1 outputs of block 0: only its first N+1 samples matter, the rest is zero so
+        // that the cyclic FFT result has no wrap-around there
+        it.j_lo = 0;
+        it.j_hi = N + 1;
+        it.o0 = 0;
+        if (it.nvalid > N + 1) it.nvalid = N + 1;
+    } else if (it.w == 0) {
+        it.j_lo = fft ? N + 1 : 0;
+        it.j_hi = a.W + N - 1;
+        it.o0 = it.j_lo;
+    } else {
+        it.j_lo = N + 1;
+        it.j_hi = N + 1 + a.W;
+        it.o0 = (int64_t)N - 1 + (int64_t)a.W * it.w;
+    }
+    int64_t room = a.out_len - it.o0;
+    if (room < 0) room = 0;
+    if ((int64_t)(it.j_hi - it.j_lo) > room) it.j_hi = it.j_lo + (int)room;
+    if (it.j_hi < it.j_lo) it.j_hi = it.j_lo;
+    return it;
+}
+
+struct Choice {
+    int mode;
+    int S, K;
+    int64_t R;
+    double cs;
+    double csck;      // c_s c_k; dequantization divides by it (eq. 16)
+    double snr_db;
+    int flags;
+};
+
+__device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st) {
+    Choice c;
+    const KState ks = *a.ks;
+    const double rms = sqrt(st.sumsq / (double)a.W_block);
+    c.flags = 0;
+    c.snr_db = INFINITY;
+    c.mode = a.mode;
+    if (a.mode == MD_AUTO) {
+        c.mode = MD_FULL32;
+#pragma unroll
+        for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
+            if (!((a.cand_mask >> m) & 1) || a.S[m] < 1) continue;
+            if (st.smax == 0.0 || ks.krms == 0.0) {
+                c.mode = m;
+                break;
+            }
+            double ratio = snr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
+            if (ratio >= a.thr_lin) {
+                c.mode = m;
+                c.snr_db = 10.0 * log10(ratio) + a.calib_db;
+                break;
+            }
+        }
+    }
+    if (c.mode >= MD_SYM && c.mode <= MD_ASYM3) {
+        // select without a runtime array index (that would copy the arguments to scratch)
+        const bool s1 = c.mode == MD_SYM, s2 = c.mode == MD_ASYM2;
+        c.S = s1 ? a.S[1] : (s2 ? a.S[2] : a.S[3]);
+        c.K = s1 ? a.K[1] : (s2 ? a.K[2] : a.K[3]);
+        c.R = s1 ? a.R[1] : (s2 ? a.R[2] : a.R[3]);
+        const double ck = s1 ? ks.ck[1] : (s2 ? ks.ck[2] : ks.ck[3]);
+        c.cs = st.smax == 0.0 ? 0.0 : (double)c.S / st.smax;
+        c.csck = c.cs * ck;
+        if (a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
+            c.snr_db = 10.0 * log10(snr_ratio(rms, st.smax, ks.krms, ks.kmax, c.S, c.K));
+    } else {
+        c.S = c.K = 0;
+        c.R = 0;
+        c.cs = 0.0;
+        c.csck = 0.0;
+    }
+    if (st.nonfinite || ks.nonfinite) c.flags |= APX_FLAG_NONFINITE;
+    if (st.smax == 0.0 || ks.kmax == 0.0) c.flags |= APX_FLAG_ZERO;
+    return c;
+}
+
+__device__ __forceinline__ void write_info(const RunArgs& a, const Item& it, const Choice& c, const BlockStats& st,
+                                           bool is_report) {
+    if (a.info && is_report && threadIdx.x == 0) {
+        apx_block_info b;
+        b.mode = c.mode;
+        b.flags = c.flags;
+        b.Sq = c.S;
+        b.Kq = c.K;
+        b.rmax = c.R;
+        b.cs = c.cs;
+        b.smax = st.smax;
+        b.rms = sqrt(st.sumsq / (double)a.W_block);
+        b.snr_pred_db = c.snr_db;
+        a.info[it.w] = b;
+    }
+}
+
+// Uniform outputs (all zero, or all NaN) for a block that needs no arithmetic.
+__device__ __forceinline__ void fill_block(const RunArgs& a, const Item& it, float v) {
+    for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NT) {
+        a.out[it.o0 + (j - it.j_lo)] = v;
+        if (a.fields) a.fields[it.o0 + (j - it.j_lo)] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double csck) {
+    const int64_t o = it.o0 + (j - it.j_lo);
+    if (a.fields) a.fields[o] = rt;
+    a.out[o] = (float)(rt / csck);
+}
+
+// Companded sample s~[i] of the item's window (eq. 2); zero outside [0, nvalid).
+__device__ __forceinline__ double sq_at(const RunArgs& a, const Item& it, double cs, int i) {
+    if (i < 0 || i >= it.nvalid) return 0.0;
+    return rint(cs * (double)a.s[it.start + i]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Unpacking (exact integer digits of the packed results)
+// ------------------------------------------------------------------------------------------
+// Symmetric packing: rb = 2R Dm + B + eps De with |B| <= R, |Dm|, |De| < R (eq. 9).  The side-eps
+// digit is read from the fraction, the rest split into base and side-eps^-1 digits by a
+// balanced division by 2R (ties at |B| = R resolved toward the smaller |Dm|, which is the only
+// decomposition inside the digit ranges).  Equals eqs. (11)-(15) wherever those are exact.
+struct SymDigits {
+    double Dm, B, De;
+};
+__device__ __forceinline__ SymDigits sym_split(double rb, double two_r, double R) {
+    SymDigits d;
+    double I = rint(rb);
+    d.De = rint((rb - I) * two_r);
+    double q = rint(I / two_r);
+    double B = I - q * two_r;
+    if (B > R) {
+        q += 1.0;
+        B -= two_r;
+    }
+    if (B < -R) {
+        q -= 1.0;
+        B += two_r;
+    }
+    if (B == R && q < 0.0) {
+        q += 1.0;
+        B -= two_r;
+    }
+    if (B == -R && q > 0.0) {
+        q -= 1.0;
+        B += two_r;
+    }
+    d.Dm = q;
+    d.B = B;
+    return d;
+}
+
+// Decode and store the kept outputs of a symmetric-packed block.  rbar(m) returns the packed
+// result at word m (m >= -1; word -1 is zero).
+template <typename Fn>
+__device__ __forceinline__ void sym_unpack_store(const RunArgs& a, const Item& it, const Choice& c, Fn rbar) {
+    const double two_r = (double)(2 * c.R), R = (double)c.R;
+    const int m_lo = it.j_lo >> 1, m_hi = (it.j_hi + 1) >> 1;
+    for (int m = m_lo + threadIdx.x; m < m_hi; m += NT) {
+        SymDigits cur = sym_split(rbar(m), two_r, R);
+        const int j0 = 2 * m, j1 = 2 * m + 1;
+        if (j0 >= it.j_lo && j0 < it.j_hi) {
+            double de_prev = (m >= 1) ? sym_split(rbar(m - 1), two_r, R).De : 0.0;
+            put(a, it, j0, cur.Dm + de_prev, c.csck);
+        }
+        if (j1 >= it.j_lo && j1 < it.j_hi) put(a, it, j1, cur.B, c.csck);
+    }
+}
+
+// Asymmetric packing: rb = sum_q eps^q d_q, balanced base-2R digits taken one after the other.
+template <int MM, typename Fn>
+__device__ __forceinline__ void asym_unpack_store(const RunArgs& a, const Item& it, const Choice& c, int Tit,
+                                                  int base_off, int m_first0, int m_first, int m_end, Fn rbar) {
+    const double two_r = (double)(2 * c.R);
+    for (int m = m_first0 + threadIdx.x; m < m_end; m += NT) {
+        double x = rbar(m);
+#pragma unroll
+        for (int q = 0; q < MM; ++q) {
+            double d = rint(x);
+            x = (x - d) * two_r;
+            if (q > 0 && m < m_first) continue;
+            const int j = base_off + q * Tit + m;
+            if (j >= it.j_lo && j < it.j_hi) put(a, it, j, d, c.csck);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Time-domain core
+// ------------------------------------------------------------------------------------------
+constexpr int RB = 8;    // consecutive outputs per thread
+constexpr int KUN = 8;   // taps per unrolled step (tap arrays are zero padded to a multiple)
+
+// r[m - mlo] = sum_n x[m - n] kt[n] for m in [mlo, mhi).  x: LDS, logical index i at x[i],
+// valid (zero filled) for i in [mlo - npad - 8, mhi + RB).
+template <typename T>
+__device__ __forceinline__ void td_core(const T* x, const T* kt, int npad, int mlo, int mhi, T* r) {
+    for (int m0 = mlo + RB * threadIdx.x; m0 < mhi; m0 += RB * NT) {
+        T acc[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) acc[i] = (T)0;
+        const T* xp = x + m0;
+        for (int n0 = 0; n0 < npad; n0 += KUN) {
+            T xv[RB + KUN - 1];
+#pragma unroll
+            for (int i = 0; i < RB + KUN - 1; ++i) xv[i] = xp[i - (KUN - 1) - n0];
+#pragma unroll
+            for (int t = 0; t < KUN; ++t) {
+                const T kv = ld_uniform(kt, n0 + t);
+#pragma unroll
+                for (int i = 0; i < RB; ++i) acc[i] = fma(xv[i - t + KUN - 1], kv, acc[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+            if (m0 + i < mhi) r[m0 + i - mlo] = acc[i];
+    }
+}
+
+size_t td_lds_bytes(int mode, int N, int W_block, int T2, int T3) {
+    // input words with zero margins + results
+    auto words = [&](int lw, int npad, int nres, size_t esz) {
+        return (size_t)(npad + 8 + lw + RB + 8) * esz + (size_t)(nres + RB) * esz;
+    };
+    auto pad8 = [](int n) { return (n + 7) / 8 * 8; };
+    size_t b = 0;
+    const int nsym = (N + 1) / 2;
+    if (mode == MD_SYM || mode == MD_AUTO) b = std::max(b, words(W_block / 2, pad8(nsym), W_block / 2 + 1, 8));
+    if (mode == MD_ASYM2 || mode == MD_AUTO) b = std::max(b, words(T2 + N - 1, pad8(N), T2 + N, 8));
+    if (mode == MD_ASYM3) b = std::max(b, words(T3 + N - 1, pad8(N), T3 + N, 8));
+    if (mode == MD_FULL32 || mode == MD_AUTO) b = std::max(b, words(W_block, pad8(N), W_block, 4));
+    if (mode == MD_FULL64) b = std::max(b, words(W_block, pad8(N), W_block, 8));
+    return b;
+}
+
+template <int MODE>
+__device__ void td_item(const RunArgs& a, const Item& it, const Choice& c, char* lds) {
+    const int N = a.N;
+    if constexpr (MODE == MD_FULL32 || MODE == MD_FULL64) {
+        using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+        const int npad = a.kf_pad;
+        const int lw = it.nvalid;
+        T* buf = (T*)lds;
+        const int pre = npad + 8;
+        T* x = buf + pre;
+        const int total = pre + a.W_block + RB + 8;
+        T* res = buf + total;
+        for (int i = threadIdx.x; i < total; i += NT) {
+            const int li = i - pre;
+            buf[i] = (li >= 0 && li < lw) ? (T)a.s[it.start + li] : (T)0;
+        }
+        __syncthreads();
+        const T* kt = (MODE == MD_FULL32) ? (const T*)a.kf : (const T*)a.kd;
+        td_core<T>(x, kt, npad, it.j_lo, it.j_hi, res);
+        __syncthreads();
+        for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NT) {
+            const int64_t o = it.o0 + (j - it.j_lo);
+            a.out[o] = (float)res[j - it.j_lo];
+            if (a.fields) a.fields[o] = 0.0;
+        }
+    } else if constexpr (MODE == MD_SYM) {
+        // eq. (4): s-[m] = s~[2m] + eps s~[2m+1] over the whole window
+        const double eps = 1.0 / (2.0 * (double)c.R);
+        const int nk = a.kq_len[MD_SYM], npad = a.kq_pad[MD_SYM];
+        const int lw = a.W_block / 2;
+        double* buf = (double*)lds;
+        const int pre = npad + 8;
+        double* x = buf + pre;
+        const int total = pre + lw + RB + 8;
+        double* res = buf + total;
+        for (int i = threadIdx.x; i < total; i += NT) {
+            const int m = i - pre;
+            double v = 0.0;
+            if (m >= 0 && m < lw) v = sq_at(a, it, c.cs, 2 * m) + eps * sq_at(a, it, c.cs, 2 * m + 1);
+            buf[i] = v;
+        }
+        __syncthreads();
+        // words needed: m in [j_lo/2 - 1, (j_hi+1)/2)
+        int mlo = (it.j_lo >> 1) - 1;
+        if (mlo < 0) mlo = 0;
+        const int mhi = (it.j_hi + 1) >> 1;
+        (void)nk;
+        td_core<double>(x, a.kq[MD_SYM], npad, mlo, mhi, res);
+        __syncthreads();
+        sym_unpack_store(a, it, c, [&](int m) -> double { return m < mlo ? 0.0 : res[m - mlo]; });
+    } else {
+        constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
+        // eq. (7) with part stride T; block 0 parts at q T (part 0 valid from word 0), other
+        // blocks at 2 + q T (valid from word N-1)
+        const double eps = 1.0 / (2.0 * (double)c.R);
+        const int npad = a.kq_pad[MODE];
+        const int T = a.T[MODE];
+        const int lw = T + N - 1;
+        const int base_off = (it.w == 0) ? 0 : 2;
+        double* buf = (double*)lds;
+        const int pre = npad + 8;
+        double* x = buf + pre;
+        const int total = pre + lw + RB + 8;
+        double* res = buf + total;
+        for (int i = threadIdx.x; i < total; i += NT) {
+            const int m = i - pre;
+            double v = 0.0;
+            if (m >= 0 && m < lw) {
+                double e = 1.0;
+#pragma unroll
+                for (int q = 0; q < MM; ++q) {
+                    v += e * sq_at(a, it, c.cs, base_off + q * T + m);
+                    e *= eps;
+                }
+            }
+            buf[i] = v;
+        }
+        __syncthreads();
+        const int m_first0 = (it.w == 0) ? 0 : N - 1;
+        td_core<double>(x, a.kq[MODE], npad, m_first0, lw, res);
+        __syncthreads();
+        asym_unpack_store<MM>(a, it, c, T, base_off, m_first0, N - 1, lw,
+                              [&](int m) -> double { return res[m - m_first0]; });
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_td(RunArgs a) {
+    extern __shared__ char lds_td[];
+    const Item it = make_item(a, blockIdx.x, false);
+    const BlockStats st = block_stats(a.s, it.start, it.nwin);
+    const Choice c = choose(a, st);
+    write_info(a, it, c, st, true);
+    if (c.flags & APX_FLAG_NONFINITE) {
+        fill_block(a, it, NAN);
+        return;
+    }
+    if ((c.flags & APX_FLAG_ZERO) && c.mode != MD_FULL32 && c.mode != MD_FULL64) {
+        fill_block(a, it, 0.0f);
+        return;
+    }
+    switch (c.mode) {
+        case MD_SYM: td_item<MD_SYM>(a, it, c, lds_td); break;
+        case MD_ASYM2: td_item<MD_ASYM2>(a, it, c, lds_td); break;
+        case MD_ASYM3: td_item<MD_ASYM3>(a, it, c, lds_td); break;
+        case MD_FULL64: td_item<MD_FULL64>(a, it, c, lds_td); break;
+        default: td_item<MD_FULL32>(a, it, c, lds_td); break;
+    }
+}
+
+hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st) {
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_td, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_td, dim3((unsigned)a.P), dim3(NT), lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// FFT core
+// ------------------------------------------------------------------------------------------
+// Complex points of the packed FFT for word length F: MW = F / 2.
+template <int MODE, int MW>
+__device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char* lds) {
+    using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+    using T2 = typename tw_of<T>::type;
+    constexpr int F = 2 * MW;
+    T* re = (T*)lds;
+    T* im = re + MW;
+    const int N = a.N;
+    const T2* tw;
+    const T2* H;
+    if constexpr (MODE == MD_FULL32) {
+        tw = a.twf + F;
+        H = a.spec32;
+    } else {
+        tw = a.twd + F;
+        H = a.spec[MODE];
+    }
+    // ---- pack: z[n] = x[2n] + i x[2n+1]
+    if constexpr (MODE == MD_FULL32) {
+        for (int n = threadIdx.x; n < MW; n += NT) {
+            const int i0 = 2 * n;
+            re[n] = (i0 < it.nvalid) ? a.s[it.start + i0] : 0.0f;
+            im[n] = (i0 + 1 < it.nvalid) ? a.s[it.start + i0 + 1] : 0.0f;
+        }
+    } else if constexpr (MODE == MD_SYM) {
+        const double eps = 1.0 / (2.0 * (double)c.R);
+        for (int n = threadIdx.x; n < MW; n += NT) {
+            const int i0 = 4 * n;
+            re[n] = sq_at(a, it, c.cs, i0) + eps * sq_at(a, it, c.cs, i0 + 1);
+            im[n] = sq_at(a, it, c.cs, i0 + 2) + eps * sq_at(a, it, c.cs, i0 + 3);
+        }
+    } else {
+        constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
+        const double eps = 1.0 / (2.0 * (double)c.R);
+        const bool prefix = it.j_lo == 0;
+        const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+        const int base_off = it.j_lo - (N - 1);
+        const int lw = Tit + N - 1;
+        for (int n = threadIdx.x; n < MW; n += NT) {
+            double v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int m = 2 * n + h;
+                double acc = 0.0;
+                if (m < lw) {
+                    double e = 1.0;
+#pragma unroll
+                    for (int q = 0; q < MM; ++q) {
+                        acc += e * sq_at(a, it, c.cs, base_off + q * Tit + m);
+                        e *= eps;
+                    }
+                }
+                v[h] = acc;
+            }
+            re[n] = v[0];
+            im[n] = v[1];
+        }
+    }
+    __syncthreads();
+    fft_lds<T, MW, false>(re, im, tw);
+    spectral_step<T, MW>(re, im, tw, H);
+    fft_lds<T, MW, true>(re, im, tw);
+    // ---- unpack + dequantize + place
+    auto word = [&](int m) -> double {
+        if (m < 0) return 0.0;
+        return (m & 1) ? (double)im[m >> 1] : (double)re[m >> 1];
+    };
+    if constexpr (MODE == MD_FULL32) {
+        for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NT) {
+            const int64_t o = it.o0 + (j - it.j_lo);
+            a.out[o] = (float)word(j);
+            if (a.fields) a.fields[o] = 0.0;
+        }
+    } else if constexpr (MODE == MD_SYM) {
+        sym_unpack_store(a, it, c, word);
+    } else {
+        constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
+        const bool prefix = it.j_lo == 0;
+        const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+        const int base_off = it.j_lo - (N - 1);
+        const int lw = Tit + N - 1;
+        asym_unpack_store<MM>(a, it, c, Tit, base_off, N - 1, N - 1, lw, word);
+    }
+}
+
+template <int LOGF>
+__global__ void __launch_bounds__(NT) k_fft(RunArgs a) {
+    constexpr int F = 1 << LOGF;        // words for FP32 / asymmetric modes
+    constexpr int MA = F / 2;           // complex points, FP32 / asymmetric
+    constexpr int MS = F / 4;           // complex points, symmetric (F/2 words)
+    __shared__ __attribute__((aligned(16))) char lds[MA * 2 * sizeof(double)];
+    const Item it = make_item(a, blockIdx.x, true);
+    const BlockStats st = block_stats(a.s, it.start, it.nwin);
+    const Choice c = choose(a, st);
+    write_info(a, it, c, st, blockIdx.x < a.P);
+    if (c.flags & APX_FLAG_NONFINITE) {
+        fill_block(a, it, NAN);
+        return;
+    }
+    if ((c.flags & APX_FLAG_ZERO) && c.mode != MD_FULL32) {
+        fill_block(a, it, 0.0f);
+        return;
+    }
+    if (it.j_hi <= it.j_lo) return;
+    switch (c.mode) {
+        case MD_SYM: fft_item<MD_SYM, MS>(a, it, c, lds); break;
+        case MD_ASYM2: fft_item<MD_ASYM2, MA>(a, it, c, lds); break;
+        case MD_ASYM3: fft_item<MD_ASYM3, MA>(a, it, c, lds); break;
+        default: fft_item<MD_FULL32, MA>(a, it, c, lds); break;
+    }
+}
+
+int fft_min_logF() { return 9; }
+int fft_max_logF() { return 13; }
+
+hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st) {
+    dim3 g((unsigned)(a.P + 1));
+    switch (logF) {
+        case 9: hipLaunchKernelGGL(k_fft<9>, g, dim3(NT), 0, st, a); break;
+        case 10: hipLaunchKernelGGL(k_fft<10>, g, dim3(NT), 0, st, a); break;
+        case 11: hipLaunchKernelGGL(k_fft<11>, g, dim3(NT), 0, st, a); break;
+        case 12: hipLaunchKernelGGL(k_fft<12>, g, dim3(NT), 0, st, a); break;
+        case 13: hipLaunchKernelGGL(k_fft<13>, g, dim3(NT), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Kernel preparation (Section IV "Initialization": ||k||_inf, eq. 2 on k, eq. 5)
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_prepare(const float* __restrict__ k_in, int32_t Ng, int32_t N, int32_t reverse,
+                                                KState* ks, float* kf, double* kd, int32_t kf_pad, double* kq1,
+                                                double* kq2, double* kq3, int32_t K1, int32_t K2, int32_t K3,
+                                                int64_t R1, int32_t kq1_pad, int32_t kq23_pad) {
+    __shared__ double s_kmax, s_ss;
+    __shared__ int s_nf;
+    // the taps as used: reversed for correlation, one zero appended for an even count
+    auto tap = [&](int n) -> float {
+        if (n >= Ng) return 0.0f;
+        return reverse ? k_in[Ng - 1 - n] : k_in[n];
+    };
+    BlockStats st = block_stats(k_in, 0, Ng);
+    if (threadIdx.x == 0) {
+        s_kmax = st.smax;
+        s_ss = st.sumsq;
+        s_nf = st.nonfinite;
+    }
+    __syncthreads();
+    const double kmax = s_kmax;
+    const int Kq[4] = {0, K1, K2, K3};
+    double ck[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = 1; m < 4; ++m) ck[m] = (kmax == 0.0 || Kq[m] == 0) ? 0.0 : (double)Kq[m] / kmax;
+    if (threadIdx.x == 0) {
+        ks->kmax = kmax;
+        ks->krms = sqrt(s_ss / (double)Ng);
+        for (int m = 0; m < 4; ++m) ks->ck[m] = ck[m];
+        ks->nonfinite = s_nf;
+        ks->pad = 0;
+    }
+    for (int n = threadIdx.x; n < kf_pad; n += NT) {
+        float v = (n < N) ? tap(n) : 0.0f;
+        kf[n] = v;
+        kd[n] = (double)v;
+    }
+    // companded taps (eq. 2) for the asymmetric modes, FP64 holding exact integers
+    for (int n = threadIdx.x; n < kq23_pad; n += NT) {
+        double v = (n < N) ? (double)tap(n) : 0.0;
+        if (kq2) kq2[n] = (n < N) ? rint(ck[2] * v) : 0.0;
+        if (kq3) kq3[n] = (n < N) ? rint(ck[3] * v) : 0.0;
+    }
+    // symmetric packed taps (eq. 5 for convolution): k-[n] = k~[2n+1] + 2R k~[2n]
+    if (kq1) {
+        const double two_r = (double)(2 * R1);
+        const int nk = (N + 1) / 2;
+        for (int n = threadIdx.x; n < kq1_pad; n += NT) {
+            double v = 0.0;
+            if (n < nk) {
+                double e = rint(ck[1] * (double)tap(2 * n));
+                double o = (2 * n + 1 < N) ? rint(ck[1] * (double)tap(2 * n + 1)) : 0.0;
+                v = o + two_r * e;
+            }
+            kq1[n] = v;
+        }
+    }
+}
+
+hipError_t launch_prepare_kernel(const float* k_in, int32_t Ng, int32_t N, int32_t reverse, KState* ks, float* kf,
+                                 double* kd, int32_t kf_pad, double* kq1, double* kq2, double* kq3, const int32_t* K,
+                                 const int64_t* R, int32_t kq1_pad, int32_t kq23_pad, hipStream_t st) {
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(NT), 0, st, k_in, Ng, N, reverse, ks, kf, kd, kf_pad, kq1, kq2, kq3,
+                       K[1], K[2], K[3], R[1], kq1_pad, kq23_pad);
+    return hipGetLastError();
+}
+
+// Spectrum of a real tap sequence (zero padded to F words), prescaled for spectral_step.
+template <typename T, int MW>
+__global__ void __launch_bounds__(NT) k_spectrum(const T* __restrict__ taps, int32_t ntaps,
+                                                 const typename tw_of<T>::type* tw,
+                                                 typename tw_of<T>::type* spec) {
+    __shared__ T re[MW], im[MW];
+    for (int n = threadIdx.x; n < MW; n += NT) {
+        re[n] = (2 * n < ntaps) ? taps[2 * n] : (T)0;
+        im[n] = (2 * n + 1 < ntaps) ? taps[2 * n + 1] : (T)0;
+    }
+    __syncthreads();
+    fft_lds<T, MW, false>(re, im, tw);
+    real_spectrum_out<T, MW>(re, im, tw, spec);
+}
+
+hipError_t launch_spectrum(const double* taps, int32_t ntaps, int32_t Fw, const double2* twd, double2* spec,
+                           hipStream_t st) {
+    const double2* tw = twd + Fw;
+    switch (Fw) {
+        case 256: hipLaunchKernelGGL((k_spectrum<double, 128>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 512: hipLaunchKernelGGL((k_spectrum<double, 256>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 1024: hipLaunchKernelGGL((k_spectrum<double, 512>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 2048: hipLaunchKernelGGL((k_spectrum<double, 1024>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 4096: hipLaunchKernelGGL((k_spectrum<double, 2048>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 8192: hipLaunchKernelGGL((k_spectrum<double, 4096>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum32(const float* taps, int32_t ntaps, int32_t Fw, const float2* twf, float2* spec,
+                             hipStream_t st) {
+    const float2* tw = twf + Fw;
+    switch (Fw) {
+        case 256: hipLaunchKernelGGL((k_spectrum<float, 128>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 512: hipLaunchKernelGGL((k_spectrum<float, 256>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 1024: hipLaunchKernelGGL((k_spectrum<float, 512>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 2048: hipLaunchKernelGGL((k_spectrum<float, 1024>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 4096: hipLaunchKernelGGL((k_spectrum<float, 2048>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 8192: hipLaunchKernelGGL((k_spectrum<float, 4096>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Calibration (Section IV.D): on one block, sum r_ref^2 and sum (r_q - r_ref)^2 over its kept
+// outputs, r_ref the FP64 block convolution, r_q the companded one at S_q = K_q = Q.
+// Workgroup g handles outputs g, g + G, ... and writes its two partial sums to partial[2g..].
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_calib(RunArgs a, int64_t block, int32_t Q, double* partial) {
+    const Item it = make_item(a, block, false);
+    const BlockStats st = block_stats(a.s, it.start, it.nwin);
+    const KState ks = *a.ks;
+    const double cs = st.smax == 0.0 ? 0.0 : (double)Q / st.smax;
+    const double ck = ks.kmax == 0.0 ? 0.0 : (double)Q / ks.kmax;
+    double pr = 0.0, pe = 0.0;
+    const int G = gridDim.x;
+    for (int j = it.j_lo + blockIdx.x * NT + threadIdx.x; j < it.j_hi; j += G * NT) {
+        double rr = 0.0, rq = 0.0;
+        for (int n = 0; n < a.N; ++n) {
+            const int i = j - n;
+            if (i < 0 || i >= it.nvalid) continue;
+            const double x = (double)a.s[it.start + i];
+            const double k = a.kd[n];
+            rr = fma(x, k, rr);
+            rq = fma(rint(cs * x), rint(ck * k), rq);
+        }
+        const double r = (cs == 0.0 || ck == 0.0) ? 0.0 : rq / (cs * ck);
+        pr += rr * rr;
+        pe += (r - rr) * (r - rr);
+    }
+    __shared__ double sp[NT / 64], se[NT / 64];
+    pr = wave_sum(pr);
+    pe = wave_sum(pe);
+    if ((threadIdx.x & 63) == 0) {
+        sp[threadIdx.x >> 6] = pr;
+        se[threadIdx.x >> 6] = pe;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int i = 0; i < NT / 64; ++i) {
+            a0 += sp[i];
+            a1 += se[i];
+        }
+        partial[2 * blockIdx.x] = a0;
+        partial[2 * blockIdx.x + 1] = a1;
+        if (blockIdx.x == 0) {
+            partial[2 * G] = st.smax;
+            partial[2 * G + 1] = sqrt(st.sumsq / (double)a.W_block);
+        }
+    }
+}
+
+hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts, hipStream_t st) {
+    hipLaunchKernelGGL(k_calib, dim3(nparts), dim3(NT), 0, st, a, block, Q, partial);
+    return hipGetLastError();
+}
+
+}  // namespace apx

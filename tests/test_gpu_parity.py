@@ -1,0 +1,255 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Packed modes: the integer fields r~ are compared bit for bit and the FP32 outputs are compared
+bit for bit (both sides divide the exact integer by c_s c_k in FP64 and round once to FP32).
+Full-precision FP32 paths: within an error bound derived from FP32 arithmetic (see _fp32_bound).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1201_3018_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1201_3018_amd import apx  # noqa: E402
+
+DEV = torch.device("cuda:0")
+MODES = {O.SYM: apx.APX_SYM, O.ASYM2: apx.APX_ASYM2, O.ASYM3: apx.APX_ASYM3}
+CORES = {"td": apx.APX_CORE_TIME, "fft": apx.APX_CORE_FFT}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = apx.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _run_fixed(ctx, s, k, Wb, mode, core, S=0, K=0, op=apx.APX_CONV):
+    kern = apx.Kernel(ctx, _dev(k), Wb, mode=MODES.get(mode, mode), core=CORES[core], Sq=S, Kq=K, op=op)
+    ts = _dev(s)
+    out, info = kern.run(ts, info=True)
+    fields = kern.fields(ts) if mode in MODES else None
+    torch.cuda.synchronize()
+    res = (out.cpu().numpy(), None if fields is None else fields.cpu().numpy(), apx.block_info(info))
+    kern.close()
+    return res
+
+
+def _check_packed(s, k, Wb, mode, S, got, fields, info, kernel_for_oracle=None):
+    kk = k if kernel_for_oracle is None else kernel_for_oracle
+    ps = O.fixed_params(s, kk, Wb, mode, S, S)
+    ref, ref_f, _ = O.conv_blocked(s, kk, Wb, ps, return_fields=True)
+    bad = np.nonzero(fields != ref_f)[0]
+    assert bad.size == 0, f"{bad.size} integer fields differ, first at {bad[:8]}"
+    badr = np.nonzero(got != ref)[0]
+    assert badr.size == 0, f"{badr.size} outputs differ, first at {badr[:8]}: {got[badr[:4]]} vs {ref[badr[:4]]}"
+    # block report
+    part = O.partition(len(s), len(k), Wb)
+    assert info.size == part.P
+    assert np.all(info["Sq"] == S) and np.all(info["Kq"] == S)
+    assert np.array_equal(info["cs"], np.array([p.cs for p in ps]))
+    assert np.array_equal(info["smax"], np.array([p.smax for p in ps]))
+    assert np.allclose(info["rms"], np.array([p.rms for p in ps]), rtol=1e-12, atol=0)
+
+
+def _fp32_bound(s, k, Wb, core):
+    """Per-output bound on |r_fp32 - r_fp64|.  Time domain: sequential FMA sums of N terms,
+    |err| <= 2 N u (|s| * |k|)[m] with u = 2^-24.  FFT core (length F, radix-8 Stockham):
+    |err| <= 8 log2(F) u ||x_block||_2 ||k||_2 + 2 N u (|s| * |k|)[m] as a generous normwise bound."""
+    u = 2.0 ** -24
+    N = len(k)
+    absconv = O.conv_direct(np.abs(s.astype(np.float64)), np.abs(k.astype(np.float64)))
+    b = 2.0 * N * u * absconv + 1e-30
+    if core == "fft":
+        part = O.partition(len(s), N, Wb)
+        F = 1 << max(9, int(math.ceil(math.log2(Wb))))
+        kn = float(np.linalg.norm(k.astype(np.float64)))
+        for w in range(part.P):
+            j_lo, j_hi, o = part.keep(w)
+            xn = float(np.linalg.norm(part.window(s, w).astype(np.float64)))
+            b[o: o + j_hi - j_lo] += 8.0 * math.log2(F) * u * xn * kn
+    return b
+
+
+# ------------------------------------------------------------------------- time-domain config
+C1 = dict(L=65536, N=64, Wb=1024)
+
+
+@pytest.mark.parametrize("mode,S", [(O.SYM, 38), (O.ASYM2, 127), (O.ASYM3, 38), (O.ASYM2, 814)])
+def test_c1_time_domain_packed(ctx, mode, S):
+    _say("case: C1 time domain", mode, "S=K=", S)
+    s, k = synth.gaussian(C1["L"], 1001), synth.uniform(C1["N"], 1002)
+    got, fields, info = _run_fixed(ctx, s, k, C1["Wb"], mode, "td", S, S)
+    _check_packed(s, k, C1["Wb"], mode, S, got, fields, info)
+    snr = O.measured_snr_db(got, O.conv_direct(s, k))
+    _say(f"  SNR vs FP64 = {snr:.2f} dB")
+
+
+@pytest.mark.parametrize("core", ["td", "fft"])
+def test_c1_full_precision_fp32(ctx, core):
+    _say("case: C1 full precision FP32", core)
+    s, k = synth.gaussian(C1["L"], 1001), synth.uniform(C1["N"], 1002)
+    got, _, info = _run_fixed(ctx, s, k, C1["Wb"], apx.APX_FULL_FP32, core)
+    ref = O.conv_direct(s, k)
+    err = np.abs(got.astype(np.float64) - ref)
+    assert np.all(err <= _fp32_bound(s, k, C1["Wb"], core)), float(np.max(err))
+    assert np.all(info["mode"] == apx.APX_FULL_FP32)
+
+
+def test_c1_full_precision_fp64(ctx):
+    _say("case: C1 full precision FP64 time domain")
+    s, k = synth.gaussian(C1["L"], 1001), synth.uniform(C1["N"], 1002)
+    got, _, _ = _run_fixed(ctx, s, k, C1["Wb"], apx.APX_FULL_FP64, "td")
+    ref = O.conv_direct(s, k)
+    assert np.array_equal(got, ref.astype(np.float32)) or np.max(np.abs(got - ref.astype(np.float32))) <= \
+        2.0 ** -23 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------------- FFT core, small
+@pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3])
+@pytest.mark.parametrize("L,N,Wb", [(50000, 256, 1024), (9000, 101, 512), (300, 33, 128), (4097, 129, 2048)])
+def test_fft_core_packed_small(ctx, mode, L, N, Wb):
+    _say("case: FFT core", mode, L, N, Wb)
+    s, k = synth.ar1(L, 11 + N), synth.hann_lowpass(N, 0.2)
+    S = O.max_q(mode, N if N % 2 else N + 1)
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "fft", S, S)
+    _check_packed(s, k, Wb, mode, S, got, fields, info)
+
+
+@pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3])
+@pytest.mark.parametrize("L,N,Wb", [(20000, 64, 1024), (9000, 101, 512), (1, 1, 8), (7, 7, 64), (40, 40, 256)])
+def test_td_core_packed_small(ctx, mode, L, N, Wb):
+    _say("case: TD core", mode, L, N, Wb)
+    s, k = synth.gaussian(L, 21 + N), synth.uniform(N, 22 + N)
+    S = O.max_q(mode, N if N % 2 else N + 1)
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "td", S, S)
+    _check_packed(s, k, Wb, mode, S, got, fields, info)
+
+
+@pytest.mark.parametrize("core", ["td", "fft"])
+def test_fp32_small_shapes(ctx, core):
+    for L, N, Wb in [(9000, 101, 512), (300, 33, 128), (4097, 129, 2048), (1000, 64, 1024)]:
+        _say("case: FP32", core, L, N, Wb)
+        s, k = synth.ar1(L, 5), synth.hann_lowpass(N, 0.1)
+        got, _, _ = _run_fixed(ctx, s, k, Wb, apx.APX_FULL_FP32, core)
+        ref = O.conv_direct(s, k)
+        err = np.abs(got.astype(np.float64) - ref)
+        assert np.all(err <= _fp32_bound(s, k, Wb, core)), (L, N, Wb, float(np.max(err)))
+
+
+# ------------------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("core", ["td", "fft"])
+def test_zero_and_nonfinite_blocks(ctx, core):
+    _say("case: zero / non-finite blocks", core)
+    s = synth.gaussian(10000, 3)
+    s[1000:3000] = 0.0
+    s[7000] = np.nan
+    k = synth.uniform(31, 4)
+    got, fields, info = _run_fixed(ctx, s, k, 256, O.SYM, core, 20, 20)
+    ref = O.conv_blocked(s, k, 256, O.fixed_params(s, k, 256, O.SYM, 20, 20))
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    fin = ~np.isnan(ref)
+    assert np.array_equal(got[fin], ref[fin])
+    assert np.any(info["flags"] & apx.APX_FLAG_NONFINITE)
+    assert np.any(info["flags"] & apx.APX_FLAG_ZERO)
+
+
+@pytest.mark.parametrize("core", ["td", "fft"])
+def test_xcorr_matches_reversed_conv_and_textbook(ctx, core):
+    _say("case: correlation", core)
+    s, k = synth.ar1(6000, 8), synth.gaussian(65, 9)
+    S = O.max_q(O.SYM, 65)
+    got, fields, info = _run_fixed(ctx, s, k, 512, O.SYM, core, S, S, op=apx.APX_XCORR)
+    _check_packed(s, k, 512, O.SYM, S, got, fields, info, kernel_for_oracle=k[::-1].copy())
+    # against the textbook correlation in full precision (quantization error only)
+    ref = O.xcorr(s, k)
+    assert O.measured_snr_db(got, ref) > 25.0
+    g32, _, _ = _run_fixed(ctx, s, k, 512, apx.APX_FULL_FP32, core, op=apx.APX_XCORR)
+    assert np.max(np.abs(g32 - ref)) < 1e-4 * np.max(np.abs(ref))
+    assert np.argmax(g32) == np.argmax(ref)
+
+
+def test_errors_reported(ctx):
+    k = _dev(synth.uniform(64, 1))
+    with pytest.raises(apx.ApxError) as e:
+        apx.Kernel(ctx, k, 1024, mode=apx.APX_SYM, Sq=127, Kq=127)      # 65*127^2 > 97667
+    assert e.value.status == apx.APX_E_BOUND
+    with pytest.raises(apx.ApxError) as e:
+        apx.Kernel(ctx, k, 1025, mode=apx.APX_SYM)                     # W odd
+    assert e.value.status == apx.APX_E_INVALID
+    kern = apx.Kernel(ctx, k, 1024, mode=apx.APX_SYM)
+    with pytest.raises(apx.ApxError):
+        kern.run(_dev(np.zeros(10, np.float32)))                       # L < N
+    kern.close()
+    # the bound is there for a reason: forced beyond it, unpacking goes wrong
+    s = synth.gaussian(8192, 1001)
+    kern = apx.Kernel(ctx, k, 1024, mode=apx.APX_SYM, Sq=127, Kq=127, allow_unsafe=True, core=apx.APX_CORE_TIME)
+    f = kern.fields(_dev(s)).cpu().numpy()
+    kern.close()
+    assert np.sum(f != O.int_fields(s, synth.uniform(64, 1), 1024, 127, 127)) > 100
+
+
+# ------------------------------------------------------------------------- full-size FFT config
+@pytest.fixture(scope="module")
+def c2():
+    s = synth.ar1(1 << 22, 2001)
+    k = synth.hann_lowpass(1024)
+    return s, k
+
+
+@pytest.mark.parametrize("mode,S", [(O.ASYM2, 205), (O.SYM, 9)])
+def test_c2_fft_full_size(ctx, c2, mode, S):
+    _say("case: C2 full size FFT", mode, S)
+    s, k = c2
+    got, fields, info = _run_fixed(ctx, s, k, 4096, mode, "fft", S, S)
+    _check_packed(s, k, 4096, mode, S, got, fields, info)
+
+
+def test_c2_auto_snr_selection(ctx, c2):
+    _say("case: C2 SNR-driven selection at 40 dB")
+    s, k = c2
+    ts, tk = _dev(s), _dev(k)
+    calib_o = O.calibrate(s, k, 4096)
+    kern = apx.Kernel(ctx, tk, 4096, mode=apx.APX_AUTO_SNR, core=apx.APX_CORE_FFT, snr_min_db=40.0)
+    calib_g = kern.calibrate(ts)
+    assert abs(calib_g - calib_o) < 1e-6
+    out, info = kern.run(ts, info=True)
+    torch.cuda.synchronize()
+    got, info = out.cpu().numpy(), apx.block_info(info)
+    kern.close()
+    ps = O.auto_params(s, k, 4096, 40.0, calib_g)
+    want = np.array([{O.SYM: 1, O.ASYM2: 2, O.FULL: 0}[p.mode] for p in ps])
+    near = np.array([abs(p.snr_pred_db - 40.0) < 1e-6 for p in ps])
+    assert np.array_equal(info["mode"][~near], want[~near])
+    # outputs: packed blocks bit-exact, FP32 blocks within the FP32 bound
+    for p, m in zip(ps, info["mode"]):
+        p.mode = {1: O.SYM, 2: O.ASYM2, 0: O.FULL}[int(m)]
+    ref = O.conv_blocked(s, k, 4096, ps)
+    part = O.partition(len(s), len(k), 4096)
+    snrs = []
+    ref64 = O.conv_direct(s, k)
+    for w in range(part.P):
+        j_lo, j_hi, o = part.keep(w)
+        sl = slice(o, o + j_hi - j_lo)
+        if info["mode"][w] != 0:
+            assert np.array_equal(got[sl], ref[sl]), w
+        snrs.append(O.measured_snr_db(got[sl], ref64[sl]))
+    snrs = np.array(snrs)
+    _say(f"  modes: {np.bincount(info['mode'], minlength=3)}; measured SNR min {snrs.min():.2f} mean {snrs.mean():.2f}")
+    assert np.all(snrs[info["mode"] != 0] >= 40.0 - 3.0)
