@@ -61,7 +61,8 @@ typedef struct {
     double snr_min_db;    /* APX_AUTO_SNR: required SNR per block */
     double calib_db;      /* APX_AUTO_SNR: offset added to the model SNR (apx_calibrate) */
     int32_t allow_unsafe; /* 1: accept R_max beyond the bound (unpacking may then be wrong) */
-    int32_t reserved;
+    int32_t fft_variant;  /* FFT core implementation: 0 = automatic, 1 = one 256-thread workgroup
+                             per block, 2 = one wavefront per block (supported sizes only) */
 } apx_params;
 
 #define APX_FLAG_NONFINITE 1

@@ -273,7 +273,8 @@ def conv_blocked(s, k, W_block: int, params: Sequence[BlockParams], out_dtype=np
 
     For each block w with window b (reading R4):
       packed modes: c_s = S/||b||_inf, s~ = [[c_s b]], k~ = [[c_k k]], r~ = s~ * k~ in exact
-                    int64, r = r~ / (c_s c_k) in FP64 (eq. 16), cast to out_dtype;
+                    int64, r = (c_s c_k)^-1 r~ in FP64 (eq. 16: the inverse is formed once per
+                    block and multiplies r~), cast to out_dtype;
       full:         r = b * k in FP64 (eq. 1 on the block);
     kept outputs are placed by eq. (17).  A block whose window holds a NaN or infinity gives
     NaN outputs (the companding factor is undefined there).  With return_fields, also returns the int64 r~ at
@@ -326,7 +327,7 @@ def conv_blocked(s, k, W_block: int, params: Sequence[BlockParams], out_dtype=np
             elif css[i] == 0.0 or ck == 0.0:
                 out[o: o + n] = 0.0
             else:
-                out[o: o + n] = seg.astype(np.float64) / (css[i] * ck)
+                out[o: o + n] = (1.0 / (css[i] * ck)) * seg.astype(np.float64)   # eq. (16)
             if return_fields:
                 fields[o: o + n] = seg
     for w in full_ws:
@@ -578,7 +579,7 @@ def conv_blocked_paper(s, k, W_block: int, mode: str, S: int, K: int, core: str 
         seg = local[j_lo:j_hi]
         fields[o: o + seg.size] = seg
         if cs != 0.0 and ck != 0.0:
-            out[o: o + seg.size] = seg.astype(np.float64) / (cs * ck)
+            out[o: o + seg.size] = (1.0 / (cs * ck)) * seg.astype(np.float64)     # eq. (16)
     return out.astype(np.float32), fields
 
 

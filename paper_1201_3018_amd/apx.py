@@ -34,7 +34,7 @@ EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "ap
 class apx_params(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("core", ctypes.c_int32), ("Sq", ctypes.c_int32), ("Kq", ctypes.c_int32),
                 ("snr_min_db", ctypes.c_double), ("calib_db", ctypes.c_double), ("allow_unsafe", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("fft_variant", ctypes.c_int32)]
 
 
 class apx_block_info(ctypes.Structure):
@@ -90,10 +90,13 @@ def _check(st: int):
         raise ApxError(st, lib().apx_last_error().decode(errors="replace"))
 
 
+FFT_AUTO, FFT_BLOCK, FFT_WAVE = 0, 1, 2
+
+
 def params(mode=APX_FULL_FP32, core=APX_CORE_AUTO, Sq=0, Kq=0, snr_min_db=0.0, calib_db=float("nan"),
-           allow_unsafe=False) -> apx_params:
+           allow_unsafe=False, fft_variant=FFT_AUTO) -> apx_params:
     return apx_params(int(mode), int(core), int(Sq), int(Kq), float(snr_min_db), float(calib_db),
-                      1 if allow_unsafe else 0, 0)
+                      1 if allow_unsafe else 0, int(fft_variant))
 
 
 def _dev_ptr(t, dtype_name: str):
@@ -191,12 +194,13 @@ class Kernel:
     """A prepared kernel (companded / packed taps and spectra resident on the device)."""
 
     def __init__(self, ctx: Context, k, W_block: int, mode=APX_FULL_FP32, core=APX_CORE_AUTO, Sq=0, Kq=0,
-                 snr_min_db=0.0, calib_db=float("nan"), op=APX_CONV, allow_unsafe=False, stream=None):
+                 snr_min_db=0.0, calib_db=float("nan"), op=APX_CONV, allow_unsafe=False, fft_variant=FFT_AUTO,
+                 stream=None):
         self.ctx = ctx
         self.N = int(k.numel())
         self.W_block = W_block
         self.op = op
-        self.prm = params(mode, core, Sq, Kq, snr_min_db, calib_db, allow_unsafe)
+        self.prm = params(mode, core, Sq, Kq, snr_min_db, calib_db, allow_unsafe, fft_variant)
         self.h = apx_kernel_create(ctx.h, k, W_block, self.prm, op, stream)
 
     def geometry(self, L: int):

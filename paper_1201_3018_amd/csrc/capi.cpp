@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -65,6 +66,8 @@ struct apx_ctx_s {
     double2* twd = nullptr;
     float2* twf = nullptr;
     int max_lds = 65536;
+    // W_F^t tables (t < F) of any length F, built on first use
+    std::map<int, std::pair<double2*, float2*>> tables;
 };
 
 struct apx_kernel_s {
@@ -92,6 +95,11 @@ struct apx_kernel_s {
     int32_t kf_pad = 0;
     double2* spec[4] = {nullptr, nullptr, nullptr, nullptr};
     float2* spec32 = nullptr;
+    // wave-per-block FFT core
+    bool wave = false;
+    int32_t wM[4] = {0, 0, 0, 0};  // complex points per mode (0 = FP32)
+    double2* coef[4] = {nullptr, nullptr, nullptr, nullptr};
+    float2* coef32 = nullptr;
     std::vector<void*> allocs;
 };
 
@@ -137,6 +145,53 @@ apx_status build_twiddles(apx_ctx c) {
     HIPCHK(hipMemcpy(c->twd, hd.data(), hd.size() * sizeof(double2), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->twf, hf.data(), hf.size() * sizeof(float2), hipMemcpyHostToDevice));
     return APX_OK;
+}
+
+long double two_pi_l() { return 6.283185307179586476925286766559005768L; }
+
+// exp(-2 pi i t / F), t < F, in extended precision (exact on the axes), rounded once.
+void fill_twiddles(int F, double2* d) {
+    for (int t = 0; t < F; ++t) {
+        long double cr, si;
+        if (t == 0) { cr = 1.0L; si = 0.0L; }
+        else if (4 * (int64_t)t == F) { cr = 0.0L; si = -1.0L; }
+        else if (2 * (int64_t)t == F) { cr = -1.0L; si = 0.0L; }
+        else if (4 * (int64_t)t == 3 * (int64_t)F) { cr = 0.0L; si = 1.0L; }
+        else {
+            long double ang = two_pi_l() * (long double)t / (long double)F;
+            cr = cosl(ang);
+            si = -sinl(ang);
+        }
+        d[t] = make_double2((double)cr, (double)si);
+    }
+}
+
+apx_status get_table(apx_ctx c, int F, double2** d, float2** f) {
+    auto it = c->tables.find(F);
+    if (it == c->tables.end()) {
+        std::vector<double2> hd(F);
+        std::vector<float2> hf(F);
+        fill_twiddles(F, hd.data());
+        for (int i = 0; i < F; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
+        double2* dd = nullptr;
+        float2* ff = nullptr;
+        HIPCHK(hipMalloc((void**)&dd, F * sizeof(double2)));
+        HIPCHK(hipMalloc((void**)&ff, F * sizeof(float2)));
+        HIPCHK(hipMemcpy(dd, hd.data(), F * sizeof(double2), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ff, hf.data(), F * sizeof(float2), hipMemcpyHostToDevice));
+        it = c->tables.emplace(F, std::make_pair(dd, ff)).first;
+    }
+    if (d) *d = it->second.first;
+    if (f) *f = it->second.second;
+    return APX_OK;
+}
+
+// smallest complex size the wave core handles that holds `words` real words (2M >= words)
+int wave_m_for(int words) {
+    const int ms[4] = {512, 1024, 1536, 2048};
+    for (int m : ms)
+        if (2 * m >= words) return m;
+    return 0;
 }
 
 apx_status geometry(int64_t L, int32_t N, int32_t W_block, int32_t* N_odd, int32_t* W, int64_t* P) {
@@ -192,6 +247,18 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
     a.spec32 = k->spec32;
     a.twd = k->ctx->twd;
     a.twf = k->ctx->twf;
+    if (k->wave) {
+        for (int m = 0; m < 4; ++m) {
+            if (!k->use[m]) continue;
+            double2* d = nullptr;
+            float2* f = nullptr;
+            get_table(k->ctx, k->wM[m], &d, &f);
+            if (m == 0) a.wtwf = f;
+            else a.wtw[m] = d;
+            a.coef[m] = k->coef[m];
+        }
+        a.coef32 = k->coef32;
+    }
     return a;
 }
 
@@ -206,7 +273,9 @@ apx_status run_impl(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float*
     if (P > (int64_t)0x7fffffff - 1) return fail(APX_E_UNSUPPORTED, "too many blocks");
     HIPCHK(hipSetDevice(ctx->device));
     RunArgs a = make_args(k, s, L, out, fields, info, P);
-    if (k->core == APX_CORE_FFT) {
+    if (k->core == APX_CORE_FFT && k->wave) {
+        HIPCHK(launch_fftw(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
+    } else if (k->core == APX_CORE_FFT) {
         HIPCHK(launch_fft(a, k->logF, st));
     } else {
         HIPCHK(launch_td(a, k->td_lds, st));
@@ -246,6 +315,13 @@ apx_status apx_create(int device, apx_ctx* out) {
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = lds;
     apx_status r = build_twiddles(c);
+    if (r == APX_OK) {
+        double2 w32[32], w24[24];
+        fill_twiddles(32, w32);
+        fill_twiddles(24, w24);
+        hipError_t e = upload_dft_constants(w32, w24);
+        if (e != hipSuccess) r = fail(APX_E_DEVICE, "constant upload: %s", hipGetErrorString(e));
+    }
     if (r != APX_OK) {
         apx_destroy(c);
         return r;
@@ -259,6 +335,10 @@ apx_status apx_destroy(apx_ctx c) {
     (void)hipSetDevice(c->device);
     if (c->twd) (void)hipFree(c->twd);
     if (c->twf) (void)hipFree(c->twf);
+    for (auto& kv : c->tables) {
+        (void)hipFree(kv.second.first);
+        (void)hipFree(kv.second.second);
+    }
     delete c;
     return APX_OK;
 }
@@ -354,6 +434,33 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
         k->Fw[MD_SYM] = F / 2;
         k->Fw[MD_ASYM2] = F;
         k->Fw[MD_ASYM3] = F;
+        // wave-per-block core: complex points per mode, if an instantiated size set covers them
+        int need[4] = {W_block, W_block / 2, k->T[MD_ASYM2] + N_odd - 1, k->T[MD_ASYM3] + N_odd - 1};
+        int wm[4];
+        bool ok = true;
+        for (int m = 0; m < 4; ++m) {
+            wm[m] = wave_m_for(need[m]);
+            if (k->use[m] && wm[m] == 0) ok = false;
+        }
+        if (ok && p.fft_variant != 1) {
+            // modes that are not used may take any size: look for a compiled set that matches
+            // the used modes (the launch needs a complete set)
+            const int cand[4] = {512, 1024, 1536, 2048};
+            for (int c = 0; c < 256 && !k->wave; ++c) {
+                const int t4[4] = {cand[c & 3], cand[(c >> 2) & 3], cand[(c >> 4) & 3], cand[(c >> 6) & 3]};
+                bool match = true;
+                for (int m = 0; m < 4; ++m)
+                    if (k->use[m] && t4[m] != wm[m]) match = false;
+                if (match && wave_supported(t4[1], t4[2], t4[3], t4[0])) {
+                    for (int m = 0; m < 4; ++m) k->wM[m] = t4[m];
+                    k->wave = true;
+                }
+            }
+        }
+        if (p.fft_variant == 2 && !k->wave) {
+            delete k;
+            return fail(APX_E_UNSUPPORTED, "no compiled wave-FFT size set covers W_block = %d, N = %d", W_block, N);
+        }
     } else {
         k->td_lds = td_lds_bytes(p.mode, N_odd, W_block, k->T[MD_ASYM2], k->T[MD_ASYM3]);
         if (k->td_lds > (size_t)ctx->max_lds) {
@@ -380,10 +487,20 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     if (r == APX_OK && k->use[MD_SYM]) r = dalloc(k, &k->kq[MD_SYM], k->kq_pad[MD_SYM] + 8);
     if (r == APX_OK && k->use[MD_ASYM2]) r = dalloc(k, &k->kq[MD_ASYM2], k->kq_pad[MD_ASYM2] + 8);
     if (r == APX_OK && k->use[MD_ASYM3]) r = dalloc(k, &k->kq[MD_ASYM3], k->kq_pad[MD_ASYM3] + 8);
-    if (r == APX_OK && core == APX_CORE_FFT) {
+    if (r == APX_OK && core == APX_CORE_FFT && !k->wave) {
         for (int m = MD_SYM; m <= MD_ASYM3 && r == APX_OK; ++m)
             if (k->use[m]) r = dalloc(k, &k->spec[m], k->Fw[m] / 2 + 1);
         if (r == APX_OK && k->use[0]) r = dalloc(k, &k->spec32, k->Fw[0] / 2 + 1);
+    }
+    if (r == APX_OK && core == APX_CORE_FFT && k->wave) {
+        for (int m = MD_SYM; m <= MD_ASYM3 && r == APX_OK; ++m)
+            if (k->use[m]) r = dalloc(k, &k->coef[m], 2 * (size_t)k->wM[m]);
+        if (r == APX_OK && k->use[0]) r = dalloc(k, &k->coef32, 2 * (size_t)k->wM[0]);
+        for (int m = 0; m < 4 && r == APX_OK; ++m) {
+            if (!k->use[m]) continue;
+            r = get_table(ctx, k->wM[m], nullptr, nullptr);
+            if (r == APX_OK) r = get_table(ctx, 2 * k->wM[m], nullptr, nullptr);
+        }
     }
     if (r != APX_OK) {
         free_kernel(k);
@@ -393,10 +510,23 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     hipError_t e = launch_prepare_kernel(k_in, N, N_odd, op == APX_XCORR, k->ks, k->kf, k->kd, k->kf_pad + 8,
                                          k->kq[MD_SYM], k->kq[MD_ASYM2], k->kq[MD_ASYM3], k->K, k->R,
                                          k->kq_pad[MD_SYM] + 8, k->kq_pad[MD_ASYM2] + 8, st);
-    if (e == hipSuccess && core == APX_CORE_FFT) {
+    if (e == hipSuccess && core == APX_CORE_FFT && !k->wave) {
         for (int m = MD_SYM; m <= MD_ASYM3 && e == hipSuccess; ++m)
             if (k->use[m]) e = launch_spectrum(k->kq[m], k->kq_len[m], k->Fw[m], ctx->twd, k->spec[m], st);
         if (e == hipSuccess && k->use[0]) e = launch_spectrum32(k->kf, N_odd, k->Fw[0], ctx->twf, k->spec32, st);
+    }
+    if (e == hipSuccess && core == APX_CORE_FFT && k->wave) {
+        for (int m = MD_SYM; m <= MD_ASYM3 && e == hipSuccess; ++m) {
+            if (!k->use[m]) continue;
+            double2* tF = nullptr;
+            get_table(ctx, 2 * k->wM[m], &tF, nullptr);
+            e = launch_coef(k->kq[m], k->kq_len[m], k->wM[m], tF, k->coef[m], st);
+        }
+        if (e == hipSuccess && k->use[0]) {
+            double2* tF = nullptr;
+            get_table(ctx, 2 * k->wM[0], &tF, nullptr);
+            e = launch_coef32(k->kd, N_odd, k->wM[0], tF, k->coef32, st);
+        }
     }
     if (e != hipSuccess) {
         free_kernel(k);

@@ -1,0 +1,715 @@
+// FFT convolution core, one wavefront per overlap-save block.
+//
+// Each 64-lane wave owns one block: it reads the window, takes the block statistics with
+// cross-lane reductions, chooses the packing, builds the packed words in registers, runs a
+// complex FFT of M = F/2 points (F = real FFT length in words) as three Stockham passes
+// (radix E = M/64 in registers, then radix 8, radix 8; the wave's own LDS slice carries the two
+// exchanges), applies the kernel spectrum through a precomputed real-split coefficient table,
+// runs the inverse the same way and unpacks + dequantizes straight from registers to r_out.
+// Workgroups are a single wave, so no barrier ever waits on another wave.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "fft.h"
+#include "internal.h"
+
+namespace apx {
+
+// exp(-2 pi i m / 32) and exp(-2 pi i m / 24), filled by the host (extended precision).
+__constant__ double2 c_w32d[32];
+__constant__ double2 c_w24d[24];
+__constant__ float2 c_w32f[32];
+__constant__ float2 c_w24f[24];
+
+hipError_t upload_dft_constants(const double2* w32, const double2* w24) {
+    float2 f32[32], f24[24];
+    for (int i = 0; i < 32; ++i) f32[i] = make_float2((float)w32[i].x, (float)w32[i].y);
+    for (int i = 0; i < 24; ++i) f24[i] = make_float2((float)w24[i].x, (float)w24[i].y);
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_w32d), w32, sizeof(double2) * 32);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_w24d), w24, sizeof(double2) * 24);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_w32f), f32, sizeof(float2) * 32);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_w24f), f24, sizeof(float2) * 24);
+    return e;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> cw_table(int R, int m) {
+    if constexpr (std::is_same<T, double>::value) {
+        double2 w = (32 % R == 0) ? c_w32d[m * (32 / R)] : c_w24d[m * (24 / R)];
+        return {w.x, w.y};
+    } else {
+        float2 w = (32 % R == 0) ? c_w32f[m * (32 / R)] : c_w24f[m * (24 / R)];
+        return {w.x, w.y};
+    }
+}
+
+// a * W_R^m, W_R = exp(-2 pi i / R) (forward) or its conjugate (inverse).  m, R are constants
+// after unrolling; the trivial factors cost no multiplication.
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> mulw(cx<T> a, int R, int m) {
+    m %= R;
+    if (m == 0) return a;
+    if (2 * m == R) return {-a.x, -a.y};
+    if (4 * m == R) return rot<T, INV>(a);
+    if (4 * m == 3 * R) return rot<T, !INV>(a);
+    const T h = (T)0.70710678118654752440084436210484903928;
+    if (8 * m == R) return INV ? cx<T>{(a.x - a.y) * h, (a.x + a.y) * h} : cx<T>{(a.x + a.y) * h, (a.y - a.x) * h};
+    if (8 * m == 3 * R)
+        return INV ? cx<T>{(-a.x - a.y) * h, (a.x - a.y) * h} : cx<T>{(a.y - a.x) * h, (-a.x - a.y) * h};
+    if (8 * m == 5 * R)
+        return INV ? cx<T>{(a.y - a.x) * h, (-a.x - a.y) * h} : cx<T>{(-a.x - a.y) * h, (a.x - a.y) * h};
+    if (8 * m == 7 * R)
+        return INV ? cx<T>{(a.x + a.y) * h, (a.y - a.x) * h} : cx<T>{(a.x - a.y) * h, (a.x + a.y) * h};
+    cx<T> w = cw_table<T>(R, m);
+    if (INV) w.y = -w.y;
+    return cmul(a, w);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cx<T>& a, cx<T>& b, cx<T>& c) {
+    const T s3 = (T)0.86602540378443864676372317075293618347;  // sqrt(3)/2
+    cx<T> t = b + c, d = b - c;
+    cx<T> m = {a.x - (T)0.5 * t.x, a.y - (T)0.5 * t.y};
+    cx<T> r = rot<T, INV>(d);
+    cx<T> s = {r.x * s3, r.y * s3};
+    a = a + t;
+    b = m + s;
+    c = m - s;
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftn(cx<T>* v);
+
+// Cooley-Tukey R = R1 R2 in registers: inner DFTs of size R1 over stride R2, twiddles W_R^(n2 k1),
+// outer DFTs of size R2; output in natural order.
+template <typename T, int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_ct(cx<T>* v) {
+    constexpr int R = R1 * R2;
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        cx<T> a[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) a[n1] = v[R2 * n1 + n2];
+        dftn<T, R1, INV>(a);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) v[R2 * k1 + n2] = mulw<T, INV>(a[k1], R, n2 * k1);
+    }
+    cx<T> out[R];
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        cx<T> b[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) b[n2] = v[R2 * k1 + n2];
+        dftn<T, R2, INV>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) out[k1 + R1 * k2] = b[k2];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = out[i];
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftn(cx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 3) dft3<T, INV>(v[0], v[1], v[2]);
+    else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<T, INV>(v);
+    else if constexpr (R == 16) dft_ct<T, 4, 4, INV>(v);
+    else if constexpr (R == 24) dft_ct<T, 8, 3, INV>(v);
+    else if constexpr (R == 32) dft_ct<T, 8, 4, INV>(v);
+    else static_assert(R == 2, "unsupported in-register DFT size");
+}
+
+// An opaque copy of the lane id: address arithmetic derived from it cannot be shared between
+// phases, so nothing computed for one phase stays live (in registers) through the next.
+__device__ __forceinline__ int lane_id_fresh() {
+    int l = (int)threadIdx.x;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
+// Complex FFT of M points by one wave: lane l holds v[r] = z[l + 64 r] on entry and
+// v[t] = Z[l + 64 t] on exit.  Passes: radix E (= M/64, registers only), radix 8, radix 8.
+// The two exchanges use the wave's LDS slice in a padded layout, point i at i + floor(i/E)
+// (rows of E points padded by one: the strided writes of the first pass spread over the
+// banks); every address below is that mapping in closed form.  tw: W_M^t, t < M.
+template <typename T, int M, bool INV>
+__device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw_of<T>::type* tw) {
+    constexpr int E = M / 64;
+    static_assert(E % 8 == 0, "points per lane must be a multiple of 8");
+    constexpr int NB = E / 8;  // radix-8 butterflies per lane in passes B and C
+    constexpr int S = E + 1;   // padded row
+    // pass A: radix E, no twiddles (sub-transform size 1); output i = l E + r
+    dftn<T, E, INV>(v);
+    {
+        cx<T>* p = lds + lane_id_fresh() * S;
+#pragma unroll
+        for (int r = 0; r < E; ++r) p[r] = v[r];
+    }
+    __syncthreads();
+    // pass B: radix 8 over sub-transforms of size E; input i = j + 8E r, output 8E q + k + E r
+    {
+        const int l = lane_id_fresh();
+        cx<T> u[NB][8];
+        int wofs[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = l + 64 * b;
+            const int q = j / E;
+            const int k = j - q * E;
+            const cx<T>* rp = lds + j + q;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) u[b][r] = rp[8 * r * S];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) {
+                auto w = tw[r * k * 8];  // W_{8E}^{rk} = W_M^{8rk}
+                u[b][r] = cmul(u[b][r], cx<T>{w.x, INV ? -w.y : w.y});
+            }
+            dft8<T, INV>(u[b]);
+            wofs[b] = q * 8 * S + k;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            cx<T>* wp = lds + wofs[b];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) wp[r * S] = u[b][r];
+        }
+        __syncthreads();
+    }
+    // pass C: radix 8 over sub-transforms of size M/8; results stay in registers
+    {
+        const int l = lane_id_fresh();
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = l + 64 * b;
+            const cx<T>* rp = lds + j + j / E;
+            cx<T> x[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = rp[8 * r * S];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) {
+                auto w = tw[r * j];
+                x[r] = cmul(x[r], cx<T>{w.x, INV ? -w.y : w.y});
+            }
+            dft8<T, INV>(x);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[b + NB * r] = x[r];
+        }
+    }
+    __syncthreads();
+}
+
+// Real-signal spectral step: V[k] = alpha_k Z[k] + beta_k conj(Z[M-k]) with alpha, beta built
+// from the kernel spectrum (see k_coef); the unnormalized inverse of V is the cyclic convolution
+// (even words + i odd words).  Plain layout here: point i at i, plus Z[M] := Z[0].
+template <typename T, int M>
+__device__ __forceinline__ void wave_spectral(cx<T>* v, cx<T>* lds, const typename tw_of<T>::type* coef) {
+    constexpr int E = M / 64;
+    {
+        const int l = lane_id_fresh();
+        cx<T>* p = lds + l;
+#pragma unroll
+        for (int t = 0; t < E; ++t) p[64 * t] = v[t];
+        if (l == 0) lds[M] = v[0];
+    }
+    __syncthreads();
+    {
+        const int l = lane_id_fresh();
+        const cx<T>* rb = lds + (M - l) - 64 * (E - 1);  // rb[64 (E-1-t)] = Z[M - l - 64 t]
+        const auto* cp = coef + 2 * l;
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+            const cx<T> zb = rb[64 * (E - 1 - t)];
+            const auto al = cp[128 * t];
+            const auto be = cp[128 * t + 1];
+            const cx<T> z = v[t];
+            v[t] = cmul(z, cx<T>{al.x, al.y}) + cmul(conj(zb), cx<T>{be.x, be.y});
+            if ((t & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wor(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+struct WStats {
+    double smax, sumsq;
+    int nonfinite;
+};
+
+// Items, choice, placement and digit splitting are shared with the block kernels.
+struct WItem {
+    int64_t start;
+    int nwin, nvalid, j_lo, j_hi;
+    int64_t o0, w;
+};
+
+__device__ __forceinline__ WItem wave_make_item(const RunArgs& a, int64_t item) {
+    WItem it;
+    const int N = a.N;
+    const bool prefix = item >= a.P;
+    it.w = prefix ? 0 : item;
+    it.start = it.w == 0 ? 0 : (int64_t)a.W * it.w - 2;
+    const int64_t rem = a.L - it.start;
+    it.nwin = (int)(rem < a.W_block ? rem : a.W_block);
+    it.nvalid = it.nwin;
+    if (prefix) {
+        it.j_lo = 0;
+        it.j_hi = N + 1;
+        it.o0 = 0;
+        if (it.nvalid > N + 1) it.nvalid = N + 1;
+    } else if (it.w == 0) {
+        it.j_lo = N + 1;
+        it.j_hi = a.W + N - 1;
+        it.o0 = it.j_lo;
+    } else {
+        it.j_lo = N + 1;
+        it.j_hi = N + 1 + a.W;
+        it.o0 = (int64_t)N - 1 + (int64_t)a.W * it.w;
+    }
+    int64_t room = a.out_len - it.o0;
+    if (room < 0) room = 0;
+    if ((int64_t)(it.j_hi - it.j_lo) > room) it.j_hi = it.j_lo + (int)room;
+    if (it.j_hi < it.j_lo) it.j_hi = it.j_lo;
+    return it;
+}
+
+struct WChoice {
+    int mode, S, K, flags;
+    int64_t R;
+    double cs, inv, snr_db;  // inv = (c_s c_k)^-1 of eq. (16)
+};
+
+__device__ __forceinline__ double wsnr_ratio(double rms, double smax, double krms, double kmax, int S, int K) {
+    const double r12 = 3.4641016151377545870548926830117447;
+    double svs = smax / ((double)S * r12);
+    double svk = kmax / ((double)K * r12);
+    double a = rms * svk, b = krms * svs, c = svk * svs;
+    double D = a * a + b * b + c * c;
+    double p = rms * krms;
+    return (p * p) / D;
+}
+
+__device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& st) {
+    WChoice c;
+    const KState ks = *a.ks;
+    const double rms = sqrt(st.sumsq / (double)a.W_block);
+    c.flags = 0;
+    c.snr_db = INFINITY;
+    c.mode = a.mode;
+    if (a.mode == MD_AUTO) {
+        c.mode = MD_FULL32;
+#pragma unroll
+        for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
+            if (!((a.cand_mask >> m) & 1) || a.S[m] < 1) continue;
+            if (st.smax == 0.0 || ks.krms == 0.0) {
+                c.mode = m;
+                break;
+            }
+            double ratio = wsnr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
+            if (ratio >= a.thr_lin) {
+                c.mode = m;
+                c.snr_db = 10.0 * log10(ratio) + a.calib_db;
+                break;
+            }
+        }
+    }
+    if (c.mode >= MD_SYM && c.mode <= MD_ASYM3) {
+        const bool s1 = c.mode == MD_SYM, s2 = c.mode == MD_ASYM2;
+        c.S = s1 ? a.S[1] : (s2 ? a.S[2] : a.S[3]);
+        c.K = s1 ? a.K[1] : (s2 ? a.K[2] : a.K[3]);
+        c.R = s1 ? a.R[1] : (s2 ? a.R[2] : a.R[3]);
+        const double ck = s1 ? ks.ck[1] : (s2 ? ks.ck[2] : ks.ck[3]);
+        c.cs = st.smax == 0.0 ? 0.0 : (double)c.S / st.smax;
+        c.inv = 1.0 / (c.cs * ck);
+        if (a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
+            c.snr_db = 10.0 * log10(wsnr_ratio(rms, st.smax, ks.krms, ks.kmax, c.S, c.K));
+    } else {
+        c.S = c.K = 0;
+        c.R = 0;
+        c.cs = 0.0;
+        c.inv = 0.0;
+    }
+    if (st.nonfinite || ks.nonfinite) c.flags |= APX_FLAG_NONFINITE;
+    if (st.smax == 0.0 || ks.kmax == 0.0) c.flags |= APX_FLAG_ZERO;
+    return c;
+}
+
+
+
+// exact digits of a symmetric-packed word: rb = 2R Dm + B + eps De, |B| <= R
+__device__ __forceinline__ void wsym_split(double rb, double two_r, double R, double& Dm, double& B, double& De) {
+    const double I = rint(rb);
+    De = rint((rb - I) * two_r);
+    double q = rint(I / two_r);
+    double b = I - q * two_r;
+    if (b > R) {
+        q += 1.0;
+        b -= two_r;
+    }
+    if (b < -R) {
+        q -= 1.0;
+        b += two_r;
+    }
+    if (b == R && q < 0.0) {
+        q += 1.0;
+        b -= two_r;
+    }
+    if (b == -R && q > 0.0) {
+        q -= 1.0;
+        b += two_r;
+    }
+    Dm = q;
+    B = b;
+}
+
+// Window of the item in the wave's LDS slice as FP32 (zero past nvalid), with its statistics
+// taken from the same loads: every input sample is read from memory once.
+__device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem& it, float* win) {
+    double m = 0.0, q = 0.0;
+    int nf = 0;
+    const float* p = a.s + it.start;  // start is even: 8-byte aligned
+    constexpr int CH = 16;             // float2 loads in flight per lane
+    for (int base = 0; base < a.W_block; base += 128 * CH) {
+        float2 f[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = base + 2 * threadIdx.x + 128 * c;
+            f[c] = make_float2(0.0f, 0.0f);
+            if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
+            else if (i < it.nwin) f[c].x = p[i];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = base + 2 * threadIdx.x + 128 * c;
+            if (i < a.W_block) {
+                const float x0 = f[c].x, x1 = f[c].y;
+                if (!isfinite(x0) || !isfinite(x1)) nf = 1;
+                const double d0 = isfinite(x0) ? (double)x0 : 0.0, d1 = isfinite(x1) ? (double)x1 : 0.0;
+                m = fmax(m, fmax(fabs(d0), fabs(d1)));
+                q += d0 * d0 + d1 * d1;
+                win[i] = (i < it.nvalid) ? x0 : 0.0f;
+                win[i + 1] = (i + 1 < it.nvalid) ? x1 : 0.0f;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        win[-1] = 0.0f;
+        win[a.W_block] = 0.0f;
+    }
+    WStats r;
+    r.smax = wmax(m);
+    r.sumsq = wsum(q);
+    r.nonfinite = wor(nf);
+    __syncthreads();
+    return r;
+}
+
+// Exact digits of a symmetric-packed word are split by wsym_split; asymmetric words are
+// balanced base-2R digits taken one after the other (see the block kernels).
+template <int MODE, int M, bool FIELDS>
+__device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, const WChoice& c, char* lds_raw) {
+    using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+    constexpr int E = M / 64;
+    const int N = a.N;
+    cx<T>* lds = reinterpret_cast<cx<T>*>(lds_raw);
+    const float* win = reinterpret_cast<const float*>(lds_raw) + 1;  // win[-1], win[W_block] are zero
+    const typename tw_of<T>::type* tw;
+    const typename tw_of<T>::type* coef;
+    if constexpr (MODE == MD_FULL32) {
+        tw = a.wtwf;
+        coef = a.coef32;
+    } else {
+        tw = (MODE == MD_SYM) ? a.wtw[1] : (MODE == MD_ASYM2 ? a.wtw[2] : a.wtw[3]);
+        coef = (MODE == MD_SYM) ? a.coef[1] : (MODE == MD_ASYM2 ? a.coef[2] : a.coef[3]);
+    }
+    constexpr int MM = (MODE == MD_ASYM3) ? 3 : 2;
+    const bool prefix = it.j_lo == 0;
+    int Tit = 0, base_off = 0, lw = 0;
+    if constexpr (MODE == MD_ASYM2 || MODE == MD_ASYM3) {
+        Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+        base_off = it.j_lo - (N - 1);
+        lw = Tit + N - 1;
+    }
+    const int wb = a.W_block;
+    // window sample, clamped onto the zero sentinels outside [0, W_block)
+    auto rd = [&](int i) -> float { return win[min(max(i, -1), wb)]; };
+    // companded sample s~[i] (eq. 2)
+    auto sqd = [&](int i) -> double { return rint(c.cs * (double)rd(i)); };
+    // ---- pack: v[r] = x[2n] + i x[2n+1], n = l + 64 r (eq. 4 / eq. 7)
+    cx<T> v[E];
+    {
+        const int l = lane_id_fresh();
+        const double eps = (MODE == MD_FULL32) ? 0.0 : 1.0 / (2.0 * (double)c.R);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int n = l + 64 * r;
+            if constexpr (MODE == MD_FULL32) {
+                v[r].x = rd(2 * n);
+                v[r].y = rd(2 * n + 1);
+            } else if constexpr (MODE == MD_SYM) {
+                v[r].x = sqd(4 * n) + eps * sqd(4 * n + 1);
+                v[r].y = sqd(4 * n + 2) + eps * sqd(4 * n + 3);
+            } else {
+                double w2[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int m = 2 * n + h;
+                    double acc = 0.0, e = 1.0;
+#pragma unroll
+                    for (int q = 0; q < MM; ++q) {
+                        acc += e * sqd(base_off + q * Tit + m);
+                        e *= eps;
+                    }
+                    w2[h] = (m < lw) ? acc : 0.0;
+                }
+                v[r].x = w2[0];
+                v[r].y = w2[1];
+            }
+            if (r & 1) __builtin_amdgcn_sched_barrier(0);  // bound the window reads in flight
+        }
+    }
+    __syncthreads();  // the window is dead from here on: the FFT reuses the slice
+    wave_fft<T, M, false>(v, lds, tw);
+    wave_spectral<T, M>(v, lds, coef);
+    wave_fft<T, M, true>(v, lds, tw);
+    // ---- unpack + dequantize (eq. 16) into a staging row in LDS, then a contiguous copy-out
+    float* st = reinterpret_cast<float*>(lds_raw);
+    const int l = lane_id_fresh();
+    int sbase;  // staging index of the first kept output
+    if constexpr (MODE == MD_FULL32) {
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+            const int n = l + 64 * t;
+            if (FIELDS) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int j = 2 * n + h;
+                    if (j >= it.j_lo && j < it.j_hi) a.fields[it.o0 + (j - it.j_lo)] = 0.0;
+                }
+            }
+            *reinterpret_cast<float2*>(st + 2 * n) = make_float2(v[t].x, v[t].y);
+        }
+        sbase = it.j_lo;
+    } else if constexpr (MODE == MD_SYM) {
+        const double two_r = (double)(2 * c.R), R = (double)c.R;
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+            const int n = l + 64 * t;
+            // packed result at word 2n-1 (the odd word of point n-1)
+            const double up = __shfl_up(v[t].y, 1);
+            const double wrap = (t > 0) ? __shfl(v[t > 0 ? t - 1 : 0].y, 63) : 0.0;
+            const double prev = (l == 0) ? wrap : up;
+            double Dm0, B0, De0, Dm1, B1, De1, Dmp, Bp, Dep;
+            wsym_split(v[t].x, two_r, R, Dm0, B0, De0);  // word 2n
+            wsym_split(v[t].y, two_r, R, Dm1, B1, De1);  // word 2n+1
+            wsym_split(prev, two_r, R, Dmp, Bp, Dep);    // word 2n-1
+            if (n == 0) Dep = 0.0;
+            const double f0 = Dm0 + Dep, f1 = B0, f2 = Dm1 + De0, f3 = B1;  // r~[4n .. 4n+3]
+            if (FIELDS) {
+                const double fv[4] = {f0, f1, f2, f3};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int j = 4 * n + h;
+                    if (j >= it.j_lo && j < it.j_hi) a.fields[it.o0 + (j - it.j_lo)] = fv[h];
+                }
+            }
+            *reinterpret_cast<float4*>(st + 4 * n) =
+                make_float4((float)(c.inv * f0), (float)(c.inv * f1), (float)(c.inv * f2), (float)(c.inv * f3));
+            if (t & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        sbase = it.j_lo;
+    } else {
+        const double two_r = (double)(2 * c.R);
+        // word m, digit q -> staging index q Tit + m (= local output - j_lo + N - 1)
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+            const int n = l + 64 * t;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int m = 2 * n + h;
+                double x = h ? (double)v[t].y : (double)v[t].x;
+                const bool ok = (m >= N - 1) && (m < lw);
+#pragma unroll
+                for (int q = 0; q < MM; ++q) {
+                    const double d = rint(x);
+                    x = (x - d) * two_r;
+                    if (ok) {
+                        st[q * Tit + m] = (float)(c.inv * d);
+                        if (FIELDS) {
+                            const int j = base_off + q * Tit + m;
+                            if (j >= it.j_lo && j < it.j_hi) a.fields[it.o0 + (j - it.j_lo)] = d;
+                        }
+                    }
+                }
+            }
+            if (t & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        sbase = N - 1;
+    }
+    __syncthreads();
+    const int nout = it.j_hi - it.j_lo;
+    const float* src = st + sbase;
+    float* dst = a.out + it.o0;
+#pragma unroll 4
+    for (int s = l; s < nout; s += 64) dst[s] = src[s];
+}
+
+// LDS slice of one wave: the padded FFT layout (M + M/E points) and Z[M] of the spectral step.
+// The same bytes hold the window (W_block + 2 floats) before and the output staging row after.
+template <int M>
+constexpr size_t wave_lds_bytes(size_t esz) {
+    return (size_t)(M + M / (M / 64) + 1) * 2 * esz;
+}
+
+template <int MS, int MA2, int MA3, int MF, bool FIELDS>
+__global__ void __launch_bounds__(64) k_fftw(RunArgs a) {
+    constexpr size_t B1 = wave_lds_bytes<MS>(8), B2 = wave_lds_bytes<MA2>(8), B3 = wave_lds_bytes<MA3>(8),
+                     B4 = wave_lds_bytes<MF>(4);
+    constexpr size_t B12 = B1 > B2 ? B1 : B2, B34 = B3 > B4 ? B3 : B4;
+    constexpr size_t BYTES = B12 > B34 ? B12 : B34;
+    __shared__ __attribute__((aligned(16))) char lds[BYTES];
+    // one item per workgroup (a loop here makes the compiler keep every per-lane address of the
+    // body live across iterations, which spills)
+    const int64_t item = blockIdx.x;
+    if (item >= a.P + 1) return;
+    {
+        const WItem it = wave_make_item(a, item);
+        const WStats st = wave_load_window(a, it, reinterpret_cast<float*>(lds) + 1);
+        const WChoice c = wave_choose(a, st);
+        if (a.info && item < a.P && threadIdx.x == 0) {
+            apx_block_info b;
+            b.mode = c.mode;
+            b.flags = c.flags;
+            b.Sq = c.S;
+            b.Kq = c.K;
+            b.rmax = c.R;
+            b.cs = c.cs;
+            b.smax = st.smax;
+            b.rms = sqrt(st.sumsq / (double)a.W_block);
+            b.snr_pred_db = c.snr_db;
+            a.info[it.w] = b;
+        }
+        const bool zero = (c.flags & APX_FLAG_ZERO) && c.mode != MD_FULL32;
+        if ((c.flags & APX_FLAG_NONFINITE) || zero || it.j_hi <= it.j_lo) {
+            const float v = (c.flags & APX_FLAG_NONFINITE) ? NAN : 0.0f;
+            for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += 64) {
+                a.out[it.o0 + (j - it.j_lo)] = v;
+                if (FIELDS) a.fields[it.o0 + (j - it.j_lo)] = 0.0;
+            }
+            return;
+        }
+        switch (c.mode) {
+            case MD_SYM: wave_item<MD_SYM, MS, FIELDS>(a, it, c, lds); break;
+            case MD_ASYM2: wave_item<MD_ASYM2, MA2, FIELDS>(a, it, c, lds); break;
+            case MD_ASYM3: wave_item<MD_ASYM3, MA3, FIELDS>(a, it, c, lds); break;
+            default: wave_item<MD_FULL32, MF, FIELDS>(a, it, c, lds); break;
+        }
+    }
+}
+
+// The wave-FFT size sets that are compiled (complex points per mode: sym, asym2, asym3, fp32).
+#define APX_WAVE_SETS(X)          \
+    X(1024, 1536, 1024, 2048)     \
+    X(1024, 1536, 1536, 2048)     \
+    X(1024, 2048, 1536, 2048)     \
+    X(1024, 2048, 2048, 2048)     \
+    X(512, 1024, 512, 1024)       \
+    X(512, 1024, 1024, 1024)      \
+    X(512, 512, 512, 1024)        \
+    X(512, 512, 512, 512)
+
+bool wave_supported(int ms, int ma2, int ma3, int mf) {
+#define APX_CHECK(a_, b_, c_, d_) \
+    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return true;
+    APX_WAVE_SETS(APX_CHECK)
+#undef APX_CHECK
+    return false;
+}
+
+hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st) {
+    const unsigned grid = (unsigned)(a.P + 1);
+#define APX_LAUNCH(a_, b_, c_, d_)                                                         \
+    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) {                                  \
+        if (a.fields)                                                                      \
+            hipLaunchKernelGGL((k_fftw<a_, b_, c_, d_, true>), dim3(grid), dim3(64), 0, st, a);  \
+        else                                                                               \
+            hipLaunchKernelGGL((k_fftw<a_, b_, c_, d_, false>), dim3(grid), dim3(64), 0, st, a); \
+        return hipGetLastError();                                                          \
+    }
+    APX_WAVE_SETS(APX_LAUNCH)
+#undef APX_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------------------------
+// Kernel spectrum -> real-split coefficients for a wave FFT of M points (F = 2M words).
+// H'[k] = (1/(2F)) sum_n h[n] W_F^(nk) (direct DFT, FP64); with c, s = cos, sin(2 pi k / F):
+//   alpha_k = (2 - 2s) H'[k] + (2 + 2s) conj(H'[M-k]),  beta_k = 2i c (H'[k] - conj(H'[M-k])).
+// coef[2k] = alpha_k, coef[2k+1] = beta_k.
+// ------------------------------------------------------------------------------------------
+template <typename OUT2>
+__global__ void __launch_bounds__(256) k_coef(const double* __restrict__ h, int32_t nh, int32_t M,
+                                              const double2* __restrict__ twF, OUT2* coef) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const int F = 2 * M;
+    auto dft = [&](int kk) {
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int n = 0; n < nh; ++n) {
+            const double2 w = twF[idx];
+            re = fma(h[n], w.x, re);
+            im = fma(h[n], w.y, im);
+            idx += kk;
+            if (idx >= F) idx -= F;
+        }
+        const double sc = 1.0 / (2.0 * (double)F);
+        return make_double2(re * sc, im * sc);
+    };
+    const double2 hk = dft(k);
+    const double2 hm = dft(M - k);  // k = 0 uses bin M
+    const double2 w = twF[k];
+    const double c = w.x, s = -w.y;
+    const double2 hmc = make_double2(hm.x, -hm.y);
+    const double2 al = make_double2((2.0 - 2.0 * s) * hk.x + (2.0 + 2.0 * s) * hmc.x,
+                                    (2.0 - 2.0 * s) * hk.y + (2.0 + 2.0 * s) * hmc.y);
+    const double2 d = make_double2(hk.x - hmc.x, hk.y - hmc.y);
+    const double2 be = make_double2(-2.0 * c * d.y, 2.0 * c * d.x);  // 2 i c d
+    if constexpr (std::is_same<OUT2, double2>::value) {
+        coef[2 * k] = al;
+        coef[2 * k + 1] = be;
+    } else {
+        coef[2 * k] = make_float2((float)al.x, (float)al.y);
+        coef[2 * k + 1] = make_float2((float)be.x, (float)be.y);
+    }
+}
+
+hipError_t launch_coef(const double* h, int32_t nh, int32_t M, const double2* twF, double2* coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_coef<double2>, dim3((M + 255) / 256), dim3(256), 0, st, h, nh, M, twF, coef);
+    return hipGetLastError();
+}
+hipError_t launch_coef32(const double* h, int32_t nh, int32_t M, const double2* twF, float2* coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_coef<float2>, dim3((M + 255) / 256), dim3(256), 0, st, h, nh, M, twF, coef);
+    return hipGetLastError();
+}
+
+}  // namespace apx

@@ -59,6 +59,11 @@ struct RunArgs {
     const float2* spec32;    // FFT-core FP32 kernel spectrum
     const double2* twd;      // twiddle tables: exp(-2 pi i t / F), t < F, at twd + F
     const float2* twf;
+    // wave-per-block FFT core: per mode, W_M^t (t < M) tables and real-split coefficients
+    const double2* wtw[4];
+    const float2* wtwf;
+    const double2* coef[4];
+    const float2* coef32;
 };
 
 // Host launchers (kernels.hip).
@@ -75,6 +80,12 @@ hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st);
 hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts,
                         hipStream_t st);
 size_t td_lds_bytes(int mode, int N_odd, int W_block, int T2, int T3);
+// wave-per-block FFT core (fftw.hip)
+hipError_t upload_dft_constants(const double2* w32, const double2* w24);
+bool wave_supported(int ms, int ma2, int ma3, int mf);
+hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st);
+hipError_t launch_coef(const double* h, int32_t nh, int32_t M, const double2* twF, double2* coef, hipStream_t st);
+hipError_t launch_coef32(const double* h, int32_t nh, int32_t M, const double2* twF, float2* coef, hipStream_t st);
 int fft_max_logF();
 int fft_min_logF();
 

@@ -57,14 +57,24 @@ __device__ BlockStats block_stats(const float* __restrict__ s, int64_t start, in
     __shared__ int red_f[NT / 64];
     double m = 0.0, q = 0.0;
     int nf = 0;
-    for (int i = threadIdx.x; i < n; i += NT) {
-        float x = s[start + i];
-        if (!isfinite(x)) {
-            nf = 1;
-        } else {
-            double d = (double)x;
-            m = fmax(m, fabs(d));
-            q += d * d;
+    constexpr int CH = 8;  // loads in flight per thread
+    for (int base = 0; base < n; base += NT * CH) {
+        float xs[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = base + threadIdx.x + NT * c;
+            xs[c] = (i < n) ? s[start + i] : 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const float x = xs[c];
+            if (!isfinite(x)) {
+                nf = 1;
+            } else {
+                double d = (double)x;
+                m = fmax(m, fabs(d));
+                q += d * d;
+            }
         }
     }
     m = wave_max(m);
@@ -150,7 +160,7 @@ struct Choice {
     int S, K;
     int64_t R;
     double cs;
-    double csck;      // c_s c_k; dequantization divides by it (eq. 16)
+    double inv;       // (c_s c_k)^-1 of eq. (16), formed once per block
     double snr_db;
     int flags;
 };
@@ -187,14 +197,14 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
         c.R = s1 ? a.R[1] : (s2 ? a.R[2] : a.R[3]);
         const double ck = s1 ? ks.ck[1] : (s2 ? ks.ck[2] : ks.ck[3]);
         c.cs = st.smax == 0.0 ? 0.0 : (double)c.S / st.smax;
-        c.csck = c.cs * ck;
+        c.inv = 1.0 / (c.cs * ck);
         if (a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
             c.snr_db = 10.0 * log10(snr_ratio(rms, st.smax, ks.krms, ks.kmax, c.S, c.K));
     } else {
         c.S = c.K = 0;
         c.R = 0;
         c.cs = 0.0;
-        c.csck = 0.0;
+        c.inv = 0.0;
     }
     if (st.nonfinite || ks.nonfinite) c.flags |= APX_FLAG_NONFINITE;
     if (st.smax == 0.0 || ks.kmax == 0.0) c.flags |= APX_FLAG_ZERO;
@@ -226,10 +236,10 @@ __device__ __forceinline__ void fill_block(const RunArgs& a, const Item& it, flo
     }
 }
 
-__device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double csck) {
+__device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double inv) {
     const int64_t o = it.o0 + (j - it.j_lo);
     if (a.fields) a.fields[o] = rt;
-    a.out[o] = (float)(rt / csck);
+    a.out[o] = (float)(inv * rt);  // eq. (16)
 }
 
 // Companded sample s~[i] of the item's window (eq. 2); zero outside [0, nvalid).
@@ -286,9 +296,9 @@ __device__ __forceinline__ void sym_unpack_store(const RunArgs& a, const Item& i
         const int j0 = 2 * m, j1 = 2 * m + 1;
         if (j0 >= it.j_lo && j0 < it.j_hi) {
             double de_prev = (m >= 1) ? sym_split(rbar(m - 1), two_r, R).De : 0.0;
-            put(a, it, j0, cur.Dm + de_prev, c.csck);
+            put(a, it, j0, cur.Dm + de_prev, c.inv);
         }
-        if (j1 >= it.j_lo && j1 < it.j_hi) put(a, it, j1, cur.B, c.csck);
+        if (j1 >= it.j_lo && j1 < it.j_hi) put(a, it, j1, cur.B, c.inv);
     }
 }
 
@@ -305,7 +315,7 @@ __device__ __forceinline__ void asym_unpack_store(const RunArgs& a, const Item& 
             x = (x - d) * two_r;
             if (q > 0 && m < m_first) continue;
             const int j = base_off + q * Tit + m;
-            if (j >= it.j_lo && j < it.j_hi) put(a, it, j, d, c.csck);
+            if (j >= it.j_lo && j < it.j_hi) put(a, it, j, d, c.inv);
         }
     }
 }

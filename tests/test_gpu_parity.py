@@ -1,7 +1,8 @@
 """Parity of the HIP path (through the C ABI) against the CPU oracle.
 
 Packed modes: the integer fields r~ are compared bit for bit and the FP32 outputs are compared
-bit for bit (both sides divide the exact integer by c_s c_k in FP64 and round once to FP32).
+bit for bit (both sides multiply the exact integer by (c_s c_k)^-1 in FP64, eq. 16, and round
+once to FP32).
 Full-precision FP32 paths: within an error bound derived from FP32 arithmetic (see _fp32_bound).
 """
 import math
@@ -40,8 +41,9 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _run_fixed(ctx, s, k, Wb, mode, core, S=0, K=0, op=apx.APX_CONV):
-    kern = apx.Kernel(ctx, _dev(k), Wb, mode=MODES.get(mode, mode), core=CORES[core], Sq=S, Kq=K, op=op)
+def _run_fixed(ctx, s, k, Wb, mode, core, S=0, K=0, op=apx.APX_CONV, variant=apx.FFT_AUTO):
+    kern = apx.Kernel(ctx, _dev(k), Wb, mode=MODES.get(mode, mode), core=CORES[core], Sq=S, Kq=K, op=op,
+                      fft_variant=variant)
     ts = _dev(s)
     out, info = kern.run(ts, info=True)
     fields = kern.fields(ts) if mode in MODES else None
@@ -78,7 +80,7 @@ def _fp32_bound(s, k, Wb, core):
     b = 2.0 * N * u * absconv + 1e-30
     if core == "fft":
         part = O.partition(len(s), N, Wb)
-        F = 1 << max(9, int(math.ceil(math.log2(Wb))))
+        F = max(2048, 1 << int(math.ceil(math.log2(2 * Wb))))   # largest transform either core uses
         kn = float(np.linalg.norm(k.astype(np.float64)))
         for w in range(part.P):
             j_lo, j_hi, o = part.keep(w)
@@ -122,13 +124,18 @@ def test_c1_full_precision_fp64(ctx):
 
 
 # ------------------------------------------------------------------------- FFT core, small
+VARIANTS = {"block": apx.FFT_BLOCK, "wave": apx.FFT_WAVE}
+
+
+@pytest.mark.parametrize("variant", ["block", "wave"])
 @pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3])
-@pytest.mark.parametrize("L,N,Wb", [(50000, 256, 1024), (9000, 101, 512), (300, 33, 128), (4097, 129, 2048)])
-def test_fft_core_packed_small(ctx, mode, L, N, Wb):
-    _say("case: FFT core", mode, L, N, Wb)
+@pytest.mark.parametrize("L,N,Wb", [(50000, 256, 1024), (9000, 101, 512), (300, 33, 128), (4097, 129, 2048),
+                                    (40000, 1024, 4096)])
+def test_fft_core_packed_small(ctx, mode, L, N, Wb, variant):
+    _say("case: FFT core", variant, mode, L, N, Wb)
     s, k = synth.ar1(L, 11 + N), synth.hann_lowpass(N, 0.2)
     S = O.max_q(mode, N if N % 2 else N + 1)
-    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "fft", S, S)
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "fft", S, S, variant=VARIANTS[variant])
     _check_packed(s, k, Wb, mode, S, got, fields, info)
 
 
@@ -142,26 +149,26 @@ def test_td_core_packed_small(ctx, mode, L, N, Wb):
     _check_packed(s, k, Wb, mode, S, got, fields, info)
 
 
-@pytest.mark.parametrize("core", ["td", "fft"])
-def test_fp32_small_shapes(ctx, core):
-    for L, N, Wb in [(9000, 101, 512), (300, 33, 128), (4097, 129, 2048), (1000, 64, 1024)]:
-        _say("case: FP32", core, L, N, Wb)
+@pytest.mark.parametrize("core,variant", [("td", "block"), ("fft", "block"), ("fft", "wave")])
+def test_fp32_small_shapes(ctx, core, variant):
+    for L, N, Wb in [(9000, 101, 512), (300, 33, 128), (4097, 129, 2048), (1000, 64, 1024), (40000, 1024, 4096)]:
+        _say("case: FP32", core, variant, L, N, Wb)
         s, k = synth.ar1(L, 5), synth.hann_lowpass(N, 0.1)
-        got, _, _ = _run_fixed(ctx, s, k, Wb, apx.APX_FULL_FP32, core)
+        got, _, _ = _run_fixed(ctx, s, k, Wb, apx.APX_FULL_FP32, core, variant=VARIANTS[variant])
         ref = O.conv_direct(s, k)
         err = np.abs(got.astype(np.float64) - ref)
         assert np.all(err <= _fp32_bound(s, k, Wb, core)), (L, N, Wb, float(np.max(err)))
 
 
 # ------------------------------------------------------------------------- edge cases
-@pytest.mark.parametrize("core", ["td", "fft"])
-def test_zero_and_nonfinite_blocks(ctx, core):
-    _say("case: zero / non-finite blocks", core)
+@pytest.mark.parametrize("core,variant", [("td", "block"), ("fft", "block"), ("fft", "wave")])
+def test_zero_and_nonfinite_blocks(ctx, core, variant):
+    _say("case: zero / non-finite blocks", core, variant)
     s = synth.gaussian(10000, 3)
     s[1000:3000] = 0.0
     s[7000] = np.nan
     k = synth.uniform(31, 4)
-    got, fields, info = _run_fixed(ctx, s, k, 256, O.SYM, core, 20, 20)
+    got, fields, info = _run_fixed(ctx, s, k, 256, O.SYM, core, 20, 20, variant=VARIANTS[variant])
     ref = O.conv_blocked(s, k, 256, O.fixed_params(s, k, 256, O.SYM, 20, 20))
     assert np.array_equal(np.isnan(got), np.isnan(ref))
     fin = ~np.isnan(ref)
@@ -213,11 +220,12 @@ def c2():
     return s, k
 
 
-@pytest.mark.parametrize("mode,S", [(O.ASYM2, 205), (O.SYM, 9)])
-def test_c2_fft_full_size(ctx, c2, mode, S):
-    _say("case: C2 full size FFT", mode, S)
+@pytest.mark.parametrize("variant", ["block", "wave"])
+@pytest.mark.parametrize("mode,S", [(O.ASYM2, 205), (O.SYM, 9), (O.ASYM3, 9)])
+def test_c2_fft_full_size(ctx, c2, mode, S, variant):
+    _say("case: C2 full size FFT", variant, mode, S)
     s, k = c2
-    got, fields, info = _run_fixed(ctx, s, k, 4096, mode, "fft", S, S)
+    got, fields, info = _run_fixed(ctx, s, k, 4096, mode, "fft", S, S, variant=VARIANTS[variant])
     _check_packed(s, k, 4096, mode, S, got, fields, info)
 
 
