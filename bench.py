@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--bufs", type=int, default=16)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the method shards by block ranges "
@@ -168,10 +170,12 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(alu_frac, 4)}
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(args.workload)  # scaled FETCH_SIZE + WRITE_SIZE, bytes/launch
     roof["alt"] = {"hbm_GBs": round(achieved_gbs, 1), "hbm_frac": round(hbm_frac, 4),
                    "fp64_TFLOPs": round(achieved_tf, 2), "fp64_frac": round(alu_frac, 4)}
-    roof["kernel"] = "k_fft<12>" if args.workload == "c2" else "k_td"
+    roof["kernel"] = kern.describe()
+    roof["bytes_per_launch"] = bytes_alg
+    roof["flops_per_launch"] = fl
 
     res = {
         "metric": "output samples/s at fixed SNR (>=40 dB per block), packed vs full-precision FP32, 1 GPU",
@@ -196,12 +200,44 @@ def main():
         "snr_db": {"min": float(np.min(snr_p)), "mean": float(np.mean(snr_p[np.isfinite(snr_p)]))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
     }
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = 2 * a.numel() * 4
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.workload, s, k, Wb, wl, calib, outputs)
     print(json.dumps(res), flush=True)
     for kh in {id(x): x for x in (kern, full, ref64)}.values():
         kh.close()
     ctx.close()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the packed kernel from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    if workload != "c2":
+        return None
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fft_c2_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("fftw.hip", "fft.h", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1201_3018_amd", "csrc", f), "rb").read())
+    if rec.get("kernel_sources_sha256_16") != h.hexdigest()[:16]:
+        return None
+    try:
+        return int(rec["traffic_bytes_per_launch"].split()[0])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(workload, s, k, Wb, wl, calib, outputs):

@@ -128,6 +128,10 @@ apx_status apx_conv(apx_ctx ctx, const float* s_in, int64_t L, const float* k, i
 apx_status apx_xcorr(apx_ctx ctx, const float* s_in, int64_t L, const float* k, int32_t N, int32_t W_block,
                      const apx_params* params, float* r_out, apx_block_info* info, void* stream);
 
+/* Host only.  A short description of how a prepared kernel runs (core, FFT kernel and transform
+ * sizes, companding ranges per mode) written into buf (host, size bytes, NUL-terminated). */
+apx_status apx_kernel_describe(apx_kernel kern, char* buf, int32_t size);
+
 const char* apx_status_str(apx_status st);
 const char* apx_last_error(void);
 

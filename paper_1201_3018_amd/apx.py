@@ -28,7 +28,8 @@ MODE_NAMES = {APX_FULL_FP32: "full", APX_SYM: "sym", APX_ASYM2: "asym2", APX_ASY
 
 # Every exported symbol of include/apx.h.
 EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "apx_kernel_destroy", "apx_run",
-           "apx_debug_fields", "apx_calibrate", "apx_conv", "apx_xcorr", "apx_status_str", "apx_last_error")
+           "apx_debug_fields", "apx_calibrate", "apx_conv", "apx_xcorr", "apx_kernel_describe", "apx_status_str",
+           "apx_last_error")
 
 
 class apx_params(ctypes.Structure):
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
         L.apx_calibrate.argtypes = [vp, vp, vp, i64, i32, i32, vp, ctypes.POINTER(dp)]
         L.apx_conv.argtypes = [vp, vp, i64, vp, i32, i32, ctypes.POINTER(apx_params), vp, vp, vp]
         L.apx_xcorr.argtypes = [vp, vp, i64, vp, i32, i32, ctypes.POINTER(apx_params), vp, vp, vp]
+        L.apx_kernel_describe.argtypes = [vp, ctypes.c_char_p, i32]
         L.apx_status_str.argtypes = [ctypes.c_int]
         L.apx_status_str.restype = ctypes.c_char_p
         L.apx_last_error.restype = ctypes.c_char_p
@@ -160,6 +162,12 @@ def apx_calibrate(ctx, kern, s, block: int = 0, Q: int = 8, stream=None) -> floa
     return off.value
 
 
+def apx_kernel_describe(kern) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().apx_kernel_describe(kern, buf, 512))
+    return buf.value.decode()
+
+
 def apx_conv(ctx, s, k, W_block: int, prm: apx_params, out, info=None, stream=None):
     _check(lib().apx_conv(ctx, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(k, "float32"), k.numel(), W_block,
                           ctypes.byref(prm), _dev_ptr(out, "float32"),
@@ -222,6 +230,9 @@ class Kernel:
         f = torch.empty(s.numel() + self.N - 1, dtype=torch.float64, device=s.device)
         apx_debug_fields(self.ctx.h, self.h, s, f, stream)
         return f
+
+    def describe(self) -> str:
+        return apx_kernel_describe(self.h)
 
     def calibrate(self, s, block: int = 0, Q: int = 8, stream=None) -> float:
         return apx_calibrate(self.ctx.h, self.h, s, block, Q, stream)

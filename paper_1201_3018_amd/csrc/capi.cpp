@@ -606,6 +606,25 @@ apx_status apx_calibrate(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, i
     return APX_OK;
 }
 
+apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {
+    if (!k || !buf || size < 1) return fail(APX_E_INVALID, "null argument");
+    char tmp[512];
+    int n;
+    if (k->core == APX_CORE_TIME) {
+        n = snprintf(tmp, sizeof tmp, "core=time kernel=k_td lds=%zu", k->td_lds);
+    } else if (k->wave) {
+        n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_fftw<%d,%d,%d,%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d",
+                     k->wM[1], k->wM[2], k->wM[3], k->wM[0], 2 * k->wM[0], 2 * k->wM[1], 2 * k->wM[2], 2 * k->wM[3]);
+    } else {
+        n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_fft<%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d", k->logF,
+                     k->Fw[0], k->Fw[1], k->Fw[2], k->Fw[3]);
+    }
+    snprintf(tmp + n, sizeof tmp - n, " N=%d W_block=%d W=%d SqKq(sym,asym2,asym3)=%d,%d,%d", k->N_odd, k->W_block,
+             k->W, k->S[1], k->S[2], k->S[3]);
+    snprintf(buf, size, "%s", tmp);
+    return APX_OK;
+}
+
 static apx_status oneshot(apx_ctx ctx, int op, const float* s, int64_t L, const float* kk, int32_t N, int32_t W_block,
                           const apx_params* params, float* out, apx_block_info* info, void* stream) {
     apx_kernel k = nullptr;

@@ -580,12 +580,18 @@ constexpr size_t wave_lds_bytes(size_t esz) {
     return (size_t)(M + M / (M / 64) + 1) * 2 * esz;
 }
 
-template <int MS, int MA2, int MA3, int MF, bool FIELDS>
+// MASK: bit m set = the packing mode m (MD_*) is compiled in; a block whose chosen mode is not
+// compiled in cannot occur (the host launches the instance that holds every mode it can choose).
+template <int MS, int MA2, int MA3, int MF, int MASK, bool FIELDS>
 __global__ void __launch_bounds__(64) k_fftw(RunArgs a) {
-    constexpr size_t B1 = wave_lds_bytes<MS>(8), B2 = wave_lds_bytes<MA2>(8), B3 = wave_lds_bytes<MA3>(8),
-                     B4 = wave_lds_bytes<MF>(4);
+    constexpr size_t B1 = ((MASK >> MD_SYM) & 1) ? wave_lds_bytes<MS>(8) : 0;
+    constexpr size_t B2 = ((MASK >> MD_ASYM2) & 1) ? wave_lds_bytes<MA2>(8) : 0;
+    constexpr size_t B3 = ((MASK >> MD_ASYM3) & 1) ? wave_lds_bytes<MA3>(8) : 0;
+    constexpr size_t B4 = ((MASK >> MD_FULL32) & 1) ? wave_lds_bytes<MF>(4) : 0;
+    constexpr size_t BW = 4 * (2 * (size_t)MF + 2);  // window with sentinels (W_block <= 2 MF)
     constexpr size_t B12 = B1 > B2 ? B1 : B2, B34 = B3 > B4 ? B3 : B4;
-    constexpr size_t BYTES = B12 > B34 ? B12 : B34;
+    constexpr size_t BF = B12 > B34 ? B12 : B34;
+    constexpr size_t BYTES = BF > BW ? BF : BW;
     __shared__ __attribute__((aligned(16))) char lds[BYTES];
     // one item per workgroup (a loop here makes the compiler keep every per-lane address of the
     // body live across iterations, which spills)
@@ -617,12 +623,14 @@ __global__ void __launch_bounds__(64) k_fftw(RunArgs a) {
             }
             return;
         }
-        switch (c.mode) {
-            case MD_SYM: wave_item<MD_SYM, MS, FIELDS>(a, it, c, lds); break;
-            case MD_ASYM2: wave_item<MD_ASYM2, MA2, FIELDS>(a, it, c, lds); break;
-            case MD_ASYM3: wave_item<MD_ASYM3, MA3, FIELDS>(a, it, c, lds); break;
-            default: wave_item<MD_FULL32, MF, FIELDS>(a, it, c, lds); break;
-        }
+        if constexpr ((MASK >> MD_SYM) & 1)
+            if (c.mode == MD_SYM) wave_item<MD_SYM, MS, FIELDS>(a, it, c, lds);
+        if constexpr ((MASK >> MD_ASYM2) & 1)
+            if (c.mode == MD_ASYM2) wave_item<MD_ASYM2, MA2, FIELDS>(a, it, c, lds);
+        if constexpr ((MASK >> MD_ASYM3) & 1)
+            if (c.mode == MD_ASYM3) wave_item<MD_ASYM3, MA3, FIELDS>(a, it, c, lds);
+        if constexpr ((MASK >> MD_FULL32) & 1)
+            if (c.mode == MD_FULL32) wave_item<MD_FULL32, MF, FIELDS>(a, it, c, lds);
     }
 }
 
@@ -630,8 +638,6 @@ __global__ void __launch_bounds__(64) k_fftw(RunArgs a) {
 #define APX_WAVE_SETS(X)          \
     X(1024, 1536, 1024, 2048)     \
     X(1024, 1536, 1536, 2048)     \
-    X(1024, 2048, 1536, 2048)     \
-    X(1024, 2048, 2048, 2048)     \
     X(512, 1024, 512, 1024)       \
     X(512, 1024, 1024, 1024)      \
     X(512, 512, 512, 1024)        \
@@ -645,16 +651,30 @@ bool wave_supported(int ms, int ma2, int ma3, int mf) {
     return false;
 }
 
+// One instance per size set and mode set: the four fixed modes alone, the per-block choice
+// (symmetric, asymmetric M=2, FP32), and every mode with the integer-field output.
+template <int A, int B, int C, int D>
+static hipError_t launch_set(const RunArgs& a, unsigned grid, hipStream_t st) {
+    constexpr int ALL = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_ASYM3) | (1 << MD_FULL32);
+    constexpr int AUTO = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_FULL32);
+    if (a.fields) {
+        hipLaunchKernelGGL((k_fftw<A, B, C, D, ALL, true>), dim3(grid), dim3(64), 0, st, a);
+    } else {
+        switch (a.mode) {
+            case MD_SYM: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_SYM, false>), dim3(grid), dim3(64), 0, st, a); break;
+            case MD_ASYM2: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_ASYM2, false>), dim3(grid), dim3(64), 0, st, a); break;
+            case MD_ASYM3: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_ASYM3, false>), dim3(grid), dim3(64), 0, st, a); break;
+            case MD_FULL32: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_FULL32, false>), dim3(grid), dim3(64), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_fftw<A, B, C, D, AUTO, false>), dim3(grid), dim3(64), 0, st, a); break;
+        }
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st) {
     const unsigned grid = (unsigned)(a.P + 1);
-#define APX_LAUNCH(a_, b_, c_, d_)                                                         \
-    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) {                                  \
-        if (a.fields)                                                                      \
-            hipLaunchKernelGGL((k_fftw<a_, b_, c_, d_, true>), dim3(grid), dim3(64), 0, st, a);  \
-        else                                                                               \
-            hipLaunchKernelGGL((k_fftw<a_, b_, c_, d_, false>), dim3(grid), dim3(64), 0, st, a); \
-        return hipGetLastError();                                                          \
-    }
+#define APX_LAUNCH(a_, b_, c_, d_) \
+    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return launch_set<a_, b_, c_, d_>(a, grid, st);
     APX_WAVE_SETS(APX_LAUNCH)
 #undef APX_LAUNCH
     return hipErrorInvalidValue;
