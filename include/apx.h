@@ -132,6 +132,46 @@ apx_status apx_xcorr(apx_ctx ctx, const float* s_in, int64_t L, const float* k, 
  * sizes, companding ranges per mode) written into buf (host, size bytes, NUL-terminated). */
 apx_status apx_kernel_describe(apx_kernel kern, char* buf, int32_t size);
 
+/* ---- Batched cross-correlation matching ----------------------------------------------------
+ * n pairs (reference s_t of L_t samples, template k_t of N_t taps).  For each pair the
+ * correlation c_t[l] = sum_n s_t[l+n] k_t[n], l in [-(N_t-1), L_t-1], is computed exactly as
+ * apx_xcorr would with the same fixed mode and the pair's W_block (apx_batch_blocks), and only
+ * its maximum is kept: lag_out[t] = the lag of the largest value (ties: smallest lag),
+ * val_out[t] = that value (FP32 output of eq. 16).  NaN outputs (blocks whose window holds a NaN
+ * or infinity) take no part; with no other output lag_out = INT64_MIN and val_out = NaN.
+ * This is the matching use of correlation in the paper's applications (Section IV.B).
+ *
+ * All pairs share one packed FFT length of 2^logW words (11..14); each pair's block size is the
+ * largest one whose packed words fit it (FP32: W_block = 2^logW samples; symmetric: 2^(logW+1);
+ * asymmetric M: W = M (2^logW - N + 1) rounded down to even), with W >= 2N (Section III
+ * opening).  One persistent launch processes every (pair, block) item.
+ *
+ * apx_batch_create: refs, tmpl are HOST arrays of n DEVICE pointers (FP32), L and N host arrays.
+ *   Pointers are kept by the batch: the reference and template memory must stay valid and
+ *   unchanged until apx_batch_destroy (templates are read at create time, references at every
+ *   run).  params->mode must be APX_FULL_FP32, APX_SYM, APX_ASYM2 or APX_ASYM3 (else
+ *   APX_E_UNSUPPORTED); Sq/Kq/allow_unsafe as for apx_kernel_create.  logW = 0 autotunes: every
+ *   FFT length that fits all pairs and a work-grab of 1, 2 or 4 items are timed on `stream`
+ *   (this runs the batch several times) and the fastest is kept.  Synchronizes `stream`.
+ * apx_batch_run: lag_out (device, n int64), val_out (device, n float).  Enqueued on `stream`;
+ *   allocates nothing and launches three kernels (clear, persistent matching, finish), so it can
+ *   be captured into a HIP graph.  Runs of one batch must not overlap (they share its counters).
+ * apx_batch_blocks (host only): W_block per pair (host array of n, nullable), the FFT length
+ *   log2 and the number of work items.
+ * apx_batch_describe (host only): kernel, grid, grab size and the tuning table as text. */
+typedef struct apx_batch_s* apx_batch;
+apx_status apx_batch_create(apx_ctx ctx, int32_t n, const float* const* refs, const int64_t* L,
+                            const float* const* tmpl, const int32_t* N, const apx_params* params, int32_t logW,
+                            void* stream, apx_batch* out);
+apx_status apx_batch_run(apx_ctx ctx, apx_batch batch, int64_t* lag_out, float* val_out, void* stream);
+apx_status apx_batch_blocks(apx_batch batch, int32_t* W_block, int32_t* logW, int32_t* nitems);
+apx_status apx_batch_describe(apx_batch batch, char* buf, int32_t size);
+apx_status apx_batch_destroy(apx_batch batch);
+/* One shot: create (autotuned) + run + destroy.  Synchronizes. */
+apx_status apx_xcorr_argmax_batch(apx_ctx ctx, int32_t n, const float* const* refs, const int64_t* L,
+                                  const float* const* tmpl, const int32_t* N, const apx_params* params,
+                                  int64_t* lag_out, float* val_out, void* stream);
+
 const char* apx_status_str(apx_status st);
 const char* apx_last_error(void);
 

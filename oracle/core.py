@@ -152,6 +152,18 @@ def argmax_lag(c: np.ndarray, N: int):
     return i - (N - 1), c[i]
 
 
+def argmax_lag_finite(c: np.ndarray, N: int):
+    """argmax_lag over the entries that are not NaN (-0 equals +0, ties to the smallest lag);
+    (None, nan) when every entry is NaN.  The matching step of the correlation applications
+    (Section IV.B) picks the lag of the largest correlation."""
+    c = np.asarray(c)
+    ok = np.nonzero(~np.isnan(c))[0]
+    if ok.size == 0:
+        return None, float("nan")
+    j = int(np.argmax(c[ok]))
+    return int(ok[j]) - (N - 1), c[ok[j]]
+
+
 # ----------------------------------------------------------------------------------------
 # Overlap-save partition (Section II, Section III opening, eqs. 10 and 17)
 # ----------------------------------------------------------------------------------------
@@ -581,6 +593,19 @@ def conv_blocked_paper(s, k, W_block: int, mode: str, S: int, K: int, core: str 
         if cs != 0.0 and ck != 0.0:
             out[o: o + seg.size] = (1.0 / (cs * ck)) * seg.astype(np.float64)     # eq. (16)
     return out.astype(np.float32), fields
+
+
+def xcorr_blocked(s, k, W_block: int, mode: str, S: int = 0, K: int = 0, out_dtype=np.float32):
+    """Cross-correlation c[l] = sum_n s[l+n] k[n] (index l + N - 1) through the blocked
+    companded convolution of conv_blocked with the time-reversed kernel, every block in `mode`
+    at S_q, K_q (0 = the largest the mode allows, reading R13); FP64 blocks for FULL."""
+    s = np.asarray(s, dtype=np.float32)
+    kr = np.ascontiguousarray(np.asarray(k, dtype=np.float32)[::-1])
+    N_odd = kr.size if kr.size % 2 else kr.size + 1
+    if mode != FULL:
+        S = S or max_q(mode, N_odd)
+        K = K or max_q(mode, N_odd)
+    return conv_blocked(s, kr, W_block, fixed_params(s, kr, W_block, mode, S, K), out_dtype=out_dtype)
 
 
 def int_fields(s, k, W_block: int, S: int, K: int):

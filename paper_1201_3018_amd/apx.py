@@ -28,8 +28,9 @@ MODE_NAMES = {APX_FULL_FP32: "full", APX_SYM: "sym", APX_ASYM2: "asym2", APX_ASY
 
 # Every exported symbol of include/apx.h.
 EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "apx_kernel_destroy", "apx_run",
-           "apx_debug_fields", "apx_calibrate", "apx_conv", "apx_xcorr", "apx_kernel_describe", "apx_status_str",
-           "apx_last_error")
+           "apx_debug_fields", "apx_calibrate", "apx_conv", "apx_xcorr", "apx_kernel_describe", "apx_batch_create",
+           "apx_batch_run", "apx_batch_blocks", "apx_batch_describe", "apx_batch_destroy", "apx_xcorr_argmax_batch",
+           "apx_status_str", "apx_last_error")
 
 
 class apx_params(ctypes.Structure):
@@ -77,6 +78,13 @@ def lib() -> ctypes.CDLL:
         L.apx_conv.argtypes = [vp, vp, i64, vp, i32, i32, ctypes.POINTER(apx_params), vp, vp, vp]
         L.apx_xcorr.argtypes = [vp, vp, i64, vp, i32, i32, ctypes.POINTER(apx_params), vp, vp, vp]
         L.apx_kernel_describe.argtypes = [vp, ctypes.c_char_p, i32]
+        pvp, pi64, pi32 = ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i32)
+        L.apx_batch_create.argtypes = [vp, i32, pvp, pi64, pvp, pi32, ctypes.POINTER(apx_params), i32, vp, pvp]
+        L.apx_batch_run.argtypes = [vp, vp, vp, vp, vp]
+        L.apx_batch_blocks.argtypes = [vp, pi32, pi32, pi32]
+        L.apx_batch_describe.argtypes = [vp, ctypes.c_char_p, i32]
+        L.apx_batch_destroy.argtypes = [vp]
+        L.apx_xcorr_argmax_batch.argtypes = [vp, i32, pvp, pi64, pvp, pi32, ctypes.POINTER(apx_params), vp, vp, vp]
         L.apx_status_str.argtypes = [ctypes.c_int]
         L.apx_status_str.restype = ctypes.c_char_p
         L.apx_last_error.restype = ctypes.c_char_p
@@ -180,6 +188,58 @@ def apx_xcorr(ctx, s, k, W_block: int, prm: apx_params, out, info=None, stream=N
                            None if info is None else _dev_ptr(info, "uint8"), _stream(stream)))
 
 
+def _pair_arrays(refs, tmpls):
+    n = len(refs)
+    if len(tmpls) != n:
+        raise ValueError("one template per reference")
+    rp = (ctypes.c_void_p * n)(*[_dev_ptr(r, "float32").value for r in refs])
+    tp = (ctypes.c_void_p * n)(*[_dev_ptr(k, "float32").value for k in tmpls])
+    L = (ctypes.c_int64 * n)(*[r.numel() for r in refs])
+    N = (ctypes.c_int32 * n)(*[k.numel() for k in tmpls])
+    return n, rp, L, tp, N
+
+
+def apx_batch_create(ctx, refs, tmpls, prm: apx_params, logW: int = 0, stream=None):
+    n, rp, L, tp, N = _pair_arrays(refs, tmpls)
+    h = ctypes.c_void_p()
+    _check(lib().apx_batch_create(ctx, n, rp, L, tp, N, ctypes.byref(prm), logW, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def apx_batch_run(ctx, batch, lag_out, val_out, stream=None):
+    import torch
+    if not (lag_out.is_cuda and lag_out.dtype == torch.int64 and lag_out.is_contiguous()):
+        raise ValueError("lag_out must be a contiguous int64 device tensor")
+    _check(lib().apx_batch_run(ctx, batch, ctypes.c_void_p(lag_out.data_ptr()), _dev_ptr(val_out, "float32"),
+                               _stream(stream)))
+
+
+def apx_batch_blocks(batch, n: int):
+    wb = (ctypes.c_int32 * n)()
+    lw, ni = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().apx_batch_blocks(batch, wb, ctypes.byref(lw), ctypes.byref(ni)))
+    return np.array(wb[:], dtype=np.int64), lw.value, ni.value
+
+
+def apx_batch_describe(batch) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().apx_batch_describe(batch, buf, 4096))
+    return buf.value.decode()
+
+
+def apx_batch_destroy(batch):
+    _check(lib().apx_batch_destroy(batch))
+
+
+def apx_xcorr_argmax_batch(ctx, refs, tmpls, prm: apx_params, lag_out, val_out, stream=None):
+    import torch
+    n, rp, L, tp, N = _pair_arrays(refs, tmpls)
+    if not (lag_out.is_cuda and lag_out.dtype == torch.int64 and lag_out.is_contiguous()):
+        raise ValueError("lag_out must be a contiguous int64 device tensor")
+    _check(lib().apx_xcorr_argmax_batch(ctx, n, rp, L, tp, N, ctypes.byref(prm), ctypes.c_void_p(lag_out.data_ptr()),
+                                        _dev_ptr(val_out, "float32"), _stream(stream)))
+
+
 # ------------------------------------------------------------------------------- conveniences
 class Context:
     def __init__(self, device: int = 0):
@@ -252,3 +312,44 @@ class Kernel:
 def block_info(info_tensor) -> np.ndarray:
     """Device block-report bytes -> numpy structured array (synchronizes)."""
     return np.frombuffer(info_tensor.cpu().numpy().tobytes(), dtype=BLOCK_INFO_DTYPE)
+
+
+class Batch:
+    """Batched cross-correlation matching of (reference, template) pairs in one persistent launch.
+    Keeps the tensors alive: the library holds their device pointers."""
+
+    def __init__(self, ctx: Context, refs, tmpls, mode=APX_SYM, Sq=0, Kq=0, allow_unsafe=False, logW: int = 0,
+                 stream=None):
+        self.ctx = ctx
+        self.refs, self.tmpls = list(refs), list(tmpls)
+        self.n = len(self.refs)
+        self.prm = params(mode, APX_CORE_FFT, Sq, Kq, 0.0, float("nan"), allow_unsafe)
+        self.h = apx_batch_create(ctx.h, self.refs, self.tmpls, self.prm, logW, stream)
+
+    def run(self, lag=None, val=None, stream=None):
+        import torch
+        dev = self.refs[0].device
+        if lag is None:
+            lag = torch.empty(self.n, dtype=torch.int64, device=dev)
+        if val is None:
+            val = torch.empty(self.n, dtype=torch.float32, device=dev)
+        apx_batch_run(self.ctx.h, self.h, lag, val, stream)
+        return lag, val
+
+    def blocks(self):
+        """(W_block per pair, log2 FFT length, work items)."""
+        return apx_batch_blocks(self.h, self.n)
+
+    def describe(self) -> str:
+        return apx_batch_describe(self.h)
+
+    def close(self):
+        if self.h:
+            apx_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

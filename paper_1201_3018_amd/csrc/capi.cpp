@@ -101,12 +101,22 @@ struct apx_kernel_s {
     double2* coef[4] = {nullptr, nullptr, nullptr, nullptr};
     float2* coef32 = nullptr;
     std::vector<void*> allocs;
+    // device buffers carved from a caller-owned pool instead of hipMalloc (batched pairs)
+    char* pool = nullptr;
+    size_t pool_off = 0, pool_cap = 0;
 };
 
 namespace {
 
 template <typename T>
 apx_status dalloc(apx_kernel k, T** p, size_t n) {
+    if (k->pool) {
+        const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) / 256 * 256;
+        if (k->pool_off + bytes > k->pool_cap) return fail(APX_E_NOMEM, "pair buffer pool exhausted");
+        *p = (T*)(k->pool + k->pool_off);
+        k->pool_off += bytes;
+        return APX_OK;
+    }
     void* q = nullptr;
     hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
     if (e != hipSuccess) return fail(APX_E_NOMEM, "hipMalloc(%zu): %s", n * sizeof(T), hipGetErrorString(e));
@@ -347,10 +357,15 @@ apx_status apx_geometry(int64_t L, int32_t N, int32_t W_block, int32_t* N_odd, i
     return geometry(L, N, W_block, N_odd, W, P);
 }
 
-apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t op, int32_t W_block,
-                             const apx_params* params, void* stream, apx_kernel* out) {
-    if (!out) return fail(APX_E_INVALID, "null output handle");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Prepare kernel state into *k (fresh).  fft_words > 0 forces the FFT core with that packed word
+// length for every mode (the batched path); 0 = the rules of apx_kernel_create.  On failure the
+// device buffers of k are released (pool buffers belong to the pool).
+apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, int32_t op, int32_t W_block,
+                       const apx_params* params, void* stream, int32_t fft_words) {
     if (!ctx || !k_in || !params) return fail(APX_E_INVALID, "null argument");
     if (op != APX_CONV && op != APX_XCORR) return fail(APX_E_INVALID, "unknown op %d", op);
     int32_t N_odd = 0, W = 0;
@@ -362,8 +377,6 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     if (p.Sq < 0 || p.Kq < 0) return fail(APX_E_INVALID, "negative companding range");
     if (p.mode == APX_AUTO_SNR && !isfinite(p.snr_min_db)) return fail(APX_E_INVALID, "snr_min_db must be finite");
 
-    apx_kernel k = new (std::nothrow) apx_kernel_s;
-    if (!k) return fail(APX_E_NOMEM, "host allocation failed");
     k->ctx = ctx;
     k->N = N;
     k->N_odd = N_odd;
@@ -387,17 +400,14 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     if (p.mode >= APX_SYM && p.mode <= APX_ASYM3) {
         const int m = p.mode;
         if (k->S[m] < 1 || k->K[m] < 1) {
-            delete k;
             return fail(APX_E_BOUND, "no companding range S_q = K_q >= 1 fits the bound for N = %d", N_odd);
         }
         if (k->R[m] > bound_of(m) && !p.allow_unsafe) {
             int64_t Rm = k->R[m];
-            delete k;
             return fail(APX_E_BOUND, "R_max = N S_q K_q = %lld exceeds the bound %lld (Table 1)", (long long)Rm,
                         (long long)bound_of(m));
         }
         if (k->R[m] > ((int64_t)1 << 40)) {
-            delete k;
             return fail(APX_E_UNSUPPORTED, "R_max too large");
         }
         k->use[m] = true;
@@ -416,17 +426,23 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     int core = p.core;
     if (p.mode == APX_FULL_FP64) {
         if (core == APX_CORE_FFT) {
-            delete k;
             return fail(APX_E_UNSUPPORTED, "FP64 full precision runs on the time-domain core only");
         }
         core = APX_CORE_TIME;
     }
     if (core == APX_CORE_AUTO) core = (N_odd <= 129) ? APX_CORE_TIME : APX_CORE_FFT;
+    if (fft_words > 0) core = APX_CORE_FFT;
     k->core = core;
-    if (core == APX_CORE_FFT) {
+    if (fft_words > 0) {
+        if (p.mode == APX_AUTO_SNR || p.mode == APX_FULL_FP64)
+            return fail(APX_E_UNSUPPORTED, "a forced FFT length needs a fixed mode");
+        k->logF = ceil_log2(fft_words);
+        if ((1 << k->logF) != fft_words || k->logF > LOGF_MAX_TABLE || k->logF < 8)
+            return fail(APX_E_UNSUPPORTED, "FFT length %d", fft_words);
+        for (int m = 0; m < 4; ++m) k->Fw[m] = fft_words;
+    } else if (core == APX_CORE_FFT) {
         k->logF = std::max(ceil_log2(W_block), fft_min_logF());
         if (k->logF > fft_max_logF()) {
-            delete k;
             return fail(APX_E_UNSUPPORTED, "FFT core supports W_block <= %d", 1 << fft_max_logF());
         }
         const int F = 1 << k->logF;
@@ -458,23 +474,18 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
             }
         }
         if (p.fft_variant == 2 && !k->wave) {
-            delete k;
             return fail(APX_E_UNSUPPORTED, "no compiled wave-FFT size set covers W_block = %d, N = %d", W_block, N);
         }
     } else {
         k->td_lds = td_lds_bytes(p.mode, N_odd, W_block, k->T[MD_ASYM2], k->T[MD_ASYM3]);
         if (k->td_lds > (size_t)ctx->max_lds) {
-            delete k;
             return fail(APX_E_UNSUPPORTED, "time-domain block needs %zu bytes of LDS (> %d); use the FFT core",
                         k->td_lds, ctx->max_lds);
         }
     }
     // device state
     hipStream_t st = (hipStream_t)stream;
-    if (hipSetDevice(ctx->device) != hipSuccess) {
-        delete k;
-        return fail(APX_E_DEVICE, "hipSetDevice failed");
-    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(APX_E_DEVICE, "hipSetDevice failed");
     k->kf_pad = pad8(N_odd);
     const int nsym = (N_odd + 1) / 2;
     k->kq_len[MD_SYM] = nsym;
@@ -504,7 +515,6 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     }
     if (r != APX_OK) {
         free_kernel(k);
-        delete k;
         return r;
     }
     hipError_t e = launch_prepare_kernel(k_in, N, N_odd, op == APX_XCORR, k->ks, k->kf, k->kd, k->kf_pad + 8,
@@ -530,8 +540,25 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     }
     if (e != hipSuccess) {
         free_kernel(k);
-        delete k;
         return fail(APX_E_DEVICE, "kernel preparation launch: %s", hipGetErrorString(e));
+    }
+    return APX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t op, int32_t W_block,
+                             const apx_params* params, void* stream, apx_kernel* out) {
+    if (!out) return fail(APX_E_INVALID, "null output handle");
+    *out = nullptr;
+    apx_kernel k = new (std::nothrow) apx_kernel_s;
+    if (!k) return fail(APX_E_NOMEM, "host allocation failed");
+    apx_status r = init_kernel(k, ctx, k_in, N, op, W_block, params, stream, 0);
+    if (r != APX_OK) {
+        delete k;
+        return r;
     }
     *out = k;
     return APX_OK;
@@ -646,6 +673,303 @@ apx_status apx_conv(apx_ctx ctx, const float* s, int64_t L, const float* k, int3
 apx_status apx_xcorr(apx_ctx ctx, const float* s, int64_t L, const float* k, int32_t N, int32_t W_block,
                      const apx_params* params, float* out, apx_block_info* info, void* stream) {
     return oneshot(ctx, APX_XCORR, s, L, k, N, W_block, params, out, info, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Batched cross-correlation matching
+// ------------------------------------------------------------------------------------------
+
+struct apx_batch_s {
+    apx_ctx ctx = nullptr;
+    int32_t n = 0;
+    int mode = 0;
+    int logW = 0, chunk = 1, grid = 0, per_cu = 0;
+    std::vector<apx_kernel_s> kerns;  // per pair; device buffers in `pool`
+    char* pool = nullptr;
+    RunArgs* d_args = nullptr;
+    int2* d_items = nullptr;
+    int32_t nitems = 0;
+    unsigned int* d_counter = nullptr;
+    unsigned long long* d_keys = nullptr;
+    int32_t* d_N = nullptr;
+    std::vector<int32_t> W_block;
+    std::string tune_log;
+};
+
+namespace {
+
+void batch_free(apx_batch b) {
+    if (!b) return;
+    (void)hipSetDevice(b->ctx->device);
+    for (void* p : {(void*)b->pool, (void*)b->d_args, (void*)b->d_items, (void*)b->d_counter, (void*)b->d_keys,
+                    (void*)b->d_N})
+        if (p) (void)hipFree(p);
+    delete b;
+}
+
+// Largest block for a pair at packed word length `words`: FP32 W_block = words; symmetric two
+// samples per word; asymmetric T = W / M parts of T + N - 1 words (T rounded up).  0 if W would
+// fall below 2 N (Section III opening).
+int32_t batch_block(int mode, int32_t N, int32_t words) {
+    const int32_t no = (N % 2) ? N : N + 1;
+    int64_t W;
+    if (mode == MD_FULL32) W = (int64_t)words - no - 1;
+    else if (mode == MD_SYM) W = 2 * (int64_t)words - no - 1;
+    else {
+        const int M = mode == MD_ASYM2 ? 2 : 3;
+        W = (int64_t)M * (words - no + 1);
+        W -= W % 2;
+    }
+    if (W < 2 * (int64_t)no || W % 2) return 0;
+    return (int32_t)(W + no + 1);
+}
+
+apx_status batch_build(apx_ctx ctx, int32_t n, const float* const* refs, const int64_t* L, const float* const* tmpl,
+                       const int32_t* N, const apx_params* params, int32_t logW, hipStream_t st, apx_batch* out) {
+    *out = nullptr;
+    const int mode = params->mode;
+    const int32_t words = 1 << logW;
+    apx_batch b = new (std::nothrow) apx_batch_s;
+    if (!b) return fail(APX_E_NOMEM, "host allocation failed");
+    b->ctx = ctx;
+    b->n = n;
+    b->mode = mode;
+    b->logW = logW;
+    b->kerns.resize(n);
+    b->W_block.resize(n);
+    // pool: per pair KState, FP32 and FP64 taps, companded taps, spectrum, each 256-aligned
+    size_t pool_bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        b->W_block[i] = batch_block(mode, N[i], words);
+        if (b->W_block[i] == 0) {
+            batch_free(b);
+            return fail(APX_E_UNSUPPORTED, "pair %d: N = %d too long for FFT length %d", i, N[i], words);
+        }
+        const size_t taps = (size_t)pad8(N[i] + 1) + 16;
+        pool_bytes += 6 * 256 + sizeof(KState) + taps * (4 + 8 + 8) + ((size_t)words / 2 + 1) * 16;
+    }
+    apx_status r = APX_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (hipMalloc((void**)&b->pool, pool_bytes) != hipSuccess) {
+        batch_free(b);
+        return fail(APX_E_NOMEM, "pair pool of %zu bytes", pool_bytes);
+    }
+    size_t off = 0;
+    std::vector<RunArgs> args(n);
+    std::vector<int64_t> P(n);
+    for (int i = 0; i < n && r == APX_OK; ++i) {
+        apx_kernel k = &b->kerns[i];
+        const size_t taps = (size_t)pad8(N[i] + 1) + 16;
+        const size_t mine = 6 * 256 + sizeof(KState) + taps * (4 + 8 + 8) + ((size_t)words / 2 + 1) * 16;
+        k->pool = b->pool + off;
+        k->pool_cap = mine;
+        off += mine;
+        r = init_kernel(k, ctx, tmpl[i], N[i], APX_XCORR, b->W_block[i], params, st, words);
+        if (r == APX_OK) r = geometry(L[i], N[i], b->W_block[i], nullptr, nullptr, &P[i]);
+        if (r == APX_OK) args[i] = make_args(k, refs[i], L[i], nullptr, nullptr, nullptr, P[i]);
+        if (r != APX_OK) r = fail(r, "pair %d: %s", i, g_err.c_str());
+    }
+    if (r != APX_OK) {
+        batch_free(b);
+        return r;
+    }
+    // work list: pairs in decreasing block count (longest first), blocks in order
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return P[x] > P[y]; });
+    std::vector<int2> items;
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) total += P[i] + 1;
+    if (total > 0x7fffffff / 2) {
+        batch_free(b);
+        return fail(APX_E_UNSUPPORTED, "%lld blocks in one batch", (long long)total);
+    }
+    items.reserve(total);
+    for (int i : order)
+        for (int64_t w = 0; w <= P[i]; ++w) items.push_back(make_int2(i, (int)w));
+    b->nitems = (int32_t)items.size();
+    hipError_t e = hipMalloc((void**)&b->d_args, sizeof(RunArgs) * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_items, sizeof(int2) * items.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 256);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_keys, sizeof(unsigned long long) * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_N, sizeof(int32_t) * n);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return fail(APX_E_NOMEM, "batch tables: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpyAsync(b->d_args, args.data(), sizeof(RunArgs) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_N, N, sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging vectors go out of scope
+    if (e == hipSuccess) e = batch_occupancy(mode, logW, &b->per_cu);
+    if (e != hipSuccess || b->per_cu < 1) {
+        batch_free(b);
+        return fail(APX_E_DEVICE, "batch setup: %s", hipGetErrorString(e));
+    }
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    b->grid = std::max(1, b->per_cu * cus);
+    *out = b;
+    return APX_OK;
+}
+
+BatchLaunch batch_args(apx_batch b, int64_t* lag, float* val, hipStream_t st) {
+    BatchLaunch l{};
+    l.mode = b->mode;
+    l.logW = b->logW;
+    l.targs = b->d_args;
+    l.items = b->d_items;
+    l.nitems = b->nitems;
+    l.chunk = b->chunk;
+    const int64_t need = (b->nitems + b->chunk - 1) / b->chunk;
+    l.grid = (int)std::min<int64_t>(b->grid, std::max<int64_t>(need, 1));
+    l.npairs = b->n;
+    l.counter = b->d_counter;
+    l.keys = b->d_keys;
+    l.Ngiven = b->d_N;
+    l.lag = lag;
+    l.val = val;
+    l.st = st;
+    return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+apx_status apx_batch_create(apx_ctx ctx, int32_t n, const float* const* refs, const int64_t* L,
+                            const float* const* tmpl, const int32_t* N, const apx_params* params, int32_t logW,
+                            void* stream, apx_batch* out) {
+    if (!out) return fail(APX_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (!ctx || !refs || !L || !tmpl || !N || !params) return fail(APX_E_INVALID, "null argument");
+    if (n < 1) return fail(APX_E_INVALID, "batch of %d pairs", n);
+    const int mode = params->mode;
+    if (mode != APX_FULL_FP32 && mode != APX_SYM && mode != APX_ASYM2 && mode != APX_ASYM3)
+        return fail(APX_E_UNSUPPORTED, "batched matching runs a fixed mode (FP32, symmetric or asymmetric)");
+    if (logW != 0 && (logW < BATCH_LOGW_MIN || logW > BATCH_LOGW_MAX))
+        return fail(APX_E_INVALID, "log2 FFT length %d outside [%d, %d]", logW, BATCH_LOGW_MIN, BATCH_LOGW_MAX);
+    for (int i = 0; i < n; ++i) {
+        if (!refs[i] || !tmpl[i]) return fail(APX_E_INVALID, "pair %d: null pointer", i);
+        if (N[i] < 1 || L[i] < N[i]) return fail(APX_E_INVALID, "pair %d: need 1 <= N <= L", i);
+        if (L[i] + N[i] - 1 > (int64_t)0xFFFFFFFEll) return fail(APX_E_UNSUPPORTED, "pair %d: too long", i);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (logW != 0) return batch_build(ctx, n, refs, L, tmpl, N, params, logW, st, out);
+
+    // autotuning: every FFT length that fits all pairs, times a grab of 1, 2 or 4 items;
+    // each candidate is run once to warm up and once timed on the caller's stream
+    apx_batch best = nullptr;
+    float best_ms = 0.0f;
+    int best_chunk = 1;
+    std::string log;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int64_t* lag = nullptr;
+    float* val = nullptr;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    apx_status r = APX_OK;
+    if (hipMalloc((void**)&lag, sizeof(int64_t) * n) != hipSuccess ||
+        hipMalloc((void**)&val, sizeof(float) * n) != hipSuccess)
+        r = fail(APX_E_NOMEM, "tuning outputs");
+    for (int lw = BATCH_LOGW_MIN; lw <= BATCH_LOGW_MAX && r == APX_OK; ++lw) {
+        bool fits = true;
+        for (int i = 0; i < n && fits; ++i) fits = batch_block(mode, N[i], 1 << lw) != 0;
+        if (!fits) continue;
+        apx_batch b = nullptr;
+        apx_status rb = batch_build(ctx, n, refs, L, tmpl, N, params, lw, st, &b);
+        if (rb == APX_E_NOMEM || rb == APX_E_UNSUPPORTED) continue;
+        if (rb != APX_OK) {
+            r = rb;
+            break;
+        }
+        bool kept = false;
+        for (int chunk : {1, 2, 4}) {
+            b->chunk = chunk;
+            hipError_t e = launch_batch(batch_args(b, lag, val, st));
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = launch_batch(batch_args(b, lag, val, st));
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                r = fail(APX_E_DEVICE, "tuning run: %s", hipGetErrorString(e));
+                break;
+            }
+            char line[96];
+            snprintf(line, sizeof line, "%slogW=%d chunk=%d %.3f ms", log.empty() ? "" : "; ", lw, chunk, ms);
+            log += line;
+            if (!best || ms < best_ms) {
+                if (best && best != b) batch_free(best);
+                best = b;
+                best_ms = ms;
+                best_chunk = chunk;
+                kept = true;
+            }
+        }
+        if (!kept) batch_free(b);
+    }
+    if (lag) (void)hipFree(lag);
+    if (val) (void)hipFree(val);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != APX_OK) {
+        if (best) batch_free(best);
+        return r;
+    }
+    if (!best) return fail(APX_E_UNSUPPORTED, "no FFT length up to %d fits every pair", 1 << BATCH_LOGW_MAX);
+    best->chunk = best_chunk;
+    best->tune_log = log;
+    *out = best;
+    return APX_OK;
+}
+
+apx_status apx_batch_run(apx_ctx ctx, apx_batch b, int64_t* lag_out, float* val_out, void* stream) {
+    if (!ctx || !b || !lag_out || !val_out) return fail(APX_E_INVALID, "null argument");
+    if (b->ctx != ctx) return fail(APX_E_INVALID, "batch belongs to another context");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_batch(batch_args(b, lag_out, val_out, (hipStream_t)stream)));
+    return APX_OK;
+}
+
+apx_status apx_batch_blocks(apx_batch b, int32_t* W_block, int32_t* logW, int32_t* nitems) {
+    if (!b) return fail(APX_E_INVALID, "null batch");
+    if (W_block) memcpy(W_block, b->W_block.data(), sizeof(int32_t) * b->n);
+    if (logW) *logW = b->logW;
+    if (nitems) *nitems = b->nitems;
+    return APX_OK;
+}
+
+apx_status apx_batch_describe(apx_batch b, char* buf, int32_t size) {
+    if (!b || !buf || size < 1) return fail(APX_E_INVALID, "null argument");
+    snprintf(buf, size, "kernel=k_batch<%d,%d> pairs=%d items=%d chunk=%d grid=%d wg_per_cu=%d lds=%zu tune=[%s]",
+             b->mode, b->logW, b->n, b->nitems, b->chunk, b->grid, b->per_cu, batch_lds_bytes(b->mode, b->logW),
+             b->tune_log.c_str());
+    return APX_OK;
+}
+
+apx_status apx_batch_destroy(apx_batch b) {
+    batch_free(b);
+    return APX_OK;
+}
+
+apx_status apx_xcorr_argmax_batch(apx_ctx ctx, int32_t n, const float* const* refs, const int64_t* L,
+                                  const float* const* tmpl, const int32_t* N, const apx_params* params,
+                                  int64_t* lag_out, float* val_out, void* stream) {
+    apx_batch b = nullptr;
+    apx_status r = apx_batch_create(ctx, n, refs, L, tmpl, N, params, 0, stream, &b);
+    if (r != APX_OK) return r;
+    r = apx_batch_run(ctx, b, lag_out, val_out, stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    batch_free(b);
+    if (r != APX_OK) return r;
+    if (e != hipSuccess) return fail(APX_E_DEVICE, "%s", hipGetErrorString(e));
+    return APX_OK;
 }
 
 }  // extern "C"

@@ -89,4 +89,22 @@ hipError_t launch_coef32(const double* h, int32_t nh, int32_t M, const double2* 
 int fft_max_logF();
 int fft_min_logF();
 
+// batched cross-correlation matching (kernels.hip)
+struct BatchLaunch {
+    int mode, logW;
+    const RunArgs* targs;   // one per pair
+    const int2* items;      // (pair, block) per item; block P = the prefix item of block 0
+    int32_t nitems, chunk, grid, npairs;
+    unsigned int* counter;
+    unsigned long long* keys;
+    const int32_t* Ngiven;  // taps per pair as given
+    int64_t* lag;
+    float* val;
+    hipStream_t st;
+};
+constexpr int BATCH_LOGW_MIN = 11, BATCH_LOGW_MAX = 14;
+size_t batch_lds_bytes(int mode, int logW);
+hipError_t batch_occupancy(int mode, int logW, int* per_cu);
+hipError_t launch_batch(const BatchLaunch& b);
+
 }  // namespace apx

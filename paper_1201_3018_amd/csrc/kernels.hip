@@ -242,6 +242,42 @@ __device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, dou
     a.out[o] = (float)(inv * rt);  // eq. (16)
 }
 
+// Where the outputs of a block go.  StoreSink writes r_out (and the debug fields); ArgmaxSink
+// keeps, per thread, the largest output seen and its r_out index (ties: smallest index).
+struct StoreSink {
+    __device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double inv) {
+        apx::put(a, it, j, rt, inv);
+    }
+    __device__ __forceinline__ void put32(const RunArgs& a, const Item& it, int j, float v) {
+        const int64_t o = it.o0 + (j - it.j_lo);
+        a.out[o] = v;
+        if (a.fields) a.fields[o] = 0.0;
+    }
+};
+
+// Order-preserving 64-bit key of (value, index): larger value first, then smaller index.
+// -0 counts as +0; NaN never enters.  Key 0 means "no finite output".
+__device__ __forceinline__ unsigned long long argmax_key(float v, int64_t o) {
+    const unsigned int b = __float_as_uint(v + 0.0f);
+    const unsigned int u = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned int)o);
+}
+
+struct ArgmaxSink {
+    unsigned long long best = 0;
+    __device__ __forceinline__ void consider(int64_t o, float v) {
+        if (v != v) return;
+        const unsigned long long k = argmax_key(v, o);
+        best = k > best ? k : best;
+    }
+    __device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double inv) {
+        consider(it.o0 + (j - it.j_lo), (float)(inv * rt));  // eq. (16), as stored by StoreSink
+    }
+    __device__ __forceinline__ void put32(const RunArgs& a, const Item& it, int j, float v) {
+        consider(it.o0 + (j - it.j_lo), v);
+    }
+};
+
 // Companded sample s~[i] of the item's window (eq. 2); zero outside [0, nvalid).
 __device__ __forceinline__ double sq_at(const RunArgs& a, const Item& it, double cs, int i) {
     if (i < 0 || i >= it.nvalid) return 0.0;
@@ -287,8 +323,9 @@ __device__ __forceinline__ SymDigits sym_split(double rb, double two_r, double R
 
 // Decode and store the kept outputs of a symmetric-packed block.  rbar(m) returns the packed
 // result at word m (m >= -1; word -1 is zero).
-template <typename Fn>
-__device__ __forceinline__ void sym_unpack_store(const RunArgs& a, const Item& it, const Choice& c, Fn rbar) {
+template <typename Fn, typename Sink = StoreSink>
+__device__ __forceinline__ void sym_unpack_store(const RunArgs& a, const Item& it, const Choice& c, Fn rbar,
+                                                 Sink&& sk = Sink{}) {
     const double two_r = (double)(2 * c.R), R = (double)c.R;
     const int m_lo = it.j_lo >> 1, m_hi = (it.j_hi + 1) >> 1;
     for (int m = m_lo + threadIdx.x; m < m_hi; m += NT) {
@@ -296,16 +333,17 @@ __device__ __forceinline__ void sym_unpack_store(const RunArgs& a, const Item& i
         const int j0 = 2 * m, j1 = 2 * m + 1;
         if (j0 >= it.j_lo && j0 < it.j_hi) {
             double de_prev = (m >= 1) ? sym_split(rbar(m - 1), two_r, R).De : 0.0;
-            put(a, it, j0, cur.Dm + de_prev, c.inv);
+            sk.put(a, it, j0, cur.Dm + de_prev, c.inv);
         }
-        if (j1 >= it.j_lo && j1 < it.j_hi) put(a, it, j1, cur.B, c.inv);
+        if (j1 >= it.j_lo && j1 < it.j_hi) sk.put(a, it, j1, cur.B, c.inv);
     }
 }
 
 // Asymmetric packing: rb = sum_q eps^q d_q, balanced base-2R digits taken one after the other.
-template <int MM, typename Fn>
+template <int MM, typename Fn, typename Sink = StoreSink>
 __device__ __forceinline__ void asym_unpack_store(const RunArgs& a, const Item& it, const Choice& c, int Tit,
-                                                  int base_off, int m_first0, int m_first, int m_end, Fn rbar) {
+                                                  int base_off, int m_first0, int m_first, int m_end, Fn rbar,
+                                                  Sink&& sk = Sink{}) {
     const double two_r = (double)(2 * c.R);
     for (int m = m_first0 + threadIdx.x; m < m_end; m += NT) {
         double x = rbar(m);
@@ -315,7 +353,7 @@ __device__ __forceinline__ void asym_unpack_store(const RunArgs& a, const Item& 
             x = (x - d) * two_r;
             if (q > 0 && m < m_first) continue;
             const int j = base_off + q * Tit + m;
-            if (j >= it.j_lo && j < it.j_hi) put(a, it, j, d, c.inv);
+            if (j >= it.j_lo && j < it.j_hi) sk.put(a, it, j, d, c.inv);
         }
     }
 }
@@ -490,8 +528,8 @@ hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st) {
 // FFT core
 // ------------------------------------------------------------------------------------------
 // Complex points of the packed FFT for word length F: MW = F / 2.
-template <int MODE, int MW>
-__device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char* lds) {
+template <int MODE, int MW, typename Sink = StoreSink>
+__device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char* lds, Sink&& sk = Sink{}) {
     using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
     using T2 = typename tw_of<T>::type;
     constexpr int F = 2 * MW;
@@ -558,20 +596,16 @@ __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char
         return (m & 1) ? (double)im[m >> 1] : (double)re[m >> 1];
     };
     if constexpr (MODE == MD_FULL32) {
-        for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NT) {
-            const int64_t o = it.o0 + (j - it.j_lo);
-            a.out[o] = (float)word(j);
-            if (a.fields) a.fields[o] = 0.0;
-        }
+        for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NT) sk.put32(a, it, j, (float)word(j));
     } else if constexpr (MODE == MD_SYM) {
-        sym_unpack_store(a, it, c, word);
+        sym_unpack_store(a, it, c, word, sk);
     } else {
         constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
         const bool prefix = it.j_lo == 0;
         const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
         const int base_off = it.j_lo - (N - 1);
         const int lw = Tit + N - 1;
-        asym_unpack_store<MM>(a, it, c, Tit, base_off, N - 1, N - 1, lw, word);
+        asym_unpack_store<MM>(a, it, c, Tit, base_off, N - 1, N - 1, lw, word, sk);
     }
 }
 
@@ -615,6 +649,149 @@ hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st) {
         case 13: hipLaunchKernelGGL(k_fft<13>, g, dim3(NT), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Batched cross-correlation matching: one persistent launch over a work list of (pair, block)
+// items.  Each workgroup takes `chunk` consecutive items at a time from a global counter, runs
+// the FFT core on each (same steps as k_fft, per pair arguments from `targs`) and folds the
+// block's outputs into the pair's argmax key with one atomic max per wave.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long wave_umax64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned int lo = __shfl_xor((unsigned int)v, o);
+        const unsigned int hi = __shfl_xor((unsigned int)(v >> 32), o);
+        const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <int MODE, int LOGW>
+__global__ void __launch_bounds__(NT) k_batch(const RunArgs* __restrict__ targs, const int2* __restrict__ items,
+                                              int32_t nitems, int32_t chunk, unsigned int* counter,
+                                              unsigned long long* keys) {
+    constexpr int MW = 1 << (LOGW - 1);  // complex points: 2^LOGW packed words
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    __shared__ int grab;
+    for (;;) {
+        __syncthreads();  // everyone has read `grab` and is done with the LDS
+        if (threadIdx.x == 0) grab = (int)atomicAdd(counter, (unsigned int)chunk);
+        __syncthreads();
+        const int base = __builtin_amdgcn_readfirstlane(grab);
+        if (base >= nitems) break;
+        const int end = min(base + chunk, nitems);
+        for (int idx = base; idx < end; ++idx) {
+            const int2 ti = items[idx];
+            const int t = __builtin_amdgcn_readfirstlane(ti.x);
+            const int w = __builtin_amdgcn_readfirstlane(ti.y);
+            const RunArgs& a = targs[t];
+            ArgmaxSink sk;
+            const Item it = make_item(a, w, true);
+            const BlockStats st = block_stats(a.s, it.start, it.nwin);
+            const Choice c = choose(a, st);
+            if (!(c.flags & APX_FLAG_NONFINITE) && it.j_hi > it.j_lo) {
+                if ((c.flags & APX_FLAG_ZERO) && MODE != MD_FULL32)
+                    sk.consider(it.o0, 0.0f);  // all outputs of the block are zero
+                else
+                    fft_item<MODE, MW>(a, it, c, lds, sk);
+            }
+            const unsigned long long k = wave_umax64(sk.best);
+            if ((threadIdx.x & 63) == 0 && k != 0) atomicMax(&keys[t], k);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_batch_init(unsigned int* counter, unsigned long long* keys, int32_t n) {
+    const int i = blockIdx.x * NT + threadIdx.x;
+    if (i == 0) *counter = 0u;
+    if (i < n) keys[i] = 0ull;
+}
+
+// keys -> (lag, value); lag = r_out index - (N - 1).  No finite output: lag INT64_MIN, value NaN.
+__global__ void __launch_bounds__(NT) k_batch_final(const unsigned long long* __restrict__ keys,
+                                                    const int32_t* __restrict__ Ngiven, int32_t n, int64_t* lag,
+                                                    float* val) {
+    const int i = blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long k = keys[i];
+    if (k == 0ull) {
+        lag[i] = INT64_MIN;
+        val[i] = NAN;
+        return;
+    }
+    const unsigned int u = (unsigned int)(k >> 32);
+    const unsigned int o = 0xFFFFFFFFu - (unsigned int)(k & 0xFFFFFFFFull);
+    const unsigned int b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    lag[i] = (int64_t)o - (int64_t)(Ngiven[i] - 1);
+    val[i] = __uint_as_float(b);
+}
+
+size_t batch_lds_bytes(int mode, int logW) {
+    const size_t esz = mode == MD_FULL32 ? sizeof(float) : sizeof(double);
+    return ((size_t)1 << logW) * esz;  // 2^(LOGW-1) complex points
+}
+
+namespace {
+template <int MODE, int LOGW>
+hipError_t batch_one(const BatchLaunch& b, bool query, int* per_cu) {
+    auto kern = k_batch<MODE, LOGW>;
+    const size_t lds = batch_lds_bytes(MODE, LOGW);
+    if (query) {
+        // sets the LDS limit once, before any launch (launches may be captured into a graph)
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, NT, lds);
+    }
+    hipLaunchKernelGGL(kern, dim3(b.grid), dim3(NT), lds, b.st, b.targs, b.items, b.nitems, b.chunk, b.counter,
+                       b.keys);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t batch_mode(const BatchLaunch& b, bool query, int* per_cu) {
+    switch (b.logW) {
+        case 11: return batch_one<MODE, 11>(b, query, per_cu);
+        case 12: return batch_one<MODE, 12>(b, query, per_cu);
+        case 13: return batch_one<MODE, 13>(b, query, per_cu);
+        case 14: return batch_one<MODE, 14>(b, query, per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_dispatch(const BatchLaunch& b, bool query, int* per_cu) {
+    switch (b.mode) {
+        case MD_FULL32: return batch_mode<MD_FULL32>(b, query, per_cu);
+        case MD_SYM: return batch_mode<MD_SYM>(b, query, per_cu);
+        case MD_ASYM2: return batch_mode<MD_ASYM2>(b, query, per_cu);
+        case MD_ASYM3: return batch_mode<MD_ASYM3>(b, query, per_cu);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t batch_occupancy(int mode, int logW, int* per_cu) {
+    BatchLaunch b{};
+    b.mode = mode;
+    b.logW = logW;
+    return batch_dispatch(b, true, per_cu);
+}
+
+hipError_t launch_batch(const BatchLaunch& b) {
+    const int nb = (b.npairs + NT - 1) / NT;
+    hipLaunchKernelGGL(k_batch_init, dim3(nb > 0 ? nb : 1), dim3(NT), 0, b.st, b.counter, b.keys, b.npairs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (b.nitems > 0) {
+        e = batch_dispatch(b, false, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_batch_final, dim3(nb > 0 ? nb : 1), dim3(NT), 0, b.st, b.keys, b.Ngiven, b.npairs, b.lag,
+                       b.val);
     return hipGetLastError();
 }
 
@@ -690,7 +867,9 @@ template <typename T, int MW>
 __global__ void __launch_bounds__(NT) k_spectrum(const T* __restrict__ taps, int32_t ntaps,
                                                  const typename tw_of<T>::type* tw,
                                                  typename tw_of<T>::type* spec) {
-    __shared__ T re[MW], im[MW];
+    extern __shared__ __attribute__((aligned(16))) char sp_lds[];
+    T* re = (T*)sp_lds;
+    T* im = re + MW;
     for (int n = threadIdx.x; n < MW; n += NT) {
         re[n] = (2 * n < ntaps) ? taps[2 * n] : (T)0;
         im[n] = (2 * n + 1 < ntaps) ? taps[2 * n + 1] : (T)0;
@@ -700,34 +879,40 @@ __global__ void __launch_bounds__(NT) k_spectrum(const T* __restrict__ taps, int
     real_spectrum_out<T, MW>(re, im, tw, spec);
 }
 
-hipError_t launch_spectrum(const double* taps, int32_t ntaps, int32_t Fw, const double2* twd, double2* spec,
-                           hipStream_t st) {
-    const double2* tw = twd + Fw;
+template <typename T, int MW>
+hipError_t spectrum_one(const T* taps, int32_t ntaps, const typename tw_of<T>::type* tw,
+                        typename tw_of<T>::type* spec, hipStream_t st) {
+    auto kern = k_spectrum<T, MW>;
+    const size_t lds = 2 * (size_t)MW * sizeof(T);
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(NT), lds, st, taps, ntaps, tw, spec);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spectrum_any(const T* taps, int32_t ntaps, int32_t Fw, const typename tw_of<T>::type* tw,
+                        typename tw_of<T>::type* spec, hipStream_t st) {
     switch (Fw) {
-        case 256: hipLaunchKernelGGL((k_spectrum<double, 128>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 512: hipLaunchKernelGGL((k_spectrum<double, 256>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 1024: hipLaunchKernelGGL((k_spectrum<double, 512>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 2048: hipLaunchKernelGGL((k_spectrum<double, 1024>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 4096: hipLaunchKernelGGL((k_spectrum<double, 2048>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 8192: hipLaunchKernelGGL((k_spectrum<double, 4096>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
+        case 256: return spectrum_one<T, 128>(taps, ntaps, tw, spec, st);
+        case 512: return spectrum_one<T, 256>(taps, ntaps, tw, spec, st);
+        case 1024: return spectrum_one<T, 512>(taps, ntaps, tw, spec, st);
+        case 2048: return spectrum_one<T, 1024>(taps, ntaps, tw, spec, st);
+        case 4096: return spectrum_one<T, 2048>(taps, ntaps, tw, spec, st);
+        case 8192: return spectrum_one<T, 4096>(taps, ntaps, tw, spec, st);
+        case 16384: return spectrum_one<T, 8192>(taps, ntaps, tw, spec, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+hipError_t launch_spectrum(const double* taps, int32_t ntaps, int32_t Fw, const double2* twd, double2* spec,
+                           hipStream_t st) {
+    return spectrum_any<double>(taps, ntaps, Fw, twd + Fw, spec, st);
 }
 
 hipError_t launch_spectrum32(const float* taps, int32_t ntaps, int32_t Fw, const float2* twf, float2* spec,
                              hipStream_t st) {
-    const float2* tw = twf + Fw;
-    switch (Fw) {
-        case 256: hipLaunchKernelGGL((k_spectrum<float, 128>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 512: hipLaunchKernelGGL((k_spectrum<float, 256>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 1024: hipLaunchKernelGGL((k_spectrum<float, 512>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 2048: hipLaunchKernelGGL((k_spectrum<float, 1024>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 4096: hipLaunchKernelGGL((k_spectrum<float, 2048>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        case 8192: hipLaunchKernelGGL((k_spectrum<float, 4096>), dim3(1), dim3(NT), 0, st, taps, ntaps, tw, spec); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return spectrum_any<float>(taps, ntaps, Fw, twf + Fw, spec, st);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -1,0 +1,201 @@
+"""Batched cross-correlation matching (apx_batch_*) through the C ABI against the oracle.
+
+Each pair's correlation is the blocked companded convolution with the time-reversed template
+(oracle.xcorr_blocked, at the pair's W_block that the batch reports); its argmax is taken over
+the FP32 outputs, ties to the smallest lag.
+Packed modes: the FP32 outputs are bit-exact against the oracle (see test_gpu_parity), so the
+lag and the value must be identical.
+FP32 mode: the GPU lag must be a maximiser within the FP32 error bound of the FFT core, and its
+value must be the FP64 value at that lag within the same bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1201_3018_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1201_3018_amd import apx  # noqa: E402
+
+DEV = torch.device("cuda:0")
+MODES = {O.SYM: apx.APX_SYM, O.ASYM2: apx.APX_ASYM2, O.ASYM3: apx.APX_ASYM3, O.FULL: apx.APX_FULL_FP32}
+INT64_MIN = -(1 << 63)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = apx.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _small_pairs():
+    refs, tmpls, _, offs = synth.xcorr_batch(n_templates=10, n_refs=4, seed_refs=31, seed_t=32,
+                                             ref_len=(8192, 32768), tmpl_len=(8, 160))
+    refs = [refs[i % 4] for i in range(10)]
+    rng = np.random.default_rng(33)
+    # edge cases: template as long as its reference, a zero template, a NaN in the reference
+    r_eq = rng.standard_normal(301).astype(np.float32)
+    refs.append(r_eq)
+    tmpls.append(r_eq.copy())
+    refs.append(rng.standard_normal(5000).astype(np.float32))
+    tmpls.append(np.zeros(40, np.float32))
+    r_nan = rng.standard_normal(9000).astype(np.float32)
+    r_nan[4000] = np.nan
+    refs.append(r_nan)
+    tmpls.append(rng.standard_normal(33).astype(np.float32))
+    r_all_nan = np.full(700, np.nan, np.float32)
+    refs.append(r_all_nan)
+    tmpls.append(rng.standard_normal(16).astype(np.float32))
+    return refs, tmpls
+
+
+def _fp32_tol(ref, k, logW):
+    u = 2.0 ** -24
+    r = np.nan_to_num(ref.astype(np.float64), nan=0.0, posinf=0.0, neginf=0.0)
+    return 16.0 * (logW + 1) * u * float(np.linalg.norm(r)) * float(
+        np.linalg.norm(k.astype(np.float64))) + 1e-30
+
+
+def _check_pair(ref, k, Wb, mode, lag, val, logW):
+    N = len(k)
+    if mode == O.FULL:
+        c = O.xcorr_blocked(ref, k, int(Wb), O.FULL, out_dtype=np.float64)
+        ok = ~np.isnan(c)
+        if not ok.any():
+            assert lag == INT64_MIN and math.isnan(val)
+            return
+        tol = _fp32_tol(ref, k, logW)
+        cmax = float(np.max(c[ok]))
+        i = lag + N - 1
+        assert 0 <= i < c.size and not math.isnan(c[i])
+        assert c[i] >= cmax - 2 * tol, (lag, c[i], cmax, tol)
+        assert abs(val - c[i]) <= tol, (val, c[i], tol)
+    else:
+        c = O.xcorr_blocked(ref, k, int(Wb), mode)
+        l_ref, v_ref = O.argmax_lag_finite(c, N)
+        if l_ref is None:
+            assert lag == INT64_MIN and math.isnan(val)
+            return
+        assert lag == l_ref, (lag, l_ref)
+        assert np.float32(val) == np.float32(v_ref), (val, v_ref)
+
+
+@pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3, O.FULL])
+@pytest.mark.parametrize("logW", [11, 12])
+def test_batch_small(ctx, mode, logW):
+    refs, tmpls = _small_pairs()
+    _say(f"batch small mode={mode} logW={logW} pairs={len(refs)}")
+    b = apx.Batch(ctx, [_dev(r) for r in refs], [_dev(k) for k in tmpls], mode=MODES[mode], logW=logW)
+    lag, val = b.run()
+    torch.cuda.synchronize()
+    wb, lw, nitems = b.blocks()
+    assert lw == logW
+    lag, val = lag.cpu().numpy(), val.cpu().numpy()
+    for i in range(len(refs)):
+        _check_pair(refs[i], tmpls[i], wb[i], mode, int(lag[i]), float(val[i]), logW)
+    b.close()
+
+
+def test_batch_autotune_and_graph(ctx):
+    refs, tmpls = _small_pairs()
+    tr, tk = [_dev(r) for r in refs], [_dev(k) for k in tmpls]
+    b = apx.Batch(ctx, tr, tk, mode=apx.APX_ASYM2, logW=0)
+    desc = b.describe()
+    _say("autotuned:", desc)
+    assert "tune=[" in desc and "chunk=" in desc
+    wb, lw, _ = b.blocks()
+    lag0, val0 = b.run()
+    torch.cuda.synchronize()
+    lag0c, val0c = lag0.cpu().numpy(), val0.cpu().numpy()
+    for i in range(len(refs)):
+        _check_pair(refs[i], tmpls[i], wb[i], O.ASYM2, int(lag0c[i]), float(val0c[i]), lw)
+    # graph capture of the run: replays must reproduce the eager result
+    lag = torch.empty_like(lag0)
+    val = torch.empty_like(val0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            b.run(lag, val, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        lag.fill_(7)
+        val.fill_(7.0)
+        _ = torch.ones(1000, device=DEV).sum()  # unrelated eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(lag, lag0), rep
+        assert torch.equal(val.view(torch.int32), val0.view(torch.int32)), rep
+    b.close()
+
+
+def test_batch_oneshot_and_errors(ctx):
+    refs, tmpls = _small_pairs()
+    tr, tk = [_dev(r) for r in refs[:6]], [_dev(k) for k in tmpls[:6]]
+    lag = torch.empty(6, dtype=torch.int64, device=DEV)
+    val = torch.empty(6, dtype=torch.float32, device=DEV)
+    prm = apx.params(apx.APX_SYM, apx.APX_CORE_FFT)
+    apx.apx_xcorr_argmax_batch(ctx.h, tr, tk, prm, lag, val)
+    b = apx.Batch(ctx, tr, tk, mode=apx.APX_SYM, logW=0)
+    lag2, val2 = b.run()
+    torch.cuda.synchronize()
+    assert torch.equal(lag, lag2) and torch.equal(val, val2)
+    b.close()
+    with pytest.raises(apx.ApxError) as e:
+        apx.Batch(ctx, tr, tk, mode=apx.APX_AUTO_SNR)
+    assert e.value.status == apx.APX_E_UNSUPPORTED
+    with pytest.raises(apx.ApxError) as e:
+        apx.Batch(ctx, tr, tk, mode=apx.APX_SYM, logW=9)
+    assert e.value.status == apx.APX_E_INVALID
+    # a template longer than its reference
+    with pytest.raises(apx.ApxError) as e:
+        apx.Batch(ctx, [_dev(np.ones(10))], [_dev(np.ones(20))], mode=apx.APX_SYM)
+    assert e.value.status == apx.APX_E_INVALID
+    # a template too long for every FFT length
+    with pytest.raises(apx.ApxError) as e:
+        apx.Batch(ctx, [_dev(np.ones(100000))], [_dev(np.ones(6000))], mode=apx.APX_FULL_FP32, logW=0)
+    assert e.value.status == apx.APX_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.FULL])
+def test_batch_full_size(ctx, mode):
+    """4096 templates (256..4096 taps) against their 64 references (2^18..2^20 samples):
+    sampled pairs against the oracle, every pair against the true offset (reported)."""
+    refs, tmpls, ridx, offs = synth.xcorr_batch()
+    tr = [_dev(r) for r in refs]
+    pr = [tr[j] for j in ridx]
+    pk = [_dev(k) for k in tmpls]
+    _say(f"batch full size mode={mode}: {len(pk)} pairs")
+    b = apx.Batch(ctx, pr, pk, mode=MODES[mode], logW=0)
+    _say(b.describe())
+    lag, val = b.run()
+    torch.cuda.synchronize()
+    wb, lw, nitems = b.blocks()
+    lag, val = lag.cpu().numpy(), val.cpu().numpy()
+    hit = float(np.mean(lag == offs))
+    _say(f"true-offset agreement {hit:.4f} (items {nitems}, logW {lw})")
+    rng = np.random.default_rng(77)
+    sample = rng.choice(len(tmpls), 4, replace=False)
+    sample = np.concatenate([sample, [int(np.argmax([k.size for k in tmpls]))]])
+    for i in sample:
+        _say(f"  oracle pair {i}: L={refs[ridx[i]].size} N={tmpls[i].size} W_block={wb[i]}")
+        _check_pair(refs[ridx[i]], tmpls[i], wb[i], mode, int(lag[i]), float(val[i]), lw)
+    assert hit > 0.5
+    b.close()
