@@ -30,6 +30,10 @@ WORKLOADS = {
     "c2": dict(L=1 << 22, N=1024, Wb=4096, snr=40.0, core="fft",
                name="FFT overlap-save convolution: L=2^22 AR(1) audio, N=1024 Hann low-pass, "
                     "W_block=4096, per-block packing for SNR>=40 dB"),
+    "c3": dict(name="batched cross-correlation matching: 4096 templates (256..4096 taps, excerpts + 20 dB noise) "
+                    "against their 64 AR(1) references (2^18..2^20 samples), one persistent launch, autotuned"),
+    "c4": dict(name="filter bank: 256 channels x 2^20 pink-noise samples, 32 Hann band-pass FIRs of N=512, "
+                    "split-precision FP16 matrix cores (three products, FP32 accumulation)"),
     "c1": dict(L=65536, N=64, Wb=1024, snr=None, core="td",
                name="time-domain overlap-save convolution: L=65536 N(0,1), N=64 U(-1,1), W_block=1024, "
                     "asymmetric M=2 at 8 bits (S_q=K_q=127)"),
@@ -64,6 +68,10 @@ def main():
     from paper_1201_3018_amd import apx, synth
 
     wl = WORKLOADS[args.workload]
+    if args.workload == "c3":
+        return bench_c3(args, wl)
+    if args.workload == "c4":
+        return bench_c4(args, wl)
     dev = torch.device("cuda:0")
     L, N, Wb = wl["L"], wl["N"], wl["Wb"]
     if args.workload == "c2":
@@ -212,6 +220,215 @@ def main():
     print(json.dumps(res), flush=True)
     for kh in {id(x): x for x in (kern, full, ref64)}.values():
         kh.close()
+    ctx.close()
+
+
+def bench_c3(args, wl):
+    """Batched matching: one step = one run of the whole batch (every pair's correlation at every
+    lag and its argmax).  value = correlation lags per second, symmetric packing at the largest
+    S_q = K_q; asymmetric M=2 and FP32 timed the same way beside it."""
+    import torch
+
+    from paper_1201_3018_amd import apx, synth
+    dev = torch.device("cuda:0")
+    refs, tmpls, ridx, offs = synth.xcorr_batch()
+    tr = [torch.from_numpy(r).to(dev) for r in refs]
+    pr = [tr[j] for j in ridx]
+    pk = [torch.from_numpy(k).to(dev) for k in tmpls]
+    lags_total = int(sum(refs[j].size + k.size - 1 for j, k in zip(ridx, tmpls)))
+    ctx = apx.Context(0)
+    res_modes = {}
+    steps = max(1, min(args.steps, 20))
+    warm = max(1, min(args.warmup, 3))
+    for name, mode in (("sym", apx.APX_SYM), ("asym2", apx.APX_ASYM2), ("full_fp32", apx.APX_FULL_FP32)):
+        b = apx.Batch(ctx, pr, pk, mode=mode, logW=0)
+        lag = torch.empty(len(pk), dtype=torch.int64, device=dev)
+        val = torch.empty(len(pk), dtype=torch.float32, device=dev)
+        for _ in range(warm):
+            b.run(lag, val)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(steps):
+                    b.run(lag, val, stream=s)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        wb, lw, nitems = b.blocks()
+        lg = lag.cpu().numpy()
+        # algorithmic work: every window read once, per item one forward and one inverse FFT
+        P = [-(-refs[j].size // (int(w) - (k.size | 1) - 1)) for j, k, w in zip(ridx, tmpls, wb)]
+        bytes_alg = sum(4 * p * int(w) for p, w in zip(P, wb))
+        fl = nitems * fft_flops_per_item(1 << lw)
+        res_modes[name] = {"ms_per_step": ms, "lags_per_s": lags_total / (ms * 1e-3), "logW": lw,
+                           "items": nitems, "true_offset_agreement": float(np.mean(lg == offs)),
+                           "bytes_per_launch": bytes_alg, "flops_per_launch": fl,
+                           "hbm_GBs": bytes_alg / (ms * 1e-3) / 1e9,
+                           "alu_TFLOPs": fl / (ms * 1e-3) / 1e12, "kernel": b.describe().split(" tune=")[0]}
+        b.close()
+    head = res_modes["sym"]
+    peak = FP64_VECTOR_TFLOPS
+    alu_frac = head["alu_TFLOPs"] / peak
+    hbm_frac = head["hbm_GBs"] / HBM_PEAK_GBS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": round(head["alu_TFLOPs"], 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(alu_frac, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(head["hbm_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    roof["traffic"] = None
+    roof["kernel"] = head["kernel"]
+    res = {
+        "metric": "correlation lags/s of batched matching (argmax per template), packed vs FP32, 1 GPU",
+        "value": head["lags_per_s"], "unit": "lags/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "pairs": len(pk), "lags": lags_total},
+        "roofline": roof, "modes": res_modes,
+        "packed_over_fp32": res_modes["full_fp32"]["ms_per_step"] / head["ms_per_step"],
+    }
+    if not args.no_cpu:
+        import oracle as O
+        t0 = time.perf_counter()
+        done = 0
+        i = 0
+        wb_sym = None
+        b = apx.Batch(ctx, pr, pk, mode=apx.APX_SYM, logW=head["logW"])
+        wb_sym = b.blocks()[0]
+        b.close()
+        while time.perf_counter() - t0 < 15.0 and i < len(pk):
+            c = O.xcorr_blocked(refs[ridx[i]], tmpls[i], int(wb_sym[i]), O.SYM)
+            O.argmax_lag_finite(c, tmpls[i].size)
+            done += c.size
+            i += 1
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": done / dt, "unit": "lags/s", "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"first {i} of {len(pk)} pairs ({done} lags), symmetric blocks + argmax, "
+                                         f"{dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+MFMA_F16_TFLOPS = 2500.0    # MI355X dense FP16 / BF16 matrix peak
+
+
+def bench_c4(args, wl):
+    """Filter bank: one step = the whole bank (256 x 32 output rows of 2^20 + 511 samples).
+    value = output samples/s of the FP16 split path; BF16 split and the FP32 vector path (the
+    time-domain FP32 core, one channel timed and scaled by the channel count) beside it, with
+    the error against FP64 per channel on sampled outputs."""
+    import torch
+
+    import oracle as O
+    from paper_1201_3018_amd import apx, synth
+    dev = torch.device("cuda:0")
+    C, L, F, N = 256, 1 << 20, 32, 512
+    Lout = L + N - 1
+    ldy = (Lout + 63) // 64 * 64
+    x = synth.pink_noise(C, L, 4001)
+    h = synth.bandpass_bank(F, N)
+    xd = torch.from_numpy(x).to(dev)
+    hd = torch.from_numpy(h).to(dev)
+    y = torch.empty(C * F, ldy, dtype=torch.float32, device=dev)
+    ctx = apx.Context(0)
+    steps = max(1, min(args.steps, 10))
+    rng = np.random.default_rng(11)
+    chans = rng.choice(C, 8, replace=False)
+    ts = rng.integers(0, Lout, 4096)
+    xs = {c: np.concatenate([np.zeros(N - 1), x[c].astype(np.float64), np.zeros(N - 1)]) for c in chans}
+    ref = {c: xs[c][ts[:, None] + np.arange(N)[None, :]] @ h.astype(np.float64)[:, ::-1].T for c in chans}
+
+    def chan_snr(get):
+        out = []
+        for c in chans:
+            g = get(c)
+            e = np.sum((g - ref[c]) ** 2)
+            out.append(float("inf") if e == 0 else 10 * math.log10(float(np.sum(ref[c] ** 2)) / e))
+        return out
+
+    tsd = torch.from_numpy(ts).to(dev)
+    modes = {}
+    for name, prec in (("f16x3", apx.APX_FB_F16X3), ("bf16x3", apx.APX_FB_BF16X3)):
+        fb = apx.FilterBank(ctx, hd, prec)
+        fb.run(xd, y=y, L=L)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fb.run(xd, y=y, L=L)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        yv = y.view(C, F, ldy)
+        snr = chan_snr(lambda c: yv[int(c)][:, tsd].cpu().numpy().T.astype(np.float64))
+        modes[name] = {"ms_per_step": ms, "samples_per_s": C * F * Lout / (ms * 1e-3),
+                       "snr_db_per_channel": [round(v, 1) for v in snr], "kernel": fb.describe()}
+        fb.close()
+    # FP32 vector path: the FP32 time-domain core, filter by filter, one channel timed
+    Wb = 2048
+    kerns = [apx.Kernel(ctx, hd[f].contiguous(), Wb, mode=apx.APX_FULL_FP32, core=apx.APX_CORE_TIME) for f in range(F)]
+    outs = [torch.empty(Lout, dtype=torch.float32, device=dev) for _ in range(F)]
+    for f in range(F):
+        kerns[f].run(xd[0], out=outs[f])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for f in range(F):
+        kerns[f].run(xd[0], out=outs[f])
+    e1.record()
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) * C
+
+    def fp32_get(c):
+        g = np.empty((ts.size, F))
+        for f in range(F):
+            kerns[f].run(xd[int(c)], out=outs[f])
+            g[:, f] = outs[f][tsd].cpu().numpy()
+        return g
+    snr32 = chan_snr(fp32_get)
+    modes["fp32_vector"] = {"ms_per_step": ms32, "samples_per_s": C * F * Lout / (ms32 * 1e-3),
+                            "snr_db_per_channel": [round(v, 1) for v in snr32],
+                            "kernel": kerns[0].describe() + " (one channel timed, x256)"}
+    for kk in kerns:
+        kk.close()
+    head = modes["f16x3"]
+    flops = 3 * 2.0 * 512 * 32 * Lout * C                 # executed MFMA work (three products)
+    bytes_alg = C * F * Lout * 4 + C * L * 4               # outputs written once + inputs read once
+    ach = flops / (head["ms_per_step"] * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(ach, 1), "peak": MFMA_F16_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / MFMA_F16_TFLOPS, 4), "traffic": None,
+            "hbm_GBs": round(bytes_alg / (head["ms_per_step"] * 1e-3) / 1e9, 1), "kernel": head["kernel"],
+            "flops_per_launch": flops, "bytes_per_launch": bytes_alg}
+    res = {
+        "metric": "filter-bank output samples/s, split-precision FP16 matrix cores vs FP32 vector path, 1 GPU",
+        "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16x3", "data": "synthetic",
+        "config": {"workload": wl["name"], "channels": C, "L": L, "filters": F, "N": N},
+        "roofline": roof, "modes": modes,
+        "speedup_over_fp32_vector": ms32 / head["ms_per_step"],
+    }
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        n = 0
+        f = 0
+        while time.perf_counter() - t0 < 10.0 and f < F:
+            O.conv_direct(x[0], h[f])
+            n += Lout
+            f += 1
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": n / dt, "unit": "samples/s", "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"channel 0 x {f} filters ({n} outputs), FP64 direct convolution, "
+                                         f"{dt:.1f} s"}
+    print(json.dumps(res), flush=True)
     ctx.close()
 
 

@@ -172,6 +172,28 @@ apx_status apx_xcorr_argmax_batch(apx_ctx ctx, int32_t n, const float* const* re
                                   const float* const* tmpl, const int32_t* N, const apx_params* params,
                                   int64_t* lag_out, float* val_out, void* stream);
 
+/* ---- Filter bank on split-precision matrix cores (the full-precision comparator) ----------------
+ * y[(c F + f) ldy + t] = sum_n x[c ldx + t - n] h[f N + n], t in [0, L + N - 1): the direct
+ * convolution of eq. (1) for C channels and F filters, computed as a Hankel-form GEMM on
+ * half-precision MFMA with FP32 accumulation.  Every sample and tap is split into a high and a
+ * low half-precision part and three products (hi*hi, hi*lo, lo*hi) are accumulated:
+ *   APX_FB_F16X3  FP16 parts, lo = fp16(2^12 (v - hi)) (accurate to about 2^-21 per product;
+ *                 |x| and |h| must stay below 32768),
+ *   APX_FB_BF16X3 BF16 parts, lo = bf16(v - hi) (about 2^-16 per product, any FP32 range).
+ * apx_fbank_create: h (device, F x N FP32, row-major), 1 <= F <= 32, 1 <= N <= 512.  Copies the
+ *   taps into split fragments owned by the handle.  Enqueued on `stream`.
+ * apx_fbank_run: x (device, C rows of ldx >= L floats), y (device, C F rows of ldy >= L + N - 1
+ *   floats, not overlapping x).  One persistent launch; allocates nothing.  Enqueued on `stream`.
+ * apx_fbank_describe (host only): kernel and launch shape as text. */
+typedef enum { APX_FB_F16X3 = 0, APX_FB_BF16X3 = 1 } apx_fb_prec;
+typedef struct apx_fbank_s* apx_fbank;
+apx_status apx_fbank_create(apx_ctx ctx, const float* h, int32_t F, int32_t N, int32_t prec, void* stream,
+                            apx_fbank* out);
+apx_status apx_fbank_run(apx_ctx ctx, apx_fbank fb, const float* x, int32_t C, int64_t L, int64_t ldx, float* y,
+                         int64_t ldy, void* stream);
+apx_status apx_fbank_describe(apx_fbank fb, char* buf, int32_t size);
+apx_status apx_fbank_destroy(apx_fbank fb);
+
 const char* apx_status_str(apx_status st);
 const char* apx_last_error(void);
 

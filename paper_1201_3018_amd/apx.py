@@ -22,6 +22,7 @@ APX_FULL_FP32, APX_SYM, APX_ASYM2, APX_ASYM3, APX_AUTO_SNR, APX_FULL_FP64 = 0, 1
 APX_CORE_AUTO, APX_CORE_TIME, APX_CORE_FFT = 0, 1, 2
 APX_CONV, APX_XCORR = 0, 1
 APX_FLAG_NONFINITE, APX_FLAG_ZERO = 1, 2
+APX_FB_F16X3, APX_FB_BF16X3 = 0, 1
 
 MODE_NAMES = {APX_FULL_FP32: "full", APX_SYM: "sym", APX_ASYM2: "asym2", APX_ASYM3: "asym3",
               APX_AUTO_SNR: "auto", APX_FULL_FP64: "full64"}
@@ -30,7 +31,8 @@ MODE_NAMES = {APX_FULL_FP32: "full", APX_SYM: "sym", APX_ASYM2: "asym2", APX_ASY
 EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "apx_kernel_destroy", "apx_run",
            "apx_debug_fields", "apx_calibrate", "apx_conv", "apx_xcorr", "apx_kernel_describe", "apx_batch_create",
            "apx_batch_run", "apx_batch_blocks", "apx_batch_describe", "apx_batch_destroy", "apx_xcorr_argmax_batch",
-           "apx_status_str", "apx_last_error")
+           "apx_fbank_create", "apx_fbank_run", "apx_fbank_describe", "apx_fbank_destroy", "apx_status_str",
+           "apx_last_error")
 
 
 class apx_params(ctypes.Structure):
@@ -85,6 +87,10 @@ def lib() -> ctypes.CDLL:
         L.apx_batch_describe.argtypes = [vp, ctypes.c_char_p, i32]
         L.apx_batch_destroy.argtypes = [vp]
         L.apx_xcorr_argmax_batch.argtypes = [vp, i32, pvp, pi64, pvp, pi32, ctypes.POINTER(apx_params), vp, vp, vp]
+        L.apx_fbank_create.argtypes = [vp, vp, i32, i32, i32, vp, pvp]
+        L.apx_fbank_run.argtypes = [vp, vp, vp, i32, i64, i64, vp, i64, vp]
+        L.apx_fbank_describe.argtypes = [vp, ctypes.c_char_p, i32]
+        L.apx_fbank_destroy.argtypes = [vp]
         L.apx_status_str.argtypes = [ctypes.c_int]
         L.apx_status_str.restype = ctypes.c_char_p
         L.apx_last_error.restype = ctypes.c_char_p
@@ -240,6 +246,34 @@ def apx_xcorr_argmax_batch(ctx, refs, tmpls, prm: apx_params, lag_out, val_out, 
                                         _dev_ptr(val_out, "float32"), _stream(stream)))
 
 
+def apx_fbank_create(ctx, h, prec: int = APX_FB_F16X3, stream=None):
+    """h: (F, N) contiguous FP32 device tensor."""
+    if h.dim() != 2:
+        raise ValueError("h must be (F, N)")
+    out = ctypes.c_void_p()
+    _check(lib().apx_fbank_create(ctx, _dev_ptr(h, "float32"), h.shape[0], h.shape[1], prec, _stream(stream),
+                                  ctypes.byref(out)))
+    return out
+
+
+def apx_fbank_run(ctx, fb, x, L: int, y, stream=None):
+    """x: (C, ldx) FP32 device tensor; y: (C * F, ldy) FP32 device tensor."""
+    if x.dim() != 2 or y.dim() != 2:
+        raise ValueError("x must be (C, ldx) and y (C*F, ldy)")
+    _check(lib().apx_fbank_run(ctx, fb, _dev_ptr(x, "float32"), x.shape[0], L, x.shape[1], _dev_ptr(y, "float32"),
+                               y.shape[1], _stream(stream)))
+
+
+def apx_fbank_describe(fb) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().apx_fbank_describe(fb, buf, 512))
+    return buf.value.decode()
+
+
+def apx_fbank_destroy(fb):
+    _check(lib().apx_fbank_destroy(fb))
+
+
 # ------------------------------------------------------------------------------- conveniences
 class Context:
     def __init__(self, device: int = 0):
@@ -346,6 +380,42 @@ class Batch:
     def close(self):
         if self.h:
             apx_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FilterBank:
+    """F <= 32 filters of N <= 512 taps on split-precision matrix cores (see apx_fbank_*)."""
+
+    def __init__(self, ctx: Context, h, prec=APX_FB_F16X3, stream=None):
+        self.ctx = ctx
+        self.F, self.N = int(h.shape[0]), int(h.shape[1])
+        self.h = apx_fbank_create(ctx.h, h, prec, stream)
+
+    def run(self, x, y=None, L: Optional[int] = None, ldy: Optional[int] = None, stream=None):
+        """x: (C, ldx); returns y viewed as (C, F, ldy) with L + N - 1 valid samples per row."""
+        import torch
+        C = x.shape[0]
+        L = x.shape[1] if L is None else L
+        Lout = L + self.N - 1
+        if y is None:
+            ldy = Lout if ldy is None else ldy
+            y = torch.empty(C * self.F, ldy, dtype=torch.float32, device=x.device)
+        y2 = y.view(C * self.F, -1)
+        apx_fbank_run(self.ctx.h, self.h, x, L, y2, stream)
+        return y2.view(C, self.F, -1)
+
+    def describe(self) -> str:
+        return apx_fbank_describe(self.h)
+
+    def close(self):
+        if self.h:
+            apx_fbank_destroy(self.h)
             self.h = None
 
     def __del__(self):

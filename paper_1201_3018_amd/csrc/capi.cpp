@@ -973,3 +973,96 @@ apx_status apx_xcorr_argmax_batch(apx_ctx ctx, int32_t n, const float* const* re
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Filter bank on split-precision matrix cores
+// ------------------------------------------------------------------------------------------
+struct apx_fbank_s {
+    apx_ctx ctx = nullptr;
+    int32_t F = 0, N = 0, KS = 0, prec = 0;
+    int per_cu = 0, cus = 0;
+    void* frag = nullptr;
+};
+
+extern "C" {
+
+apx_status apx_fbank_create(apx_ctx ctx, const float* h, int32_t F, int32_t N, int32_t prec, void* stream,
+                            apx_fbank* out) {
+    if (!out) return fail(APX_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (!ctx || !h) return fail(APX_E_INVALID, "null argument");
+    if (F < 1 || F > 32) return fail(APX_E_INVALID, "F = %d filters: one bank holds 1..32", F);
+    if (N < 1) return fail(APX_E_INVALID, "N = %d taps", N);
+    if (prec != APX_FB_F16X3 && prec != APX_FB_BF16X3) return fail(APX_E_INVALID, "unknown precision %d", prec);
+    const int KS = fb_ks_for(N);
+    if (KS == 0) return fail(APX_E_UNSUPPORTED, "N = %d taps: the matrix-core bank takes N <= 512", N);
+    HIPCHK(hipSetDevice(ctx->device));
+    apx_fbank fb = new (std::nothrow) apx_fbank_s;
+    if (!fb) return fail(APX_E_NOMEM, "host allocation failed");
+    fb->ctx = ctx;
+    fb->F = F;
+    fb->N = N;
+    fb->KS = KS;
+    fb->prec = prec;
+    const size_t bytes = (size_t)2 * KS * 64 * 16;
+    if (hipMalloc(&fb->frag, bytes) != hipSuccess) {
+        delete fb;
+        return fail(APX_E_NOMEM, "tap fragments");
+    }
+    hipError_t e = fb_prepare(h, F, N, KS, prec, fb->frag, (hipStream_t)stream);
+    if (e == hipSuccess) e = fb_occupancy(prec, KS, &fb->per_cu);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&fb->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e != hipSuccess || fb->per_cu < 1) {
+        (void)hipFree(fb->frag);
+        delete fb;
+        return fail(APX_E_DEVICE, "filter bank setup: %s", hipGetErrorString(e));
+    }
+    *out = fb;
+    return APX_OK;
+}
+
+apx_status apx_fbank_run(apx_ctx ctx, apx_fbank fb, const float* x, int32_t C, int64_t L, int64_t ldx, float* y,
+                         int64_t ldy, void* stream) {
+    if (!ctx || !fb || !x || !y) return fail(APX_E_INVALID, "null argument");
+    if (fb->ctx != ctx) return fail(APX_E_INVALID, "bank belongs to another context");
+    if (C < 1 || L < 1) return fail(APX_E_INVALID, "C = %d, L = %lld", C, (long long)L);
+    if (ldx < L) return fail(APX_E_INVALID, "ldx = %lld < L", (long long)ldx);
+    const int64_t Lout = L + fb->N - 1;
+    if (ldy < Lout) return fail(APX_E_INVALID, "ldy = %lld < L + N - 1 = %lld", (long long)ldy, (long long)Lout);
+    HIPCHK(hipSetDevice(ctx->device));
+    FbLaunch b{};
+    b.prec = fb->prec;
+    b.KS = fb->KS;
+    b.x = x;
+    b.C = C;
+    b.L = L;
+    b.ldx = ldx;
+    b.frag = fb->frag;
+    b.F = fb->F;
+    b.Lout = Lout;
+    b.y = y;
+    b.ldy = ldy;
+    const int64_t items = (int64_t)C * ((Lout + fb_tile_rows() - 1) / fb_tile_rows());
+    b.grid = (int)std::min<int64_t>((int64_t)fb->per_cu * fb->cus, items);
+    b.st = (hipStream_t)stream;
+    HIPCHK(fb_launch(b));
+    return APX_OK;
+}
+
+apx_status apx_fbank_describe(apx_fbank fb, char* buf, int32_t size) {
+    if (!fb || !buf || size < 1) return fail(APX_E_INVALID, "null argument");
+    snprintf(buf, size, "kernel=k_fbank<%d,%d,%d> F=%d N=%d taps_padded=%d tile_rows=%lld wg_per_cu=%d grid=%d",
+             fb->prec, fb->KS, FB_WAVES, fb->F, fb->N, 16 * fb->KS, (long long)fb_tile_rows(), fb->per_cu,
+             fb->per_cu * fb->cus);
+    return APX_OK;
+}
+
+apx_status apx_fbank_destroy(apx_fbank fb) {
+    if (!fb) return APX_OK;
+    (void)hipSetDevice(fb->ctx->device);
+    if (fb->frag) (void)hipFree(fb->frag);
+    delete fb;
+    return APX_OK;
+}
+
+}  // extern "C"

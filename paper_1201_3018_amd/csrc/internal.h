@@ -107,4 +107,26 @@ size_t batch_lds_bytes(int mode, int logW);
 hipError_t batch_occupancy(int mode, int logW, int* per_cu);
 hipError_t launch_batch(const BatchLaunch& b);
 
+// filter bank on split-precision MFMA (fbank.hip)
+enum { FB_F16X3 = 0, FB_BF16X3 = 1 };
+constexpr int FB_WAVES = 8;  // waves per workgroup; 128 outputs per wave and tile
+struct FbLaunch {
+    int prec, KS;           // precision, k-steps of 16 taps (padded taps = 16 KS)
+    const float* x;
+    int32_t C;
+    int64_t L, ldx;
+    const void* frag;       // split tap fragments (fb_prepare)
+    int32_t F;
+    int64_t Lout;           // L + N - 1
+    float* y;
+    int64_t ldy;
+    int grid;
+    hipStream_t st;
+};
+int fb_ks_for(int N);
+int64_t fb_tile_rows();
+hipError_t fb_prepare(const float* h, int32_t F, int32_t N, int32_t KS, int32_t prec, void* frag, hipStream_t st);
+hipError_t fb_occupancy(int32_t prec, int32_t KS, int* per_cu);
+hipError_t fb_launch(const FbLaunch& b);
+
 }  // namespace apx
