@@ -34,6 +34,9 @@ WORKLOADS = {
                     "against their 64 AR(1) references (2^18..2^20 samples), one persistent launch, autotuned"),
     "c4": dict(name="filter bank: 256 channels x 2^20 pink-noise samples, 32 Hann band-pass FIRs of N=512, "
                     "split-precision FP16 matrix cores (three products, FP32 accumulation)"),
+    "c5": dict(name="serving: Poisson arrivals at 2000 req/s for 10 s, L log-uniform in [2^12, 2^22], N log-uniform "
+                    "in [16, 4096] (32 sizes, 128 kernels per size), SNR target in {30, 40, 50} dB, admission by a "
+                    "32 GiB HBM budget, resident kernels"),
     "c1": dict(L=65536, N=64, Wb=1024, snr=None, core="td",
                name="time-domain overlap-save convolution: L=65536 N(0,1), N=64 U(-1,1), W_block=1024, "
                     "asymmetric M=2 at 8 bits (S_q=K_q=127)"),
@@ -72,6 +75,8 @@ def main():
         return bench_c3(args, wl)
     if args.workload == "c4":
         return bench_c4(args, wl)
+    if args.workload == "c5":
+        return bench_c5(args, wl)
     dev = torch.device("cuda:0")
     L, N, Wb = wl["L"], wl["N"], wl["Wb"]
     if args.workload == "c2":
@@ -430,6 +435,95 @@ def bench_c4(args, wl):
                                          f"{dt:.1f} s"}
     print(json.dumps(res), flush=True)
     ctx.close()
+
+
+def bench_c5(args, wl, duration: float = 10.0, rate: float = 2000.0):
+    """Serving: requests are submitted at their Poisson arrival times to the native server
+    (8 streams, 48 requests in flight, 32 GiB budget); latency = completion time - scheduled
+    arrival (client lag and waits for a free output buffer included).  Inputs are prefixes of 8
+    pinned AR(1) signals; kernels are Hann low-passes, one per (size, pool index)."""
+    import torch
+
+    from paper_1201_3018_amd import apx, synth
+    reqs = synth.poisson_requests(rate=rate, duration=duration)
+    Lmax = max(r["L"] for r in reqs)
+    Nmax = max(r["N"] for r in reqs)
+    sig = []
+    for i in range(8):
+        t = torch.empty(Lmax, dtype=torch.float32, pin_memory=True)
+        t.copy_(torch.from_numpy(synth.ar1(Lmax, 5100 + i)))
+        sig.append(t)
+    nbuf = 64
+    outs = [torch.empty(Lmax + Nmax - 1, dtype=torch.float32, pin_memory=True) for _ in range(nbuf)]
+    free = list(range(nbuf))
+    taps = {}
+
+    def kernel_for(r):
+        key = (r["N"], r["kernel"])
+        if key not in taps:
+            taps[key] = synth.hann_lowpass(r["N"], 0.02 + 0.45 * r["kernel"] / 128.0)
+        return key[0] * 1000 + key[1], taps[key]
+
+    ctx = apx.Context(0)
+    srv = apx.Server(ctx, hbm_budget=32 << 30, n_streams=8, max_inflight=48)
+    # warm-up: one request per size so that library code paths are loaded (not timed)
+    for N in sorted({r["N"] for r in reqs}):
+        key, k = kernel_for({"N": N, "kernel": 0})
+        srv.submit(key, k, sig[0], outs[0], 40.0, L=max(4096, N))
+        srv.drain()
+        srv.poll(max_n=1024)
+    srv.close()
+    srv = apx.Server(ctx, hbm_budget=32 << 30, n_streams=8, max_inflight=48)
+    lat, done_samples, buf_of, arr_of, cores = [], 0, {}, {}, {0: 0, 1: 0, 2: 0}
+    t0 = apx.Server.now() + 0.2
+    last_done = t0
+
+    def collect(wait_ms=0):
+        nonlocal done_samples, last_done
+        for c in srv.poll(wait_ms=wait_ms):
+            if c["status"] != 0:
+                raise RuntimeError(f"request failed: {c}")
+            lat.append(c["t_done"] - arr_of.pop(c["ticket"]))
+            free.append(buf_of.pop(c["ticket"]))
+            done_samples += c["L"] + c["N"] - 1
+            cores[c["core"]] += 1
+            last_done = max(last_done, c["t_done"])
+
+    for i, r in enumerate(reqs):
+        arrival = t0 + r["t"]
+        while True:
+            collect()
+            now = apx.Server.now()
+            if now >= arrival and free:
+                break
+            if not free:
+                collect(wait_ms=1)
+            elif arrival - now > 0.0004:
+                time.sleep(0.0002)
+        b = free.pop()
+        key, k = kernel_for(r)
+        tk = srv.submit(key, k, sig[i % 8], outs[b], r["snr"], L=r["L"])
+        buf_of[tk] = b
+        arr_of[tk] = arrival
+    srv.drain()
+    collect()
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+    lat = np.array(lat) * 1e3
+    span = last_done - t0
+    res = {
+        "metric": "serving latency p50/p99 and output samples/s under Poisson load, 1 GPU",
+        "value": done_samples / span, "unit": "samples/s", "n_gpus": 1, "steps": len(reqs), "warmup": 0,
+        "ms_per_step": float(np.mean(lat)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "requests": len(reqs), "rate_req_s": rate, "duration_s": duration},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                       "p99": float(np.percentile(lat, 99)), "max": float(np.max(lat))},
+        "served_req_s": len(reqs) / span, "cores": {"time": cores[1], "fft": cores[2]},
+        "server": st,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def measured_traffic(workload: str):

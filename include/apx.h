@@ -128,6 +128,19 @@ apx_status apx_conv(apx_ctx ctx, const float* s_in, int64_t L, const float* k, i
 apx_status apx_xcorr(apx_ctx ctx, const float* s_in, int64_t L, const float* k, int32_t N, int32_t W_block,
                      const apx_params* params, float* r_out, apx_block_info* info, void* stream);
 
+/* apx_run for an APX_AUTO_SNR kernel with the SNR target and the calibration of this call
+ * (Section IV.D): the calibration of apx_calibrate (measured against FP64 at S_q = K_q = 8 on
+ * block `calib_block` of s_in, minus the model of eqs. 18-19) is computed on the device ahead of
+ * the run, on the same stream, and used by this call only; snr_min_db replaces the kernel's
+ * target.  A calibration block without quantization error or without signal gives offset 0.
+ * workspace: device, apx_workspace_bytes() bytes, owned by the caller; calls that overlap in
+ * time need distinct workspaces.  Allocates nothing and never synchronizes, so several requests
+ * may share one prepared kernel concurrently on different streams. */
+size_t apx_workspace_bytes(void);
+apx_status apx_run_auto(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t L, float* r_out,
+                        apx_block_info* info, double snr_min_db, int32_t calib_block, void* workspace,
+                        void* stream);
+
 /* Host only.  A short description of how a prepared kernel runs (core, FFT kernel and transform
  * sizes, companding ranges per mode) written into buf (host, size bytes, NUL-terminated). */
 apx_status apx_kernel_describe(apx_kernel kern, char* buf, int32_t size);
@@ -193,6 +206,75 @@ apx_status apx_fbank_run(apx_ctx ctx, apx_fbank fb, const float* x, int32_t C, i
                          int64_t ldy, void* stream);
 apx_status apx_fbank_describe(apx_fbank fb, char* buf, int32_t size);
 apx_status apx_fbank_destroy(apx_fbank fb);
+
+/* ---- Serving: a request loop with admission by HBM budget and resident kernels ---------------
+ * Convolution and correlation requests of mixed L and N (the paper's problem statement,
+ * Section II, with the SNR constraint of Section IV.D per request) are queued by
+ * apx_server_submit and served by one scheduler thread per server:
+ *   - admission in arrival order while the request's device memory (input, output, workspace,
+ *     and its prepared kernel on a cache miss) fits hbm_budget and fewer than max_inflight
+ *     requests are on the device; idle cached kernels are evicted (least recently used) to make
+ *     room; a request that could never fit is refused at submit (APX_E_NOMEM);
+ *   - every admitted request is launched at once on one of n_streams HIP streams (copy in,
+ *     per-call calibration and block kernel through apx_run_auto, copy out), so requests that
+ *     arrive while others run overlap with them on the device;
+ *   - prepared kernels stay resident, keyed by (kernel_key, N, op, W_block, mode).
+ * Each request is computed exactly as apx_run_auto (APX_AUTO_SNR, calibration on its own block
+ * 0) or apx_run (fixed modes) would compute it alone; the mix changes only timing.
+ * While a server exists, the context belongs to its scheduler thread: the caller must not use
+ * the same context for other calls. */
+typedef struct {
+    int64_t hbm_budget;    /* bytes of device memory for requests and cached kernels (>= 1 MiB) */
+    int32_t n_streams;     /* 1..64 */
+    int32_t max_inflight;  /* requests on the device at once (>= 1) */
+} apx_server_config;
+
+typedef struct {
+    uint64_t kernel_key;   /* equal keys must carry equal taps */
+    const float* k;        /* host, N taps; read when the kernel is not cached */
+    int32_t N;
+    int32_t op;            /* APX_CONV or APX_XCORR */
+    const float* s;        /* host (pinned memory lets the copy overlap), L >= N samples */
+    int64_t L;
+    float* r_out;          /* host (pinned), L + N - 1 samples, written when the request completes */
+    double snr_min_db;     /* APX_AUTO_SNR: per-block target */
+    int32_t W_block;       /* 0: the server's choice (time-domain core up to 129 taps, else FFT core,
+                              smallest power of two with W >= 2N) */
+    int32_t mode;          /* apx_mode; APX_AUTO_SNR for the SNR-driven packing */
+} apx_request;
+/* s, k and r_out must stay valid until the request's completion has been returned by
+ * apx_server_poll (or apx_server_drain returned). */
+
+typedef struct {
+    uint64_t ticket;
+    int32_t status;        /* APX_OK or the failure */
+    int32_t core;          /* apx_core the request ran on */
+    int32_t W_block, N;
+    int64_t L;
+    double t_submit, t_admit, t_done;  /* apx_server_now() clock, seconds */
+} apx_completion;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected;
+    int64_t kernel_hits, kernel_misses, evictions;
+    int64_t peak_bytes;     /* largest budgeted device memory in use */
+    int64_t reserved_bytes; /* device memory held by the server's allocator */
+    int32_t cached_kernels, pad;
+} apx_server_counters;
+
+typedef struct apx_server_s* apx_server;
+apx_status apx_server_create(apx_ctx ctx, const apx_server_config* cfg, apx_server* out);
+/* Thread safe.  *ticket identifies the request's completion. */
+apx_status apx_server_submit(apx_server srv, const apx_request* req, uint64_t* ticket);
+/* Up to max completions (host array), oldest first; waits up to wait_ms for the first one. */
+apx_status apx_server_poll(apx_server srv, apx_completion* out, int32_t max, int32_t* n, int32_t wait_ms);
+/* Blocks until every submitted request has completed. */
+apx_status apx_server_drain(apx_server srv);
+apx_status apx_server_stats(apx_server srv, apx_server_counters* out);
+/* Finishes queued work, then releases everything. */
+apx_status apx_server_destroy(apx_server srv);
+/* The server's clock (steady, seconds). */
+double apx_server_now(void);
 
 const char* apx_status_str(apx_status st);
 const char* apx_last_error(void);

@@ -31,8 +31,9 @@ MODE_NAMES = {APX_FULL_FP32: "full", APX_SYM: "sym", APX_ASYM2: "asym2", APX_ASY
 EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "apx_kernel_destroy", "apx_run",
            "apx_debug_fields", "apx_calibrate", "apx_conv", "apx_xcorr", "apx_kernel_describe", "apx_batch_create",
            "apx_batch_run", "apx_batch_blocks", "apx_batch_describe", "apx_batch_destroy", "apx_xcorr_argmax_batch",
-           "apx_fbank_create", "apx_fbank_run", "apx_fbank_describe", "apx_fbank_destroy", "apx_status_str",
-           "apx_last_error")
+           "apx_fbank_create", "apx_fbank_run", "apx_fbank_describe", "apx_fbank_destroy", "apx_workspace_bytes",
+           "apx_run_auto", "apx_server_create", "apx_server_submit", "apx_server_poll", "apx_server_drain",
+           "apx_server_stats", "apx_server_destroy", "apx_server_now", "apx_status_str", "apx_last_error")
 
 
 class apx_params(ctypes.Structure):
@@ -50,6 +51,28 @@ class apx_block_info(ctypes.Structure):
 BLOCK_INFO_DTYPE = np.dtype([("mode", "<i4"), ("flags", "<i4"), ("Sq", "<i4"), ("Kq", "<i4"), ("rmax", "<i8"),
                              ("cs", "<f8"), ("smax", "<f8"), ("rms", "<f8"), ("snr_pred_db", "<f8")])
 assert BLOCK_INFO_DTYPE.itemsize == ctypes.sizeof(apx_block_info)
+
+
+class apx_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("n_streams", ctypes.c_int32), ("max_inflight", ctypes.c_int32)]
+
+
+class apx_request(ctypes.Structure):
+    _fields_ = [("kernel_key", ctypes.c_uint64), ("k", ctypes.c_void_p), ("N", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("s", ctypes.c_void_p), ("L", ctypes.c_int64), ("r_out", ctypes.c_void_p),
+                ("snr_min_db", ctypes.c_double), ("W_block", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
+class apx_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("core", ctypes.c_int32),
+                ("W_block", ctypes.c_int32), ("N", ctypes.c_int32), ("L", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class apx_server_counters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "rejected", "kernel_hits",
+                                              "kernel_misses", "evictions", "peak_bytes", "reserved_bytes")] + \
+               [("cached_kernels", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class ApxError(RuntimeError):
@@ -91,11 +114,22 @@ def lib() -> ctypes.CDLL:
         L.apx_fbank_run.argtypes = [vp, vp, vp, i32, i64, i64, vp, i64, vp]
         L.apx_fbank_describe.argtypes = [vp, ctypes.c_char_p, i32]
         L.apx_fbank_destroy.argtypes = [vp]
+        L.apx_workspace_bytes.argtypes = []
+        L.apx_workspace_bytes.restype = ctypes.c_size_t
+        L.apx_run_auto.argtypes = [vp, vp, vp, i64, vp, vp, dp, i32, vp, vp]
+        L.apx_server_create.argtypes = [vp, ctypes.POINTER(apx_server_config), pvp]
+        L.apx_server_submit.argtypes = [vp, ctypes.POINTER(apx_request), ctypes.POINTER(ctypes.c_uint64)]
+        L.apx_server_poll.argtypes = [vp, ctypes.POINTER(apx_completion), i32, pi32, i32]
+        L.apx_server_drain.argtypes = [vp]
+        L.apx_server_stats.argtypes = [vp, ctypes.POINTER(apx_server_counters)]
+        L.apx_server_destroy.argtypes = [vp]
+        L.apx_server_now.argtypes = []
+        L.apx_server_now.restype = dp
         L.apx_status_str.argtypes = [ctypes.c_int]
         L.apx_status_str.restype = ctypes.c_char_p
         L.apx_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("apx_status_str", "apx_last_error"):
+            if name not in ("apx_status_str", "apx_last_error", "apx_workspace_bytes", "apx_server_now"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -174,6 +208,16 @@ def apx_calibrate(ctx, kern, s, block: int = 0, Q: int = 8, stream=None) -> floa
     _check(lib().apx_calibrate(ctx, kern, _dev_ptr(s, "float32"), s.numel(), block, Q, _stream(stream),
                                ctypes.byref(off)))
     return off.value
+
+
+def apx_workspace_bytes() -> int:
+    return int(lib().apx_workspace_bytes())
+
+
+def apx_run_auto(ctx, kern, s, out, snr_min_db: float, calib_block: int, workspace, info=None, stream=None):
+    _check(lib().apx_run_auto(ctx, kern, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(out, "float32"),
+                              None if info is None else _dev_ptr(info, "uint8"), float(snr_min_db), int(calib_block),
+                              _dev_ptr(workspace, "uint8"), _stream(stream)))
 
 
 def apx_kernel_describe(kern) -> str:
@@ -328,6 +372,17 @@ class Kernel:
     def describe(self) -> str:
         return apx_kernel_describe(self.h)
 
+    def run_auto(self, s, snr_min_db: float, out=None, calib_block: int = 0, workspace=None, stream=None):
+        """APX_AUTO_SNR run with this call's target and a calibration measured on the device on
+        block `calib_block` of s (apx_run_auto)."""
+        import torch
+        if out is None:
+            out = torch.empty(s.numel() + self.N - 1, dtype=torch.float32, device=s.device)
+        if workspace is None:
+            workspace = torch.empty(apx_workspace_bytes(), dtype=torch.uint8, device=s.device)
+        apx_run_auto(self.ctx.h, self.h, s, out, snr_min_db, calib_block, workspace, None, stream)
+        return out
+
     def calibrate(self, s, block: int = 0, Q: int = 8, stream=None) -> float:
         return apx_calibrate(self.ctx.h, self.h, s, block, Q, stream)
 
@@ -417,6 +472,83 @@ class FilterBank:
         if self.h:
             apx_fbank_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host_ptr(a):
+    """Host address of a contiguous float32 numpy array or CPU tensor."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float32 or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("expected a contiguous float32 array")
+        return a.ctypes.data
+    if a.is_cuda or not a.is_contiguous() or str(a.dtype) != "torch.float32":
+        raise ValueError("expected a contiguous float32 CPU tensor")
+    return a.data_ptr()
+
+
+class Server:
+    """Request loop with admission by HBM budget and resident kernels (apx_server_*).  Keeps the
+    host buffers of every outstanding request alive until its completion is polled."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 32 << 30, n_streams: int = 8, max_inflight: int = 64):
+        self.ctx = ctx
+        cfg = apx_server_config(int(hbm_budget), int(n_streams), int(max_inflight))
+        h = ctypes.c_void_p()
+        _check(lib().apx_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self.keep = {}
+        self._buf = (apx_completion * 1024)()
+
+    @staticmethod
+    def now() -> float:
+        return float(lib().apx_server_now())
+
+    def submit(self, key: int, k, s, r_out, snr_min_db: float = 40.0, op: int = APX_CONV, mode: int = APX_AUTO_SNR,
+               W_block: int = 0, L: Optional[int] = None) -> int:
+        """k: N taps, s: input (first L samples used), r_out: L + N - 1 outputs; host memory
+        (numpy float32 or CPU tensors, pinned ones overlap their copies)."""
+        N = int(k.shape[0])
+        L = int(s.shape[0]) if L is None else int(L)
+        if r_out.shape[0] < L + N - 1:
+            raise ValueError("r_out too short")
+        req = apx_request(int(key), _host_ptr(k), N, int(op), _host_ptr(s), L, _host_ptr(r_out), float(snr_min_db),
+                          int(W_block), int(mode))
+        t = ctypes.c_uint64()
+        st = lib().apx_server_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        if st != APX_OK:
+            raise ApxError(st, "request refused")
+        self.keep[t.value] = (k, s, r_out)
+        return t.value
+
+    def poll(self, wait_ms: int = 0, max_n: int = 1024):
+        n = ctypes.c_int32()
+        _check(lib().apx_server_poll(self.h, self._buf, min(max_n, 1024), ctypes.byref(n), int(wait_ms)))
+        out = []
+        for i in range(n.value):
+            c = self._buf[i]
+            out.append({"ticket": c.ticket, "status": c.status, "core": c.core, "W_block": c.W_block, "N": c.N,
+                        "L": c.L, "t_submit": c.t_submit, "t_admit": c.t_admit, "t_done": c.t_done})
+            self.keep.pop(c.ticket, None)
+        return out
+
+    def drain(self):
+        _check(lib().apx_server_drain(self.h))
+
+    def stats(self) -> dict:
+        c = apx_server_counters()
+        _check(lib().apx_server_stats(self.h, ctypes.byref(c)))
+        return {n: getattr(c, n) for n, _ in apx_server_counters._fields_ if n != "pad"}
+
+    def close(self):
+        if self.h:
+            _check(lib().apx_server_destroy(self.h))
+            self.h = None
+            self.keep.clear()
 
     def __del__(self):
         try:

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "engine.h"
 #include "internal.h"
 
 using namespace apx;
@@ -38,8 +39,6 @@ apx_status fail(apx_status st, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(APX_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int LOGF_MAX_TABLE = 14;  // twiddle tables up to F = 16384
-
 int64_t isqrt64(int64_t x) {
     int64_t r = (int64_t)sqrt((double)x);
     while (r * r > x) --r;
@@ -61,51 +60,6 @@ int ceil_log2(int64_t x) {
 
 }  // namespace
 
-struct apx_ctx_s {
-    int device = 0;
-    double2* twd = nullptr;
-    float2* twf = nullptr;
-    int max_lds = 65536;
-    // W_F^t tables (t < F) of any length F, built on first use
-    std::map<int, std::pair<double2*, float2*>> tables;
-};
-
-struct apx_kernel_s {
-    apx_ctx ctx = nullptr;
-    int32_t N = 0;       // taps as given
-    int32_t N_odd = 0;
-    int32_t op = APX_CONV;
-    int32_t W_block = 0, W = 0;
-    apx_params params{};
-    int core = APX_CORE_TIME;
-    int logF = 0;
-    int32_t S[4] = {0, 0, 0, 0}, K[4] = {0, 0, 0, 0};
-    int64_t R[4] = {0, 0, 0, 0};
-    int32_t T[4] = {0, 0, 0, 0};
-    int32_t Fw[4] = {0, 0, 0, 0};
-    int32_t cand_mask = 0;
-    double calib_db = 0.0;
-    size_t td_lds = 0;
-    bool use[4] = {false, false, false, false};  // FP32, SYM, ASYM2, ASYM3 states needed
-    KState* ks = nullptr;
-    float* kf = nullptr;
-    double* kd = nullptr;
-    double* kq[4] = {nullptr, nullptr, nullptr, nullptr};
-    int32_t kq_len[4] = {0, 0, 0, 0}, kq_pad[4] = {0, 0, 0, 0};
-    int32_t kf_pad = 0;
-    double2* spec[4] = {nullptr, nullptr, nullptr, nullptr};
-    float2* spec32 = nullptr;
-    // wave-per-block FFT core
-    bool wave = false;
-    int32_t wM[4] = {0, 0, 0, 0};  // complex points per mode (0 = FP32)
-    double2* coef[4] = {nullptr, nullptr, nullptr, nullptr};
-    float2* coef32 = nullptr;
-    std::vector<void*> allocs;
-    // device buffers carved from a caller-owned pool instead of hipMalloc (batched pairs)
-    char* pool = nullptr;
-    size_t pool_off = 0, pool_cap = 0;
-};
-
 namespace {
 
 template <typename T>
@@ -115,12 +69,14 @@ apx_status dalloc(apx_kernel k, T** p, size_t n) {
         if (k->pool_off + bytes > k->pool_cap) return fail(APX_E_NOMEM, "pair buffer pool exhausted");
         *p = (T*)(k->pool + k->pool_off);
         k->pool_off += bytes;
+        k->dev_bytes += bytes;
         return APX_OK;
     }
     void* q = nullptr;
     hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
     if (e != hipSuccess) return fail(APX_E_NOMEM, "hipMalloc(%zu): %s", n * sizeof(T), hipGetErrorString(e));
     k->allocs.push_back(q);
+    k->dev_bytes += std::max<size_t>(n, 1) * sizeof(T);
     *p = (T*)q;
     return APX_OK;
 }
@@ -272,6 +228,17 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
     return a;
 }
 
+apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
+    if (k->core == APX_CORE_FFT && k->wave) {
+        HIPCHK(launch_fftw(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
+    } else if (k->core == APX_CORE_FFT) {
+        HIPCHK(launch_fft(a, k->logF, st));
+    } else {
+        HIPCHK(launch_td(a, k->td_lds, st));
+    }
+    return APX_OK;
+}
+
 apx_status run_impl(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, double* fields,
                     apx_block_info* info, hipStream_t st) {
     if (!ctx || !k) return fail(APX_E_INVALID, "null context or kernel");
@@ -283,14 +250,7 @@ apx_status run_impl(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float*
     if (P > (int64_t)0x7fffffff - 1) return fail(APX_E_UNSUPPORTED, "too many blocks");
     HIPCHK(hipSetDevice(ctx->device));
     RunArgs a = make_args(k, s, L, out, fields, info, P);
-    if (k->core == APX_CORE_FFT && k->wave) {
-        HIPCHK(launch_fftw(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
-    } else if (k->core == APX_CORE_FFT) {
-        HIPCHK(launch_fft(a, k->logF, st));
-    } else {
-        HIPCHK(launch_td(a, k->td_lds, st));
-    }
-    return APX_OK;
+    return launch_block_kernel(k, a, st);
 }
 
 }  // namespace
@@ -538,6 +498,7 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             e = launch_coef32(k->kd, N_odd, k->wM[0], tF, k->coef32, st);
         }
     }
+    if (e == hipSuccess && core == APX_CORE_FFT && !k->wave && fft_words == 0) e = fft_set_lds(k->logF);
     if (e != hipSuccess) {
         free_kernel(k);
         return fail(APX_E_DEVICE, "kernel preparation launch: %s", hipGetErrorString(e));
@@ -631,6 +592,32 @@ apx_status apx_calibrate(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, i
     k->calib_db = measured - model;
     if (offset_db) *offset_db = k->calib_db;
     return APX_OK;
+}
+
+size_t apx_workspace_bytes(void) { return 2048; }
+
+apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info,
+                        double snr_min_db, int32_t calib_block, void* workspace, void* stream) {
+    if (!ctx || !k || !s || !out || !workspace) return fail(APX_E_INVALID, "null argument");
+    if (k->params.mode != APX_AUTO_SNR) return fail(APX_E_INVALID, "apx_run_auto needs an APX_AUTO_SNR kernel");
+    if (!isfinite(snr_min_db)) return fail(APX_E_INVALID, "snr_min_db must be finite");
+    if (L < k->N) return fail(APX_E_INVALID, "input length L = %lld shorter than the kernel N = %d", (long long)L, k->N);
+    int64_t P = 0;
+    apx_status r = geometry(L, k->N, k->W_block, nullptr, nullptr, &P);
+    if (r != APX_OK) return r;
+    if (calib_block < 0 || calib_block >= P)
+        return fail(APX_E_INVALID, "calibration block %d outside [0, %lld)", calib_block, (long long)P);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    const int nparts = 64, Q = 8;
+    double* part = (double*)workspace;
+    double* off = part + 2 * nparts + 2;
+    RunArgs a = make_args(k, s, L, out, nullptr, info, P);
+    HIPCHK(launch_calib(a, calib_block, Q, part, nparts, st));
+    HIPCHK(launch_calib_finish(part, nparts, k->ks, Q, off, st));
+    a.calib_dev = off;
+    a.snr_min_db = snr_min_db;
+    return launch_block_kernel(k, a, st);
 }
 
 apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {

@@ -1,0 +1,64 @@
+// Host-side handle types of libapx shared by the C ABI (capi.cpp) and the serving engine
+// (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "apx.h"
+#include "internal.h"
+
+constexpr int LOGF_MAX_TABLE = 14;  // twiddle tables up to F = 16384
+
+using apx::KState;
+
+struct apx_ctx_s {
+    int device = 0;
+    double2* twd = nullptr;
+    float2* twf = nullptr;
+    int max_lds = 65536;
+    // W_F^t tables (t < F) of any length F, built on first use
+    std::map<int, std::pair<double2*, float2*>> tables;
+};
+
+struct apx_kernel_s {
+    apx_ctx ctx = nullptr;
+    int32_t N = 0;       // taps as given
+    int32_t N_odd = 0;
+    int32_t op = APX_CONV;
+    int32_t W_block = 0, W = 0;
+    apx_params params{};
+    int core = APX_CORE_TIME;
+    int logF = 0;
+    int32_t S[4] = {0, 0, 0, 0}, K[4] = {0, 0, 0, 0};
+    int64_t R[4] = {0, 0, 0, 0};
+    int32_t T[4] = {0, 0, 0, 0};
+    int32_t Fw[4] = {0, 0, 0, 0};
+    int32_t cand_mask = 0;
+    double calib_db = 0.0;
+    size_t td_lds = 0;
+    bool use[4] = {false, false, false, false};  // FP32, SYM, ASYM2, ASYM3 states needed
+    KState* ks = nullptr;
+    float* kf = nullptr;
+    double* kd = nullptr;
+    double* kq[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t kq_len[4] = {0, 0, 0, 0}, kq_pad[4] = {0, 0, 0, 0};
+    int32_t kf_pad = 0;
+    double2* spec[4] = {nullptr, nullptr, nullptr, nullptr};
+    float2* spec32 = nullptr;
+    // wave-per-block FFT core
+    bool wave = false;
+    int32_t wM[4] = {0, 0, 0, 0};  // complex points per mode (0 = FP32)
+    double2* coef[4] = {nullptr, nullptr, nullptr, nullptr};
+    float2* coef32 = nullptr;
+    std::vector<void*> allocs;
+    size_t dev_bytes = 0;  // device memory owned by (or carved for) this kernel
+    // device buffers carved from a caller-owned pool instead of hipMalloc (batched pairs)
+    char* pool = nullptr;
+    size_t pool_off = 0, pool_cap = 0;
+};
+

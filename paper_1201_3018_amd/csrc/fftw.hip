@@ -316,6 +316,11 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
     c.snr_db = INFINITY;
     c.mode = a.mode;
     if (a.mode == MD_AUTO) {
+        double thr = a.thr_lin, calib = a.calib_db;
+        if (a.calib_dev) {
+            calib = *a.calib_dev;
+            thr = pow(10.0, (a.snr_min_db - calib) / 10.0);
+        }
         c.mode = MD_FULL32;
 #pragma unroll
         for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
@@ -325,9 +330,9 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
                 break;
             }
             double ratio = wsnr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
-            if (ratio >= a.thr_lin) {
+            if (ratio >= thr) {
                 c.mode = m;
-                c.snr_db = 10.0 * log10(ratio) + a.calib_db;
+                c.snr_db = 10.0 * log10(ratio) + calib;
                 break;
             }
         }

@@ -47,6 +47,8 @@ struct RunArgs {
     int32_t Fw[4];       // FFT length in words per mode (index 0 = FP32 full precision)
     double thr_lin;      // MD_AUTO: SNR ratio that a candidate's model must reach
     double calib_db;     // MD_AUTO: offset reported in the block info
+    const double* calib_dev;  // MD_AUTO: offset measured on the device for this call (nullable);
+    double snr_min_db;        //   then the threshold is formed per block from snr_min_db
     const KState* ks;
     const double* kq[4]; // [1] packed symmetric taps, [2], [3] companded taps (FP64, zero padded)
     int32_t kq_len[4];   // taps per mode before padding
@@ -79,6 +81,10 @@ hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st);
 hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st);
 hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts,
                         hipStream_t st);
+// offset = measured - model SNR from launch_calib's partials, written to *out (device)
+hipError_t launch_calib_finish(const double* partial, int32_t nparts, const KState* ks, int32_t Q, double* out,
+                               hipStream_t st);
+hipError_t fft_set_lds(int logF);
 size_t td_lds_bytes(int mode, int N_odd, int W_block, int T2, int T3);
 // wave-per-block FFT core (fftw.hip)
 hipError_t upload_dft_constants(const double2* w32, const double2* w24);

@@ -173,6 +173,11 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
     c.snr_db = INFINITY;
     c.mode = a.mode;
     if (a.mode == MD_AUTO) {
+        double thr = a.thr_lin, calib = a.calib_db;
+        if (a.calib_dev) {
+            calib = *a.calib_dev;
+            thr = pow(10.0, (a.snr_min_db - calib) / 10.0);
+        }
         c.mode = MD_FULL32;
 #pragma unroll
         for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
@@ -182,9 +187,9 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
                 break;
             }
             double ratio = snr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
-            if (ratio >= a.thr_lin) {
+            if (ratio >= thr) {
                 c.mode = m;
-                c.snr_db = 10.0 * log10(ratio) + a.calib_db;
+                c.snr_db = 10.0 * log10(ratio) + calib;
                 break;
             }
         }
@@ -614,7 +619,7 @@ __global__ void __launch_bounds__(NT) k_fft(RunArgs a) {
     constexpr int F = 1 << LOGF;        // words for FP32 / asymmetric modes
     constexpr int MA = F / 2;           // complex points, FP32 / asymmetric
     constexpr int MS = F / 4;           // complex points, symmetric (F/2 words)
-    __shared__ __attribute__((aligned(16))) char lds[MA * 2 * sizeof(double)];
+    extern __shared__ __attribute__((aligned(16))) char lds[];  // MA complex FP64 points
     const Item it = make_item(a, blockIdx.x, true);
     const BlockStats st = block_stats(a.s, it.start, it.nwin);
     const Choice c = choose(a, st);
@@ -637,16 +642,36 @@ __global__ void __launch_bounds__(NT) k_fft(RunArgs a) {
 }
 
 int fft_min_logF() { return 9; }
-int fft_max_logF() { return 13; }
+int fft_max_logF() { return 14; }
+
+static size_t fft_lds(int logF) { return ((size_t)1 << logF) * sizeof(double); }
+
+// Raises the LDS limit of the kernel for logF (once, at kernel preparation: launches may be
+// captured into a graph).
+hipError_t fft_set_lds(int logF) {
+    const void* f = nullptr;
+    switch (logF) {
+        case 9: f = (const void*)k_fft<9>; break;
+        case 10: f = (const void*)k_fft<10>; break;
+        case 11: f = (const void*)k_fft<11>; break;
+        case 12: f = (const void*)k_fft<12>; break;
+        case 13: f = (const void*)k_fft<13>; break;
+        case 14: f = (const void*)k_fft<14>; break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds(logF));
+}
 
 hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st) {
     dim3 g((unsigned)(a.P + 1));
+    const size_t lds = fft_lds(logF);
     switch (logF) {
-        case 9: hipLaunchKernelGGL(k_fft<9>, g, dim3(NT), 0, st, a); break;
-        case 10: hipLaunchKernelGGL(k_fft<10>, g, dim3(NT), 0, st, a); break;
-        case 11: hipLaunchKernelGGL(k_fft<11>, g, dim3(NT), 0, st, a); break;
-        case 12: hipLaunchKernelGGL(k_fft<12>, g, dim3(NT), 0, st, a); break;
-        case 13: hipLaunchKernelGGL(k_fft<13>, g, dim3(NT), 0, st, a); break;
+        case 9: hipLaunchKernelGGL(k_fft<9>, g, dim3(NT), lds, st, a); break;
+        case 10: hipLaunchKernelGGL(k_fft<10>, g, dim3(NT), lds, st, a); break;
+        case 11: hipLaunchKernelGGL(k_fft<11>, g, dim3(NT), lds, st, a); break;
+        case 12: hipLaunchKernelGGL(k_fft<12>, g, dim3(NT), lds, st, a); break;
+        case 13: hipLaunchKernelGGL(k_fft<13>, g, dim3(NT), lds, st, a); break;
+        case 14: hipLaunchKernelGGL(k_fft<14>, g, dim3(NT), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -967,6 +992,36 @@ __global__ void __launch_bounds__(NT) k_calib(RunArgs a, int64_t block, int32_t 
 
 hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts, hipStream_t st) {
     hipLaunchKernelGGL(k_calib, dim3(nparts), dim3(NT), 0, st, a, block, Q, partial);
+    return hipGetLastError();
+}
+
+// Same arithmetic as the host side of apx_calibrate, in the same order.  A block without
+// quantization error or without signal gives offset 0 (the model alone).
+__global__ void k_calib_finish(const double* __restrict__ partial, int32_t nparts, const KState* __restrict__ ks,
+                               int32_t Q, double* out) {
+    if (threadIdx.x != 0) return;
+    double pr = 0.0, pe = 0.0;
+    for (int i = 0; i < nparts; ++i) {
+        pr += partial[2 * i];
+        pe += partial[2 * i + 1];
+    }
+    const double smax = partial[2 * nparts], rms = partial[2 * nparts + 1];
+    const double kmax = ks->kmax, krms = ks->krms;
+    double off = 0.0;
+    if (pe > 0.0 && pr > 0.0 && rms > 0.0 && krms > 0.0) {
+        const double measured = 10.0 * log10(pr / pe);
+        const double r12 = sqrt(12.0);
+        const double svs = smax / (Q * r12), svk = kmax / (Q * r12);
+        const double D = (rms * svk) * (rms * svk) + (krms * svs) * (krms * svs) + (svk * svs) * (svk * svs);
+        const double model = 10.0 * log10((rms * krms) * (rms * krms) / D);
+        off = measured - model;
+    }
+    *out = off;
+}
+
+hipError_t launch_calib_finish(const double* partial, int32_t nparts, const KState* ks, int32_t Q, double* out,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_calib_finish, dim3(1), dim3(64), 0, st, partial, nparts, ks, Q, out);
     return hipGetLastError();
 }
 

@@ -98,9 +98,10 @@ def xcorr_batch(n_templates: int = 4096, n_refs: int = 64, seed_refs: int = 3001
 
 def poisson_requests(rate: float = 2000.0, duration: float = 10.0, seed: int = 5001,
                      L_range=(1 << 12, 1 << 22), N_range=(16, 4096), n_sizes: int = 32,
-                     snr_choices=(30.0, 40.0, 50.0)):
+                     snr_choices=(30.0, 40.0, 50.0), kernels_per_size: int = 128):
     """Poisson arrivals; L log-uniform, N log-uniform snapped to n_sizes log-spaced values,
-    SNR target uniform over snr_choices.  Returns a list of dicts sorted by arrival time."""
+    SNR target uniform over snr_choices, kernel index uniform in a pool of kernels_per_size.
+    Returns a list of dicts sorted by arrival time."""
     rng = np.random.default_rng(seed)
     t, out = 0.0, []
     sizes = np.unique(np.round(np.geomspace(N_range[0], N_range[1], n_sizes)).astype(int))
@@ -112,5 +113,5 @@ def poisson_requests(rate: float = 2000.0, duration: float = 10.0, seed: int = 5
         N = int(sizes[int(np.argmin(np.abs(np.log(sizes) - rng.uniform(math.log(N_range[0]),
                                                                          math.log(N_range[1])))))])
         out.append({"t": t, "L": L, "N": N, "snr": float(rng.choice(snr_choices)),
-                    "seed": int(rng.integers(0, 2 ** 31))})
+                    "seed": int(rng.integers(0, 2 ** 31)), "kernel": int(rng.integers(0, kernels_per_size))})
     return out
