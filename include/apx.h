@@ -62,7 +62,9 @@ typedef struct {
     double calib_db;      /* APX_AUTO_SNR: offset added to the model SNR (apx_calibrate) */
     int32_t allow_unsafe; /* 1: accept R_max beyond the bound (unpacking may then be wrong) */
     int32_t fft_variant;  /* FFT core implementation: 0 = automatic, 1 = one 256-thread workgroup
-                             per block, 2 = one wavefront per block (supported sizes only) */
+                             per block with LDS passes, 2 = one wavefront per block, 3 = a group
+                             of 512-point wavefront transforms per block (2 and 3: supported
+                             sizes only) */
 } apx_params;
 
 #define APX_FLAG_NONFINITE 1

@@ -229,7 +229,9 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
 }
 
 apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
-    if (k->core == APX_CORE_FFT && k->wave) {
+    if (k->core == APX_CORE_FFT && k->group) {
+        HIPCHK(launch_fftg(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
+    } else if (k->core == APX_CORE_FFT && k->wave) {
         HIPCHK(launch_fftw(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
     } else if (k->core == APX_CORE_FFT) {
         HIPCHK(launch_fft(a, k->logF, st));
@@ -418,23 +420,35 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             wm[m] = wave_m_for(need[m]);
             if (k->use[m] && wm[m] == 0) ok = false;
         }
+        if (wm[0] == 0) ok = false;  // the FP32 size also sizes the window in LDS
         if (ok && p.fft_variant != 1) {
-            // modes that are not used may take any size: look for a compiled set that matches
-            // the used modes (the launch needs a complete set)
+            // modes that are not used may take any size, except the FP32 slot (W_block <= 2 M):
+            // look for a compiled set that matches (the launch needs a complete set); the
+            // one-wave core first (faster on every measured shape), the group core if asked for
             const int cand[4] = {512, 1024, 1536, 2048};
-            for (int c = 0; c < 256 && !k->wave; ++c) {
-                const int t4[4] = {cand[c & 3], cand[(c >> 2) & 3], cand[(c >> 4) & 3], cand[(c >> 6) & 3]};
-                bool match = true;
-                for (int m = 0; m < 4; ++m)
-                    if (k->use[m] && t4[m] != wm[m]) match = false;
-                if (match && wave_supported(t4[1], t4[2], t4[3], t4[0])) {
-                    for (int m = 0; m < 4; ++m) k->wM[m] = t4[m];
-                    k->wave = true;
+            for (int pass = (p.fft_variant == 3 ? 0 : 1); pass >= 0 && !k->wave; --pass) {
+                if (pass == 0 && p.fft_variant != 3) continue;
+                for (int c = 0; c < 256 && !k->wave; ++c) {
+                    const int t4[4] = {cand[c & 3], cand[(c >> 2) & 3], cand[(c >> 4) & 3], cand[(c >> 6) & 3]};
+                    bool match = t4[0] == wm[0];
+                    for (int m = 1; m < 4; ++m)
+                        if (k->use[m] && t4[m] != wm[m]) match = false;
+                    const bool sup = pass == 0 ? group_supported(t4[1], t4[2], t4[3], t4[0])
+                                               : wave_supported(t4[1], t4[2], t4[3], t4[0]);
+                    if (match && sup) {
+                        for (int m = 0; m < 4; ++m) k->wM[m] = t4[m];
+                        k->wave = true;
+                        k->group = pass == 0;
+                    }
                 }
             }
         }
-        if (p.fft_variant == 2 && !k->wave) {
-            return fail(APX_E_UNSUPPORTED, "no compiled wave-FFT size set covers W_block = %d, N = %d", W_block, N);
+        if ((p.fft_variant == 2 || p.fft_variant == 3) && !k->wave) {
+            return fail(APX_E_UNSUPPORTED, "no compiled %s size set covers W_block = %d, N = %d",
+                        p.fft_variant == 2 ? "one-wave" : "group", W_block, N);
+        }
+        if (p.fft_variant == 3 && !k->group) {
+            return fail(APX_E_UNSUPPORTED, "no compiled group size set covers W_block = %d, N = %d", W_block, N);
         }
     } else {
         k->td_lds = td_lds_bytes(p.mode, N_odd, W_block, k->T[MD_ASYM2], k->T[MD_ASYM3]);
@@ -627,8 +641,9 @@ apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {
     if (k->core == APX_CORE_TIME) {
         n = snprintf(tmp, sizeof tmp, "core=time kernel=k_td lds=%zu", k->td_lds);
     } else if (k->wave) {
-        n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_fftw<%d,%d,%d,%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d",
-                     k->wM[1], k->wM[2], k->wM[3], k->wM[0], 2 * k->wM[0], 2 * k->wM[1], 2 * k->wM[2], 2 * k->wM[3]);
+        n = snprintf(tmp, sizeof tmp, "core=fft kernel=%s<%d,%d,%d,%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d",
+                     k->group ? "k_fftg" : "k_fftw", k->wM[1], k->wM[2], k->wM[3], k->wM[0], 2 * k->wM[0],
+                     2 * k->wM[1], 2 * k->wM[2], 2 * k->wM[3]);
     } else {
         n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_fft<%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d", k->logF,
                      k->Fw[0], k->Fw[1], k->Fw[2], k->Fw[3]);

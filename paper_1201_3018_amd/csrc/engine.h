@@ -52,6 +52,7 @@ struct apx_kernel_s {
     float2* spec32 = nullptr;
     // wave-per-block FFT core
     bool wave = false;
+    bool group = false;  // wave tables, run by the group-of-waves core
     int32_t wM[4] = {0, 0, 0, 0};  // complex points per mode (0 = FP32)
     double2* coef[4] = {nullptr, nullptr, nullptr, nullptr};
     float2* coef32 = nullptr;

@@ -123,20 +123,21 @@ __device__ __forceinline__ void dftn(cx<T>* v) {
     else static_assert(R == 2, "unsupported in-register DFT size");
 }
 
-// An opaque copy of the lane id: address arithmetic derived from it cannot be shared between
+// An opaque copy of the lane id (0..63 in every wave of the workgroup): address arithmetic derived from it cannot be shared between
 // phases, so nothing computed for one phase stays live (in registers) through the next.
 __device__ __forceinline__ int lane_id_fresh() {
-    int l = (int)threadIdx.x;
+    int l = (int)threadIdx.x & 63;
     asm volatile("" : "+v"(l));
     return l;
 }
 
 // Complex FFT of M points by one wave: lane l holds v[r] = z[l + 64 r] on entry and
-// v[t] = Z[l + 64 t] on exit.  Passes: radix E (= M/64, registers only), radix 8, radix 8.
+// v[t] = Z[l + 64 t] on exit.  It passes WAVE_FFT_BARRIERS workgroup barriers (a wave of a
+// larger workgroup that has no transform to run passes the same number).  tw[t TS] = W_M^t.  Passes: radix E (= M/64, registers only), radix 8, radix 8.
 // The two exchanges use the wave's LDS slice in a padded layout, point i at i + floor(i/E)
 // (rows of E points padded by one: the strided writes of the first pass spread over the
 // banks); every address below is that mapping in closed form.  tw: W_M^t, t < M.
-template <typename T, int M, bool INV>
+template <typename T, int M, bool INV, int TS = 1>
 __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw_of<T>::type* tw) {
     constexpr int E = M / 64;
     static_assert(E % 8 == 0, "points per lane must be a multiple of 8");
@@ -165,7 +166,7 @@ __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw
             for (int r = 0; r < 8; ++r) u[b][r] = rp[8 * r * S];
 #pragma unroll
             for (int r = 1; r < 8; ++r) {
-                auto w = tw[r * k * 8];  // W_{8E}^{rk} = W_M^{8rk}
+                auto w = tw[r * k * 8 * TS];  // W_{8E}^{rk} = W_M^{8rk}
                 u[b][r] = cmul(u[b][r], cx<T>{w.x, INV ? -w.y : w.y});
             }
             dft8<T, INV>(u[b]);
@@ -192,7 +193,7 @@ __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw
             for (int r = 0; r < 8; ++r) x[r] = rp[8 * r * S];
 #pragma unroll
             for (int r = 1; r < 8; ++r) {
-                auto w = tw[r * j];
+                auto w = tw[r * j * TS];
                 x[r] = cmul(x[r], cx<T>{w.x, INV ? -w.y : w.y});
             }
             dft8<T, INV>(x);
@@ -201,6 +202,13 @@ __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw
         }
     }
     __syncthreads();
+}
+
+constexpr int WAVE_FFT_BARRIERS = 4;
+
+__device__ __forceinline__ void wave_fft_idle() {
+#pragma unroll
+    for (int i = 0; i < WAVE_FFT_BARRIERS; ++i) __syncthreads();
 }
 
 // Real-signal spectral step: V[k] = alpha_k Z[k] + beta_k conj(Z[M-k]) with alpha, beta built
@@ -681,6 +689,391 @@ hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipSt
 #define APX_LAUNCH(a_, b_, c_, d_) \
     if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return launch_set<a_, b_, c_, d_>(a, grid, st);
     APX_WAVE_SETS(APX_LAUNCH)
+#undef APX_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Group-of-waves FFT core: one workgroup of NW waves per block.  The M = 512 R point transform
+// is split by decimation in time into R transforms of 512 points, one per wave in registers
+// (wave_fft<512>), joined by a radix-R step across the waves in LDS:
+//   Z[k + 512 j] = sum_w W_R^(w j) W_M^(w k) Z_w[k],   Z_w = DFT_512(z[R n + w]);
+// the inverse splits first (decimation in frequency):
+//   x[R n + w] = IDFT_512(y_w)[n],   y_w[k] = W_M^(-w k) sum_j W_R^(-w j) V[k + 512 j].
+// The whole workgroup loads the window, takes the statistics, runs the column steps, the
+// spectral step and the unpacking; each wave's 512-point transforms use its own LDS slice.
+// ------------------------------------------------------------------------------------------
+constexpr int GM = 512;                   // points per wave transform
+constexpr int GSLICE = GM + GM / 8 + 1;   // wave_fft slice (E = 8, rows of 8 padded by one)
+
+template <int R, typename T>
+constexpr size_t group_lds_bytes() {
+    return ((size_t)(GM * R + 2) + (size_t)R * GSLICE) * 2 * sizeof(T);
+}
+
+template <int NTH>
+__device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WItem& it, float* win, double* red) {
+    double m = 0.0, q = 0.0;
+    int nf = 0;
+    const float* p = a.s + it.start;
+    constexpr int CH = 8;
+    for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
+        float2 f[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = base + 2 * ((int)threadIdx.x + NTH * c);
+            f[c] = make_float2(0.0f, 0.0f);
+            if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
+            else if (i < it.nwin) f[c].x = p[i];
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = base + 2 * ((int)threadIdx.x + NTH * c);
+            if (i < a.W_block) {
+                const float x0 = f[c].x, x1 = f[c].y;
+                if (!isfinite(x0) || !isfinite(x1)) nf = 1;
+                const double d0 = isfinite(x0) ? (double)x0 : 0.0, d1 = isfinite(x1) ? (double)x1 : 0.0;
+                m = fmax(m, fmax(fabs(d0), fabs(d1)));
+                q += d0 * d0 + d1 * d1;
+                win[i] = (i < it.nvalid) ? x0 : 0.0f;
+                win[i + 1] = (i + 1 < it.nvalid) ? x1 : 0.0f;
+            }
+        }
+    }
+    m = wmax(m);
+    q = wsum(q);
+    nf = wor(nf);
+    constexpr int NW = NTH / 64;
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[wv] = m;
+        red[NW + wv] = q;
+        red[2 * NW + wv] = (double)nf;
+    }
+    if (threadIdx.x == 0) {
+        win[-1] = 0.0f;
+        win[a.W_block] = 0.0f;
+    }
+    __syncthreads();
+    WStats r;
+    r.smax = 0.0;
+    r.sumsq = 0.0;
+    r.nonfinite = 0;
+    for (int i = 0; i < NW; ++i) {  // same order in every thread
+        r.smax = fmax(r.smax, red[i]);
+        r.sumsq += red[NW + i];
+        r.nonfinite |= red[2 * NW + i] != 0.0;
+    }
+    return r;
+}
+
+template <int MODE, int R, int NW, bool FIELDS>
+__device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, const WChoice& c, char* lds_raw) {
+    using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+    constexpr int M = GM * R;
+    constexpr int NTH = 64 * NW;
+    const int N = a.N;
+    cx<T>* Z = reinterpret_cast<cx<T>*>(lds_raw);              // M + 1 points
+    cx<T>* slice0 = Z + (M + 2);                                // R slices
+    const float* win = reinterpret_cast<const float*>(lds_raw) + 1;  // aliases Z until the join
+    const typename tw_of<T>::type* tw;  // W_M^t, t < M
+    const typename tw_of<T>::type* coef;
+    if constexpr (MODE == MD_FULL32) {
+        tw = a.wtwf;
+        coef = a.coef32;
+    } else {
+        tw = (MODE == MD_SYM) ? a.wtw[1] : (MODE == MD_ASYM2 ? a.wtw[2] : a.wtw[3]);
+        coef = (MODE == MD_SYM) ? a.coef[1] : (MODE == MD_ASYM2 ? a.coef[2] : a.coef[3]);
+    }
+    constexpr int MM = (MODE == MD_ASYM3) ? 3 : 2;
+    const bool prefix = it.j_lo == 0;
+    int Tit = 0, base_off = 0, lw = 0;
+    if constexpr (MODE == MD_ASYM2 || MODE == MD_ASYM3) {
+        Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+        base_off = it.j_lo - (N - 1);
+        lw = Tit + N - 1;
+    }
+    const int wb = a.W_block;
+    auto rd = [&](int i) -> float { return win[min(max(i, -1), wb)]; };
+    auto sqd = [&](int i) -> double { return rint(c.cs * (double)rd(i)); };
+    const int wv = threadIdx.x >> 6;
+    const bool active = wv < R;
+    // ---- pack: wave w holds z[R n + w], n = l + 64 r (eq. 4 / eq. 7 on words 2m, 2m + 1)
+    cx<T> v[8];
+    if (active) {
+        const int l = lane_id_fresh() & 63;
+        const double eps = (MODE == MD_FULL32) ? 0.0 : 1.0 / (2.0 * (double)c.R);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int m = R * (l + 64 * r) + wv;  // complex point = words 2m, 2m + 1
+            if constexpr (MODE == MD_FULL32) {
+                v[r].x = rd(2 * m);
+                v[r].y = rd(2 * m + 1);
+            } else if constexpr (MODE == MD_SYM) {
+                v[r].x = sqd(4 * m) + eps * sqd(4 * m + 1);
+                v[r].y = sqd(4 * m + 2) + eps * sqd(4 * m + 3);
+            } else {
+                double w2[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int wd = 2 * m + h;
+                    double acc = 0.0, e = 1.0;
+#pragma unroll
+                    for (int q = 0; q < MM; ++q) {
+                        acc += e * sqd(base_off + q * Tit + wd);
+                        e *= eps;
+                    }
+                    w2[h] = (wd < lw) ? acc : 0.0;
+                }
+                v[r].x = w2[0];
+                v[r].y = w2[1];
+            }
+        }
+    }
+    __syncthreads();  // the window (which may overlap the slices) is dead from here on
+    // ---- forward transforms of the decimated sequences
+    if (active) wave_fft<T, GM, false, R>(v, slice0 + wv * GSLICE, tw);
+    else wave_fft_idle();
+    // ---- join: Z[k + 512 j] = DFT_R over w of W_M^(w k) Z_w[k]
+    if (active) {
+        const int l = lane_id_fresh() & 63;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int k = l + 64 * t;
+            cx<T> z = v[t];
+            if (wv > 0) {
+                const auto w = tw[wv * k];
+                z = cmul(z, cx<T>{w.x, w.y});
+            }
+            Z[wv * GM + k] = z;
+        }
+    }
+    __syncthreads();
+    if constexpr (R > 1) {
+        for (int k = threadIdx.x; k < GM; k += NTH) {
+            cx<T> col[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) col[j] = Z[j * GM + k];
+            dftn<T, R, false>(col);
+#pragma unroll
+            for (int j = 0; j < R; ++j) Z[j * GM + k] = col[j];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) Z[M] = Z[0];
+    __syncthreads();
+    // ---- spectral step on pairs (k, M - k): V[k] = alpha_k Z[k] + beta_k conj(Z[M - k])
+    for (int k = threadIdx.x; k <= M / 2; k += NTH) {
+        const cx<T> za = Z[k], zb = Z[M - k];
+        const auto a0 = coef[2 * k], b0 = coef[2 * k + 1];
+        const cx<T> va = cmul(za, cx<T>{a0.x, a0.y}) + cmul(conj(zb), cx<T>{b0.x, b0.y});
+        if (k > 0 && 2 * k < M) {
+            const auto a1 = coef[2 * (M - k)], b1 = coef[2 * (M - k) + 1];
+            Z[M - k] = cmul(zb, cx<T>{a1.x, a1.y}) + cmul(conj(za), cx<T>{b1.x, b1.y});
+        }
+        Z[k] = va;
+    }
+    __syncthreads();
+    // ---- split: y_w[k] = W_M^(-w k) IDFT_R over j of V[k + 512 j], stored at Z[w 512 + k]
+    if constexpr (R > 1) {
+        for (int k = threadIdx.x; k < GM; k += NTH) {
+            cx<T> col[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) col[j] = Z[j * GM + k];
+            dftn<T, R, true>(col);
+#pragma unroll
+            for (int w = 0; w < R; ++w) {
+                cx<T> y = col[w];
+                if (w > 0) {
+                    const auto tww = tw[w * k];
+                    y = cmul(y, cx<T>{tww.x, -tww.y});
+                }
+                Z[w * GM + k] = y;
+            }
+        }
+        __syncthreads();
+    }
+    // ---- inverse transforms; every wave has read its row before the first barrier inside
+    if (active) {
+        const int l = lane_id_fresh() & 63;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = Z[wv * GM + l + 64 * r];
+        wave_fft<T, GM, true, R>(v, slice0 + wv * GSLICE, tw);
+    } else {
+        wave_fft_idle();
+    }
+    // ---- words of the cyclic convolution: point m = R n + w is (word 2m, word 2m + 1)
+    T* wd = reinterpret_cast<T*>(Z);
+    if (active) {
+        const int l = lane_id_fresh() & 63;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int m = R * (l + 64 * t) + wv;
+            wd[2 * m] = v[t].x;
+            wd[2 * m + 1] = v[t].y;
+        }
+    }
+    __syncthreads();
+    // ---- unpack + dequantize (eq. 16) + place (eq. 17), consecutive threads on consecutive outputs
+    float* out = a.out + it.o0;
+    const int nout = it.j_hi - it.j_lo;
+    if constexpr (MODE == MD_FULL32) {
+        for (int s = threadIdx.x; s < nout; s += NTH) {
+            out[s] = (float)wd[it.j_lo + s];
+            if (FIELDS) a.fields[it.o0 + s] = 0.0;
+        }
+    } else if constexpr (MODE == MD_SYM) {
+        // word m -> r~[2m + 1] = B(m), r~[2m] = Dm(m) + De(m - 1)
+        const double two_r = (double)(2 * c.R), R_ = (double)c.R;
+        for (int s = threadIdx.x; s < nout; s += NTH) {
+            const int j = it.j_lo + s;
+            const int m = j >> 1;
+            double Dm, B, De;
+            wsym_split((double)wd[m], two_r, R_, Dm, B, De);
+            double f = B;
+            if ((j & 1) == 0) {
+                double Dm1 = 0.0, B1 = 0.0, De1 = 0.0;
+                if (m >= 1) wsym_split((double)wd[m - 1], two_r, R_, Dm1, B1, De1);
+                f = Dm + De1;
+            }
+            out[s] = (float)(c.inv * f);
+            if (FIELDS) a.fields[it.o0 + s] = f;
+        }
+    } else {
+        // local output j = base_off + q Tit + word  <->  word = j - base_off - q Tit in [N-1, lw)
+        const double two_r = (double)(2 * c.R);
+        for (int s = threadIdx.x; s < nout; s += NTH) {
+            const int jj = it.j_lo + s - base_off;  // = q Tit + word
+            int q = 0;
+            int wdx = jj;
+#pragma unroll
+            for (int qq = 1; qq < MM; ++qq)
+                if (jj - qq * Tit >= N - 1) {
+                    q = qq;
+                    wdx = jj - qq * Tit;
+                }
+            double x = (double)wd[wdx];
+            double d = 0.0;
+#pragma unroll
+            for (int qq = 0; qq < MM; ++qq) {
+                const double dq = rint(x);
+                x = (x - dq) * two_r;
+                if (qq == q) d = dq;
+            }
+            out[s] = (float)(c.inv * d);
+            if (FIELDS) a.fields[it.o0 + s] = d;
+        }
+    }
+}
+
+template <int RS, int RA2, int RA3, int RF, int MASK>
+struct GroupShape {
+    static constexpr int r(int m) {
+        return m == MD_SYM ? RS : (m == MD_ASYM2 ? RA2 : (m == MD_ASYM3 ? RA3 : RF));
+    }
+    static constexpr int used(int m) { return ((MASK >> m) & 1) ? r(m) : 0; }
+    static constexpr int mx(int x, int y) { return x > y ? x : y; }
+    static constexpr int NW = mx(mx(used(MD_SYM), used(MD_ASYM2)), mx(used(MD_ASYM3), used(MD_FULL32)));
+    static constexpr size_t bytes(int m) {
+        return !((MASK >> m) & 1) ? 0
+               : m == MD_FULL32   ? group_lds_bytes<RF, float>()
+               : m == MD_SYM      ? group_lds_bytes<RS, double>()
+               : m == MD_ASYM2    ? group_lds_bytes<RA2, double>()
+                                  : group_lds_bytes<RA3, double>();
+    }
+    static constexpr size_t mxs(size_t x, size_t y) { return x > y ? x : y; }
+    static constexpr size_t WIN = 4 * (2 * (size_t)GM * RF + 4);  // window + sentinels (W_block <= 2 M_fp32)
+    static constexpr size_t LDS = mxs(mxs(mxs(bytes(MD_SYM), bytes(MD_ASYM2)), mxs(bytes(MD_ASYM3), bytes(MD_FULL32))), WIN);
+};
+
+template <int RS, int RA2, int RA3, int RF, int MASK, bool FIELDS>
+__global__ void __launch_bounds__((64 * GroupShape<RS, RA2, RA3, RF, MASK>::NW)) k_fftg(RunArgs a) {
+    using G = GroupShape<RS, RA2, RA3, RF, MASK>;
+    constexpr int NW = G::NW;
+    constexpr int NTH = 64 * NW;
+    __shared__ __attribute__((aligned(16))) char lds[G::LDS];
+    __shared__ double red[3 * NW];
+    const int64_t item = blockIdx.x;
+    if (item >= a.P + 1) return;
+    const WItem it = wave_make_item(a, item);
+    const WStats st = group_load_window<NTH>(a, it, reinterpret_cast<float*>(lds) + 1, red);
+    const WChoice c = wave_choose(a, st);
+    if (a.info && item < a.P && threadIdx.x == 0) {
+        apx_block_info b;
+        b.mode = c.mode;
+        b.flags = c.flags;
+        b.Sq = c.S;
+        b.Kq = c.K;
+        b.rmax = c.R;
+        b.cs = c.cs;
+        b.smax = st.smax;
+        b.rms = sqrt(st.sumsq / (double)a.W_block);
+        b.snr_pred_db = c.snr_db;
+        a.info[it.w] = b;
+    }
+    const bool zero = (c.flags & APX_FLAG_ZERO) && c.mode != MD_FULL32;
+    if ((c.flags & APX_FLAG_NONFINITE) || zero || it.j_hi <= it.j_lo) {
+        const float v = (c.flags & APX_FLAG_NONFINITE) ? NAN : 0.0f;
+        for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NTH) {
+            a.out[it.o0 + (j - it.j_lo)] = v;
+            if (FIELDS) a.fields[it.o0 + (j - it.j_lo)] = 0.0;
+        }
+        return;
+    }
+    if constexpr ((MASK >> MD_SYM) & 1)
+        if (c.mode == MD_SYM) group_item<MD_SYM, RS, NW, FIELDS>(a, it, c, lds);
+    if constexpr ((MASK >> MD_ASYM2) & 1)
+        if (c.mode == MD_ASYM2) group_item<MD_ASYM2, RA2, NW, FIELDS>(a, it, c, lds);
+    if constexpr ((MASK >> MD_ASYM3) & 1)
+        if (c.mode == MD_ASYM3) group_item<MD_ASYM3, RA3, NW, FIELDS>(a, it, c, lds);
+    if constexpr ((MASK >> MD_FULL32) & 1)
+        if (c.mode == MD_FULL32) group_item<MD_FULL32, RF, NW, FIELDS>(a, it, c, lds);
+}
+
+// Compiled group sets: complex points per mode (sym, asym2, asym3, fp32), each a multiple of 512.
+#define APX_GROUP_SETS(X)         \
+    X(1024, 1536, 1024, 2048)     \
+    X(1024, 1536, 1536, 2048)     \
+    X(512, 1024, 512, 1024)       \
+    X(512, 1024, 1024, 1024)
+
+bool group_supported(int ms, int ma2, int ma3, int mf) {
+#define APX_CHECK(a_, b_, c_, d_) \
+    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return true;
+    APX_GROUP_SETS(APX_CHECK)
+#undef APX_CHECK
+    return false;
+}
+
+template <int A, int B, int C, int D>
+static hipError_t launch_gset(const RunArgs& a, unsigned grid, hipStream_t st) {
+    constexpr int RS = A / GM, RA2 = B / GM, RA3 = C / GM, RF = D / GM;
+    constexpr int ALL = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_ASYM3) | (1 << MD_FULL32);
+    constexpr int AUTO = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_FULL32);
+#define APX_G(MASK_, FIELDS_)                                                                                 \
+    hipLaunchKernelGGL((k_fftg<RS, RA2, RA3, RF, MASK_, FIELDS_>), dim3(grid),                               \
+                       dim3(64 * GroupShape<RS, RA2, RA3, RF, MASK_>::NW), 0, st, a)
+    if (a.fields) {
+        APX_G(ALL, true);
+    } else {
+        switch (a.mode) {
+            case MD_SYM: APX_G(1 << MD_SYM, false); break;
+            case MD_ASYM2: APX_G(1 << MD_ASYM2, false); break;
+            case MD_ASYM3: APX_G(1 << MD_ASYM3, false); break;
+            case MD_FULL32: APX_G(1 << MD_FULL32, false); break;
+            default: APX_G(AUTO, false); break;
+        }
+    }
+#undef APX_G
+    return hipGetLastError();
+}
+
+hipError_t launch_fftg(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st) {
+    const unsigned grid = (unsigned)(a.P + 1);
+#define APX_LAUNCH(a_, b_, c_, d_) \
+    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return launch_gset<a_, b_, c_, d_>(a, grid, st);
+    APX_GROUP_SETS(APX_LAUNCH)
 #undef APX_LAUNCH
     return hipErrorInvalidValue;
 }

@@ -90,6 +90,9 @@ size_t td_lds_bytes(int mode, int N_odd, int W_block, int T2, int T3);
 hipError_t upload_dft_constants(const double2* w32, const double2* w24);
 bool wave_supported(int ms, int ma2, int ma3, int mf);
 hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st);
+// group-of-waves FFT core (fftw.hip): sizes are multiples of 512 points
+bool group_supported(int ms, int ma2, int ma3, int mf);
+hipError_t launch_fftg(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st);
 hipError_t launch_coef(const double* h, int32_t nh, int32_t M, const double2* twF, double2* coef, hipStream_t st);
 hipError_t launch_coef32(const double* h, int32_t nh, int32_t M, const double2* twF, float2* coef, hipStream_t st);
 int fft_max_logF();

@@ -124,7 +124,9 @@ def test_c1_full_precision_fp64(ctx):
 
 
 # ------------------------------------------------------------------------- FFT core, small
-VARIANTS = {"block": apx.FFT_BLOCK, "wave": apx.FFT_WAVE}
+VARIANTS = {"block": apx.FFT_BLOCK, "wave": apx.FFT_WAVE, "group": apx.FFT_GROUP}
+# shapes whose transform sizes the group core is compiled for (multiples of 512 points)
+GROUP_SHAPES = [(4097, 129, 2048), (12000, 300, 2048), (40000, 1024, 4096), (9001, 1000, 4096)]
 
 
 @pytest.mark.parametrize("variant", ["block", "wave"])
@@ -137,6 +139,40 @@ def test_fft_core_packed_small(ctx, mode, L, N, Wb, variant):
     S = O.max_q(mode, N if N % 2 else N + 1)
     got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "fft", S, S, variant=VARIANTS[variant])
     _check_packed(s, k, Wb, mode, S, got, fields, info)
+
+
+@pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3])
+@pytest.mark.parametrize("L,N,Wb", GROUP_SHAPES)
+def test_fft_group_packed(ctx, mode, L, N, Wb):
+    _say("case: FFT core, group", mode, L, N, Wb)
+    s, k = synth.ar1(L, 31 + N), synth.hann_lowpass(N, 0.2)
+    S = O.max_q(mode, N if N % 2 else N + 1)
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "fft", S, S, variant=apx.FFT_GROUP)
+    _check_packed(s, k, Wb, mode, S, got, fields, info)
+
+
+def test_fft_group_fp32_and_edges(ctx):
+    for L, N, Wb in GROUP_SHAPES:
+        _say("case: FP32 group", L, N, Wb)
+        s, k = synth.ar1(L, 6), synth.hann_lowpass(N, 0.1)
+        got, _, _ = _run_fixed(ctx, s, k, Wb, apx.APX_FULL_FP32, "fft", variant=apx.FFT_GROUP)
+        err = np.abs(got.astype(np.float64) - O.conv_direct(s, k))
+        assert np.all(err <= _fp32_bound(s, k, Wb, "fft")), (L, N, Wb, float(np.max(err)))
+    _say("case: zero / non-finite blocks, group")
+    s = synth.gaussian(30000, 7)
+    s[5000:9000] = 0.0
+    s[20000] = np.inf
+    k = synth.uniform(129, 8)
+    got, fields, info = _run_fixed(ctx, s, k, 2048, O.ASYM2, "fft", variant=apx.FFT_GROUP)
+    S = O.max_q(O.ASYM2, 129)
+    ref = O.conv_blocked(s, k, 2048, O.fixed_params(s, k, 2048, O.ASYM2, S, S))
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    fin = ~np.isnan(ref)
+    assert np.array_equal(got[fin], ref[fin])
+    assert np.any(info["flags"] & apx.APX_FLAG_NONFINITE) and np.any(info["flags"] & apx.APX_FLAG_ZERO)
+    with pytest.raises(apx.ApxError) as e:
+        _run_fixed(ctx, s, k[:31], 256, O.SYM, "fft", variant=apx.FFT_GROUP)
+    assert e.value.status == apx.APX_E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3])
@@ -220,7 +256,7 @@ def c2():
     return s, k
 
 
-@pytest.mark.parametrize("variant", ["block", "wave"])
+@pytest.mark.parametrize("variant", ["block", "wave", "group"])
 @pytest.mark.parametrize("mode,S", [(O.ASYM2, 205), (O.SYM, 9), (O.ASYM3, 9)])
 def test_c2_fft_full_size(ctx, c2, mode, S, variant):
     _say("case: C2 full size FFT", variant, mode, S)
