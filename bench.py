@@ -37,6 +37,9 @@ WORKLOADS = {
     "c5": dict(name="serving: Poisson arrivals at 2000 req/s for 10 s, L log-uniform in [2^12, 2^22], N log-uniform "
                     "in [16, 4096] (32 sizes, 128 kernels per size), SNR target in {30, 40, 50} dB, admission by a "
                     "32 GiB HBM budget, resident kernels"),
+    "c1sweep": dict(name="time-domain sweep: L=2^22 N(0,1) signal, U(-1,1) kernels N in {64,128,256,512,1024}, "
+                         "W_block = max(2N, 1024) + N + 1; symmetric and asymmetric M=2 at the largest S_q=K_q, FP32, "
+                         "FP64"),
     "c1": dict(L=65536, N=64, Wb=1024, snr=None, core="td",
                name="time-domain overlap-save convolution: L=65536 N(0,1), N=64 U(-1,1), W_block=1024, "
                     "asymmetric M=2 at 8 bits (S_q=K_q=127)"),
@@ -77,6 +80,8 @@ def main():
         return bench_c4(args, wl)
     if args.workload == "c5":
         return bench_c5(args, wl)
+    if args.workload == "c1sweep":
+        return bench_c1sweep(args, wl)
     dev = torch.device("cuda:0")
     L, N, Wb = wl["L"], wl["N"], wl["Wb"]
     if args.workload == "c2":
@@ -332,7 +337,6 @@ def bench_c4(args, wl):
     the error against FP64 per channel on sampled outputs."""
     import torch
 
-    import oracle as O
     from paper_1201_3018_amd import apx, synth
     dev = torch.device("cuda:0")
     C, L, F, N = 256, 1 << 20, 32, 512
@@ -422,6 +426,7 @@ def bench_c4(args, wl):
         "speedup_over_fp32_vector": ms32 / head["ms_per_step"],
     }
     if not args.no_cpu:
+        import oracle as O
         t0 = time.perf_counter()
         n = 0
         f = 0
@@ -524,6 +529,71 @@ def bench_c5(args, wl, duration: float = 10.0, rate: float = 2000.0):
         "server": st,
     }
     print(json.dumps(res), flush=True)
+
+
+def bench_c1sweep(args, wl):
+    """Time-domain core across kernel lengths: per mode, output samples/s, with the measured SNR
+    of every mode against the FP64 path on the first 2^18 outputs.  FMAs per output: FP32 and
+    FP64 N, asymmetric M=2 N/2, symmetric ceil(N/2)/2 (one packed word carries two outputs)."""
+    import torch
+
+    from paper_1201_3018_amd import apx, synth
+    dev = torch.device("cuda:0")
+    L = 1 << 22
+    s = synth.gaussian(L, 1001)
+    ts = torch.from_numpy(s).to(dev)
+    ctx = apx.Context(0)
+    rows = []
+    steps = max(1, min(args.steps, 20))
+    for N in (64, 128, 256, 512, 1024):
+        No = N + 1 - N % 2
+        Wb = max(2 * No, 1024) + No + 1
+        k = synth.uniform(N, 1002 + N)
+        tk = torch.from_numpy(k).to(dev)
+        out = torch.empty(L + N - 1, dtype=torch.float32, device=dev)
+        ref = None
+        row = {"N": N, "W_block": Wb}
+        for name, mode in (("fp64", apx.APX_FULL_FP64), ("fp32", apx.APX_FULL_FP32), ("sym", apx.APX_SYM),
+                           ("asym2", apx.APX_ASYM2)):
+            kern = apx.Kernel(ctx, tk, Wb, mode=mode, core=apx.APX_CORE_TIME)
+            kern.run(ts, out=out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                kern.run(ts, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            r = out[: 1 << 18].cpu().numpy().astype(np.float64)
+            if name == "fp64":
+                ref = r
+                snr = float("inf")
+            else:
+                e = float(np.sum((r - ref) ** 2))
+                snr = float("inf") if e == 0 else 10 * math.log10(float(np.sum(ref ** 2)) / e)
+            row[name] = {"ms": ms, "samples_per_s": (L + N - 1) / (ms * 1e-3), "snr_db": snr}
+            kern.close()
+        row["sym_over_fp64"] = row["fp64"]["ms"] / row["sym"]["ms"]
+        row["sym_over_fp32"] = row["fp32"]["ms"] / row["sym"]["ms"]
+        row["asym2_over_fp32"] = row["fp32"]["ms"] / row["asym2"]["ms"]
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    big = rows[-1]
+    fl = 2.0 * (L + 1023) * ((1025 + 1) // 2) / 2  # symmetric: ceil(N/2) FMAs per packed word of 2 outputs
+    ach = fl / (big["sym"]["ms"] * 1e-3) / 1e12
+    res = {
+        "metric": "time-domain output samples/s, symmetric packing vs FP64 and FP32, 1 GPU",
+        "value": big["sym"]["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": big["sym"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic", "config": {"workload": wl["name"], "L": L},
+        "roofline": {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / FP64_VECTOR_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_td symmetric, N=1024", "flops_per_launch": fl},
+        "sweep": rows,
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
 
 
 def measured_traffic(workload: str):
