@@ -132,6 +132,18 @@ def main():
 
     ms_packed = timed(kern, args.steps, args.warmup)
     ms_full = timed(full, args.steps, args.warmup)
+    # context: the same path at other SNR targets (lower targets admit the symmetric packing)
+    snr_sweep = []
+    if args.workload == "c2":
+        for target in (20.0, 30.0, 50.0):
+            kt = apx.Kernel(ctx, tk, Wb, mode=apx.APX_AUTO_SNR, core=core, snr_min_db=target, calib_db=calib)
+            ms_t = timed(kt, max(1, args.steps // 4), 2)
+            _, inf_t = kt.run(ts[0], info=True)
+            torch.cuda.synchronize()
+            m_t = np.bincount(apx.block_info(inf_t)["mode"], minlength=4)
+            snr_sweep.append({"snr_min_db": target, "ms_per_step": ms_t, "over_fp32": ms_full / ms_t,
+                              "blocks": {"full_fp32": int(m_t[0]), "sym": int(m_t[1]), "asym2": int(m_t[2])}})
+            kt.close()
 
     # per-call latency as a caller sees it (enqueue + completion), packed path
     lat = []
@@ -218,6 +230,8 @@ def main():
         "snr_db": {"min": float(np.min(snr_p)), "mean": float(np.mean(snr_p[np.isfinite(snr_p)]))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
     }
+    if snr_sweep:
+        res["snr_sweep"] = snr_sweep
     if args.copy_probe:
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)

@@ -340,7 +340,7 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
             double ratio = wsnr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
             if (ratio >= thr) {
                 c.mode = m;
-                c.snr_db = 10.0 * log10(ratio) + calib;
+                if (a.info) c.snr_db = 10.0 * log10(ratio) + calib;  // reported only
                 break;
             }
         }
@@ -353,7 +353,7 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
         const double ck = s1 ? ks.ck[1] : (s2 ? ks.ck[2] : ks.ck[3]);
         c.cs = st.smax == 0.0 ? 0.0 : (double)c.S / st.smax;
         c.inv = 1.0 / (c.cs * ck);
-        if (a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
+        if (a.info && a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
             c.snr_db = 10.0 * log10(wsnr_ratio(rms, st.smax, ks.krms, ks.kmax, c.S, c.K));
     } else {
         c.S = c.K = 0;
@@ -368,11 +368,14 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
 
 
 
-// exact digits of a symmetric-packed word: rb = 2R Dm + B + eps De, |B| <= R
-__device__ __forceinline__ void wsym_split(double rb, double two_r, double R, double& Dm, double& B, double& De) {
+// exact digits of a symmetric-packed word: rb = 2R Dm + B + eps De, |B| <= R.  The quotient
+// estimate uses the rounded reciprocal of 2R; it can be off by one only, which the range
+// corrections below undo, so the digits are exact.
+__device__ __forceinline__ void wsym_split(double rb, double two_r, double inv_two_r, double R, double& Dm, double& B,
+                                           double& De) {
     const double I = rint(rb);
     De = rint((rb - I) * two_r);
-    double q = rint(I / two_r);
+    double q = rint(I * inv_two_r);
     double b = I - q * two_r;
     if (b > R) {
         q += 1.0;
@@ -523,19 +526,18 @@ __device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, con
         }
         sbase = it.j_lo;
     } else if constexpr (MODE == MD_SYM) {
-        const double two_r = (double)(2 * c.R), R = (double)c.R;
+        const double two_r = (double)(2 * c.R), R = (double)c.R, inv_two_r = 1.0 / two_r;
+        double de_last = 0.0;  // side digit of word 2n - 1 for lane 0: lane 63's odd word at t - 1
 #pragma unroll
         for (int t = 0; t < E; ++t) {
             const int n = l + 64 * t;
-            // packed result at word 2n-1 (the odd word of point n-1)
-            const double up = __shfl_up(v[t].y, 1);
-            const double wrap = (t > 0) ? __shfl(v[t > 0 ? t - 1 : 0].y, 63) : 0.0;
-            const double prev = (l == 0) ? wrap : up;
-            double Dm0, B0, De0, Dm1, B1, De1, Dmp, Bp, Dep;
-            wsym_split(v[t].x, two_r, R, Dm0, B0, De0);  // word 2n
-            wsym_split(v[t].y, two_r, R, Dm1, B1, De1);  // word 2n+1
-            wsym_split(prev, two_r, R, Dmp, Bp, Dep);    // word 2n-1
-            if (n == 0) Dep = 0.0;
+            double Dm0, B0, De0, Dm1, B1, De1;
+            wsym_split(v[t].x, two_r, inv_two_r, R, Dm0, B0, De0);  // word 2n
+            wsym_split(v[t].y, two_r, inv_two_r, R, Dm1, B1, De1);  // word 2n+1
+            // side digit of word 2n-1 (the odd word of point n-1): neighbour lane, or the wrap
+            const double up = __shfl_up(De1, 1);
+            const double Dep = (n == 0) ? 0.0 : ((l == 0) ? de_last : up);
+            de_last = __shfl(De1, 63);
             const double f0 = Dm0 + Dep, f1 = B0, f2 = Dm1 + De0, f3 = B1;  // r~[4n .. 4n+3]
             if (FIELDS) {
                 const double fv[4] = {f0, f1, f2, f3};
@@ -925,16 +927,16 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
         }
     } else if constexpr (MODE == MD_SYM) {
         // word m -> r~[2m + 1] = B(m), r~[2m] = Dm(m) + De(m - 1)
-        const double two_r = (double)(2 * c.R), R_ = (double)c.R;
+        const double two_r = (double)(2 * c.R), R_ = (double)c.R, inv_two_r = 1.0 / two_r;
         for (int s = threadIdx.x; s < nout; s += NTH) {
             const int j = it.j_lo + s;
             const int m = j >> 1;
             double Dm, B, De;
-            wsym_split((double)wd[m], two_r, R_, Dm, B, De);
+            wsym_split((double)wd[m], two_r, inv_two_r, R_, Dm, B, De);
             double f = B;
             if ((j & 1) == 0) {
                 double Dm1 = 0.0, B1 = 0.0, De1 = 0.0;
-                if (m >= 1) wsym_split((double)wd[m - 1], two_r, R_, Dm1, B1, De1);
+                if (m >= 1) wsym_split((double)wd[m - 1], two_r, inv_two_r, R_, Dm1, B1, De1);
                 f = Dm + De1;
             }
             out[s] = (float)(c.inv * f);

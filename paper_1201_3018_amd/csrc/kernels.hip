@@ -189,7 +189,7 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
             double ratio = snr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
             if (ratio >= thr) {
                 c.mode = m;
-                c.snr_db = 10.0 * log10(ratio) + calib;
+                if (a.info) c.snr_db = 10.0 * log10(ratio) + calib;  // reported only
                 break;
             }
         }
@@ -203,7 +203,7 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
         const double ck = s1 ? ks.ck[1] : (s2 ? ks.ck[2] : ks.ck[3]);
         c.cs = st.smax == 0.0 ? 0.0 : (double)c.S / st.smax;
         c.inv = 1.0 / (c.cs * ck);
-        if (a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
+        if (a.info && a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
             c.snr_db = 10.0 * log10(snr_ratio(rms, st.smax, ks.krms, ks.kmax, c.S, c.K));
     } else {
         c.S = c.K = 0;
@@ -299,11 +299,11 @@ __device__ __forceinline__ double sq_at(const RunArgs& a, const Item& it, double
 struct SymDigits {
     double Dm, B, De;
 };
-__device__ __forceinline__ SymDigits sym_split(double rb, double two_r, double R) {
+__device__ __forceinline__ SymDigits sym_split(double rb, double two_r, double inv_two_r, double R) {
     SymDigits d;
     double I = rint(rb);
     d.De = rint((rb - I) * two_r);
-    double q = rint(I / two_r);
+    double q = rint(I * inv_two_r);  // off by at most one; the range corrections below undo it
     double B = I - q * two_r;
     if (B > R) {
         q += 1.0;
@@ -331,13 +331,13 @@ __device__ __forceinline__ SymDigits sym_split(double rb, double two_r, double R
 template <typename Fn, typename Sink = StoreSink>
 __device__ __forceinline__ void sym_unpack_store(const RunArgs& a, const Item& it, const Choice& c, Fn rbar,
                                                  Sink&& sk = Sink{}) {
-    const double two_r = (double)(2 * c.R), R = (double)c.R;
+    const double two_r = (double)(2 * c.R), R = (double)c.R, inv_two_r = 1.0 / two_r;
     const int m_lo = it.j_lo >> 1, m_hi = (it.j_hi + 1) >> 1;
     for (int m = m_lo + threadIdx.x; m < m_hi; m += NT) {
-        SymDigits cur = sym_split(rbar(m), two_r, R);
+        SymDigits cur = sym_split(rbar(m), two_r, inv_two_r, R);
         const int j0 = 2 * m, j1 = 2 * m + 1;
         if (j0 >= it.j_lo && j0 < it.j_hi) {
-            double de_prev = (m >= 1) ? sym_split(rbar(m - 1), two_r, R).De : 0.0;
+            double de_prev = (m >= 1) ? sym_split(rbar(m - 1), two_r, inv_two_r, R).De : 0.0;
             sk.put(a, it, j0, cur.Dm + de_prev, c.inv);
         }
         if (j1 >= it.j_lo && j1 < it.j_hi) sk.put(a, it, j1, cur.B, c.inv);

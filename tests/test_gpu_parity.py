@@ -185,6 +185,21 @@ def test_td_core_packed_small(ctx, mode, L, N, Wb):
     _check_packed(s, k, Wb, mode, S, got, fields, info)
 
 
+@pytest.mark.parametrize("mode", [O.SYM, O.ASYM2])
+@pytest.mark.parametrize("N", [128, 257, 512, 1024])
+def test_td_core_long_kernels(ctx, mode, N):
+    """Time-domain core at the kernel lengths of the time-domain sweep (W_block = max(2N, 1024)
+    + N + 1), several blocks and a ragged tail."""
+    No = N if N % 2 else N + 1
+    Wb = max(2 * No, 1024) + No + 1
+    L = 3 * (Wb - No - 1) + 777
+    _say("case: TD long kernel", mode, L, N, Wb)
+    s, k = synth.gaussian(L, 41 + N), synth.uniform(N, 42 + N)
+    S = O.max_q(mode, No)
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "td", S, S)
+    _check_packed(s, k, Wb, mode, S, got, fields, info)
+
+
 @pytest.mark.parametrize("core,variant", [("td", "block"), ("fft", "block"), ("fft", "wave")])
 def test_fp32_small_shapes(ctx, core, variant):
     for L, N, Wb in [(9000, 101, 512), (300, 33, 128), (4097, 129, 2048), (1000, 64, 1024), (40000, 1024, 4096)]:
