@@ -370,24 +370,49 @@ constexpr int RB = 8;    // consecutive outputs per thread
 constexpr int KUN = 8;   // taps per unrolled step (tap arrays are zero padded to a multiple)
 
 // r[m - mlo] = sum_n x[m - n] kt[n] for m in [mlo, mhi).  x: LDS, logical index i at x[i],
-// valid (zero filled) for i in [mlo - npad - 8, mhi + RB).
+// valid (zero filled) for i in [mlo - npad - 8, mhi + RB).  Each thread owns RB = 8 consecutive
+// outputs m0 .. m0+7 and walks the taps in steps of 8: step n0 reads x[m0 - n0 - 8 .. m0 - n0 + 7],
+// the chunk x[m0 - n0 .. m0 - n0 + 7] it shares with the previous step stays in registers, so one
+// chunk of 8 samples is read per 64 FMAs (the two chunk registers swap roles every step).  The
+// FMA order per output is n = 0, 1, 2, ... as in the plain sum.
+template <typename T>
+__device__ __forceinline__ void td_step(const T* hi, const T* lo, const T* kt, int n0, T* acc) {
+    // hi[e] = x[m0 - n0 + e], lo[e] = x[m0 - n0 - 8 + e]; output i, tap n0 + t reads x[m0 + i - n0 - t]
+#pragma unroll
+    for (int t = 0; t < KUN; ++t) {
+        const T kv = ld_uniform(kt, n0 + t);
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int e = i - t;
+            acc[i] = fma(e >= 0 ? hi[e] : lo[8 + e], kv, acc[i]);
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void td_core(const T* x, const T* kt, int npad, int mlo, int mhi, T* r) {
+    static_assert(RB == 8 && KUN == 8, "the chunk walk assumes 8 outputs and 8 taps per step");
     for (int m0 = mlo + RB * threadIdx.x; m0 < mhi; m0 += RB * NT) {
         T acc[RB];
 #pragma unroll
         for (int i = 0; i < RB; ++i) acc[i] = (T)0;
         const T* xp = x + m0;
-        for (int n0 = 0; n0 < npad; n0 += KUN) {
-            T xv[RB + KUN - 1];
+        T c0[8], c1[8];
 #pragma unroll
-            for (int i = 0; i < RB + KUN - 1; ++i) xv[i] = xp[i - (KUN - 1) - n0];
+        for (int e = 0; e < 8; ++e) c0[e] = xp[e];
+        int n0 = 0;
+        for (; n0 + 2 * KUN <= npad; n0 += 2 * KUN) {
 #pragma unroll
-            for (int t = 0; t < KUN; ++t) {
-                const T kv = ld_uniform(kt, n0 + t);
+            for (int e = 0; e < 8; ++e) c1[e] = xp[e - n0 - 8];
+            td_step<T>(c0, c1, kt, n0, acc);
 #pragma unroll
-                for (int i = 0; i < RB; ++i) acc[i] = fma(xv[i - t + KUN - 1], kv, acc[i]);
-            }
+            for (int e = 0; e < 8; ++e) c0[e] = xp[e - n0 - 16];
+            td_step<T>(c1, c0, kt, n0 + KUN, acc);
+        }
+        if (n0 < npad) {  // npad is a multiple of 8: one step left
+#pragma unroll
+            for (int e = 0; e < 8; ++e) c1[e] = xp[e - n0 - 8];
+            td_step<T>(c0, c1, kt, n0, acc);
         }
 #pragma unroll
         for (int i = 0; i < RB; ++i)
