@@ -8,7 +8,7 @@ S_q = K_q = 8).  A step is one pass of the whole path over one input signal; the
 over distinct device buffers (more than the 256 MB last-level cache holds) so every step reads
 its input from HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c1|...] [--no-cpu]
 """
 import argparse
 import json
@@ -40,6 +40,10 @@ WORKLOADS = {
     "c1sweep": dict(name="time-domain sweep: L=2^22 N(0,1) signal, U(-1,1) kernels N in {64,128,256,512,1024}, "
                          "W_block = max(2N, 1024) + N + 1; symmetric and asymmetric M=2 at the largest S_q=K_q, FP32, "
                          "FP64"),
+    "sweep": dict(name="paper sweep (Section IV.A, synthetic): L=2^23, U[-128,128] signal and kernel; block sizes "
+                       "W in {2,4,8,16,32,64}x2^10 at N=800, and N in {32..8192} at W=8x2^10; FFT core; symmetric and "
+                       "asymmetric M=3 at S_q=K_q=16, asymmetric M=2 at 256 (the paper's settings) and at the largest "
+                       "in-bound S_q=K_q; FP32 comparator"),
     "c1": dict(L=65536, N=64, Wb=1024, snr=None, core="td",
                name="time-domain overlap-save convolution: L=65536 N(0,1), N=64 U(-1,1), W_block=1024, "
                     "asymmetric M=2 at 8 bits (S_q=K_q=127)"),
@@ -82,6 +86,8 @@ def main():
         return bench_c5(args, wl)
     if args.workload == "c1sweep":
         return bench_c1sweep(args, wl)
+    if args.workload == "sweep":
+        return bench_sweep(args, wl)
     dev = torch.device("cuda:0")
     L, N, Wb = wl["L"], wl["N"], wl["Wb"]
     if args.workload == "c2":
@@ -443,15 +449,15 @@ def bench_c4(args, wl):
         import oracle as O
         t0 = time.perf_counter()
         n = 0
-        f = 0
-        while time.perf_counter() - t0 < 10.0 and f < F:
-            O.conv_direct(x[0], h[f])
+        pairs = 0
+        while time.perf_counter() - t0 < 10.0 and pairs < C * F:
+            O.conv_direct(x[pairs // F], h[pairs % F])
             n += Lout
-            f += 1
+            pairs += 1
         dt = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": n / dt, "unit": "samples/s", "cores": O.num_threads(), "kind": "oracle",
-                               "sample": f"channel 0 x {f} filters ({n} outputs), FP64 direct convolution, "
-                                         f"{dt:.1f} s"}
+                               "sample": f"first {pairs} (channel, filter) rows ({n} outputs), FP64 direct "
+                                         f"convolution, {dt:.1f} s"}
     print(json.dumps(res), flush=True)
     ctx.close()
 
@@ -610,6 +616,113 @@ def bench_c1sweep(args, wl):
     ctx.close()
 
 
+def bench_sweep(args, wl):
+    """The paper's throughput experiments (Section IV.A) on synthetic data, on the FFT core.
+
+    E1: block size W (outputs per block; W_block = W + N_odd + 1) over {2,...,64} x 2^10 at N = 800.
+    E2: kernel length N over {32, ..., 8192} at W = 8 x 2^10 (the paper's 32 x 2^10 needs
+    transforms longer than one workgroup's LDS for every mode but symmetric packing).
+    Modes: the paper's settings (symmetric and asymmetric M=3 at S_q = K_q = 16, asymmetric M=2
+    at 256; these exceed the Table 1 bounds at N = 800, so they run with allow_unsafe and their
+    SNR includes any unpacking errors), the largest in-bound S_q = K_q of each mode, and the FP32
+    comparator.  Each point reports output samples/s and the SNR against the exact convolution
+    (FP64 FFT on the host, from the same FP32 inputs).  Points whose transform does not fit the
+    FFT core are reported as unsupported."""
+    import torch
+
+    from paper_1201_3018_amd import apx, synth
+    dev = torch.device("cuda:0")
+    L = 1 << 23
+    s = synth.uniform(L, 6001) * np.float32(128.0)
+    ts = torch.from_numpy(s).to(dev)
+    ctx = apx.Context(0)
+    steps = max(1, min(args.steps, 10))
+    modes = [("fp32", apx.APX_FULL_FP32, 0, False), ("sym16", apx.APX_SYM, 16, True),
+             ("asym3_16", apx.APX_ASYM3, 16, True), ("asym2_256", apx.APX_ASYM2, 256, True),
+             ("sym_max", apx.APX_SYM, 0, False), ("asym3_max", apx.APX_ASYM3, 0, False),
+             ("asym2_max", apx.APX_ASYM2, 0, False)]
+
+    def exact(k):
+        n = L + k.size - 1
+        nf = 1 << (n - 1).bit_length()
+        return np.fft.irfft(np.fft.rfft(s.astype(np.float64), nf) * np.fft.rfft(k.astype(np.float64), nf), nf)[:n]
+
+    def point(N, W, k, tk, ref):
+        No = N + 1 - N % 2
+        Wb = W + No + 1
+        row = {"N": N, "W": W, "W_block": Wb}
+        out = torch.empty(L + N - 1, dtype=torch.float32, device=dev)
+        for name, mode, q, unsafe in modes:
+            try:
+                kern = apx.Kernel(ctx, tk, Wb, mode=mode, core=apx.APX_CORE_FFT, Sq=q, Kq=q, allow_unsafe=unsafe)
+            except apx.ApxError as e:
+                row[name] = {"unsupported": str(e)}
+                continue
+            kern.run(ts, out=out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                kern.run(ts, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            r = out.cpu().numpy().astype(np.float64)
+            err = float(np.sum((r - ref) ** 2))
+            snr = float("inf") if err == 0 else 10 * math.log10(float(np.sum(ref ** 2)) / err)
+            ent = {"ms": round(ms, 4), "samples_per_s": (L + N - 1) / (ms * 1e-3), "snr_db": round(snr, 2)}
+            if q == 0 and mode != apx.APX_FULL_FP32:
+                d = kern.describe()
+                ent["kernel"] = d[:160]
+            row[name] = ent
+            kern.close()
+        if "ms" in row.get("fp32", {}):
+            for name, *_ in modes[1:]:
+                if "ms" in row[name]:
+                    row[name]["gain_pct_vs_fp32"] = round(100.0 * (row["fp32"]["ms"] / row[name]["ms"] - 1.0), 1)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        return row
+
+    e1 = []
+    k800 = synth.uniform(800, 6002) * np.float32(128.0)
+    ref800 = exact(k800)
+    tk800 = torch.from_numpy(k800).to(dev)
+    for W in (2, 4, 8, 16, 32, 64):
+        e1.append(point(800, W * 1024, k800, tk800, ref800))
+    e2 = []
+    for N in (32, 64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        kN = synth.uniform(N, 6100 + N) * np.float32(128.0)
+        W = 8 * 1024 if 2 * (N + 1) <= 8 * 1024 else 2 * (N + 1)
+        e2.append(point(N, W, kN, torch.from_numpy(kN).to(dev), exact(kN)))
+
+    # Table 2 analogue: min / max throughput gain over the E1 block sizes, mean SNR, per method
+    table2 = {}
+    for name, *_ in modes[1:]:
+        g = [r[name]["gain_pct_vs_fp32"] for r in e1 if "gain_pct_vs_fp32" in r.get(name, {})]
+        sn = [r[name]["snr_db"] for r in e1 if "snr_db" in r.get(name, {})]
+        if g:
+            table2[name] = {"min_gain_pct": min(g), "max_gain_pct": max(g), "mean_snr_db": round(float(np.mean(sn)), 2),
+                            "block_sizes": [r["W"] for r in e1 if "gain_pct_vs_fp32" in r.get(name, {})]}
+    head = next(r for r in e1 if r["W"] == 8192)
+    hs = head["sym_max"]
+    P = -(-L // head["W"])
+    bytes_launch = 4.0 * (L + P * (head["W_block"] - head["W"])) + 4.0 * (L + 799)
+    ach = bytes_launch / (hs["ms"] * 1e-3) / 1e9
+    res = {
+        "metric": "output samples/s per packing method vs the FP32 comparator (paper sweep, synthetic), 1 GPU",
+        "value": hs["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": hs["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic", "config": {"workload": wl["name"], "L": L},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "FFT core, symmetric packing at the largest in-bound S_q=K_q, N=800, W=8x2^10",
+                     "bytes_per_launch": bytes_launch},
+        "table2": table2, "e1": e1, "e2": e2,
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def measured_traffic(workload: str):
     """HBM bytes per launch of the packed kernel from the committed rocprofv3 counter summary,
     or None when the kernel sources changed since the counters were taken."""
@@ -640,14 +753,20 @@ def cpu_baseline(workload, s, k, Wb, wl, calib, outputs):
     (C loops, OpenMP over blocks) with the same block selection, whole signal."""
     import oracle as O
     t0 = time.perf_counter()
-    if workload == "c2":
-        ps = O.auto_params(s, k, Wb, wl["snr"], calib)
-    else:
-        ps = O.fixed_params(s, k, Wb, O.ASYM2, 127, 127)
-    O.conv_blocked(s, k, Wb, ps)
+    runs = 0
+    while True:  # the whole workload, repeated until about 10 s of CPU work
+        if workload == "c2":
+            ps = O.auto_params(s, k, Wb, wl["snr"], calib)
+        else:
+            ps = O.fixed_params(s, k, Wb, O.ASYM2, 127, 127)
+        O.conv_blocked(s, k, Wb, ps)
+        runs += 1
+        if time.perf_counter() - t0 >= 10.0:
+            break
     dt = time.perf_counter() - t0
-    return {"value": outputs / dt, "unit": "samples/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"whole workload ({outputs} outputs), selection + int64 block convolution, {dt:.2f} s"}
+    return {"value": runs * outputs / dt, "unit": "samples/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"whole workload ({outputs} outputs) x {runs}: selection + int64 block convolution, "
+                      f"{dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -132,19 +132,32 @@ void fill_twiddles(int F, double2* d) {
     }
 }
 
+// Entries after the F-entry table of a one-wave FFT size (F a multiple of 512): the radix-8
+// passes' twiddles in the order the lanes read them, W_F^{8 r k} at (r-1) E + k (k < E = F/64)
+// and then W_F^{r j} at 7 E + (r-1) F/8 + j (j < F/8), r = 1..7, copies of the table's values.
+int pass_table_len(int F) { return (F % 512 == 0) ? 7 * (F / 64) + 7 * (F / 8) : 0; }
+
 apx_status get_table(apx_ctx c, int F, double2** d, float2** f) {
     auto it = c->tables.find(F);
     if (it == c->tables.end()) {
-        std::vector<double2> hd(F);
-        std::vector<float2> hf(F);
+        const int n = F + pass_table_len(F);
+        std::vector<double2> hd(n);
+        std::vector<float2> hf(n);
         fill_twiddles(F, hd.data());
-        for (int i = 0; i < F; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
+        if (n > F) {
+            const int E = F / 64, F8 = F / 8;
+            for (int r = 1; r < 8; ++r) {
+                for (int k = 0; k < E; ++k) hd[F + (r - 1) * E + k] = hd[8 * r * k];
+                for (int j = 0; j < F8; ++j) hd[F + 7 * E + (r - 1) * F8 + j] = hd[r * j];
+            }
+        }
+        for (int i = 0; i < n; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
         double2* dd = nullptr;
         float2* ff = nullptr;
-        HIPCHK(hipMalloc((void**)&dd, F * sizeof(double2)));
-        HIPCHK(hipMalloc((void**)&ff, F * sizeof(float2)));
-        HIPCHK(hipMemcpy(dd, hd.data(), F * sizeof(double2), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(ff, hf.data(), F * sizeof(float2), hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc((void**)&dd, n * sizeof(double2)));
+        HIPCHK(hipMalloc((void**)&ff, n * sizeof(float2)));
+        HIPCHK(hipMemcpy(dd, hd.data(), n * sizeof(double2), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ff, hf.data(), n * sizeof(float2), hipMemcpyHostToDevice));
         it = c->tables.emplace(F, std::make_pair(dd, ff)).first;
     }
     if (d) *d = it->second.first;
@@ -233,6 +246,8 @@ apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
         HIPCHK(launch_fftg(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
     } else if (k->core == APX_CORE_FFT && k->wave) {
         HIPCHK(launch_fftw(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
+    } else if (k->core == APX_CORE_FFT && k->fft1_logmw > 0) {
+        HIPCHK(launch_fft1(a, k->params.mode, k->fft1_logmw, st));
     } else if (k->core == APX_CORE_FFT) {
         HIPCHK(launch_fft(a, k->logF, st));
     } else {
@@ -404,14 +419,30 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         for (int m = 0; m < 4; ++m) k->Fw[m] = fft_words;
     } else if (core == APX_CORE_FFT) {
         k->logF = std::max(ceil_log2(W_block), fft_min_logF());
-        if (k->logF > fft_max_logF()) {
+        // a fixed packed mode transforms only its own words: W_block / 2 (symmetric) or
+        // T + N - 1 (asymmetric), at the shortest power of two that holds them
+        const bool fixed_packed = p.mode >= APX_SYM && p.mode <= APX_ASYM3;
+        int own_logw = 0;
+        if (fixed_packed) {
+            const int words = (p.mode == MD_SYM) ? W_block / 2 : k->T[p.mode] + N_odd - 1;
+            own_logw = std::max(ceil_log2(words), fft_min_logF() - 1);
+            if (own_logw > fft_max_logF() || !fft1_supported(p.mode, own_logw - 1))
+                return fail(APX_E_UNSUPPORTED, "FFT core: %d packed words per block exceed %d", words,
+                            1 << fft_max_logF());
+        } else if (k->logF > fft_max_logF()) {
             return fail(APX_E_UNSUPPORTED, "FFT core supports W_block <= %d", 1 << fft_max_logF());
         }
-        const int F = 1 << k->logF;
-        k->Fw[0] = F;
-        k->Fw[MD_SYM] = F / 2;
-        k->Fw[MD_ASYM2] = F;
-        k->Fw[MD_ASYM3] = F;
+        if (k->logF <= fft_max_logF()) {
+            const int F = 1 << k->logF;
+            k->Fw[0] = F;
+            k->Fw[MD_SYM] = F / 2;
+            k->Fw[MD_ASYM2] = F;
+            k->Fw[MD_ASYM3] = F;
+        }
+        if (fixed_packed) {
+            k->fft1_logmw = own_logw - 1;
+            k->Fw[p.mode] = 1 << own_logw;
+        }
         // wave-per-block core: complex points per mode, if an instantiated size set covers them
         int need[4] = {W_block, W_block / 2, k->T[MD_ASYM2] + N_odd - 1, k->T[MD_ASYM3] + N_odd - 1};
         int wm[4];
@@ -512,7 +543,8 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             e = launch_coef32(k->kd, N_odd, k->wM[0], tF, k->coef32, st);
         }
     }
-    if (e == hipSuccess && core == APX_CORE_FFT && !k->wave && fft_words == 0) e = fft_set_lds(k->logF);
+    if (e == hipSuccess && core == APX_CORE_FFT && !k->wave && fft_words == 0)
+        e = k->fft1_logmw > 0 ? fft1_set_lds(p.mode, k->fft1_logmw) : fft_set_lds(k->logF);
     if (e != hipSuccess) {
         free_kernel(k);
         return fail(APX_E_DEVICE, "kernel preparation launch: %s", hipGetErrorString(e));
@@ -644,6 +676,9 @@ apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {
         n = snprintf(tmp, sizeof tmp, "core=fft kernel=%s<%d,%d,%d,%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d",
                      k->group ? "k_fftg" : "k_fftw", k->wM[1], k->wM[2], k->wM[3], k->wM[0], 2 * k->wM[0],
                      2 * k->wM[1], 2 * k->wM[2], 2 * k->wM[3]);
+    } else if (k->fft1_logmw > 0) {
+        n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_fft1<mode %d, %d points> words=%d", k->params.mode,
+                     1 << k->fft1_logmw, k->Fw[k->params.mode]);
     } else {
         n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_fft<%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d", k->logF,
                      k->Fw[0], k->Fw[1], k->Fw[2], k->Fw[3]);

@@ -14,6 +14,14 @@
 
 constexpr int LOGF_MAX_TABLE = 14;  // twiddle tables up to F = 16384
 
+namespace apx {
+// LDS FFT core for one fixed packed mode at its own transform length (2^logmw complex points,
+// kernels.hip)
+bool fft1_supported(int mode, int logmw);
+hipError_t fft1_set_lds(int mode, int logmw);
+hipError_t launch_fft1(const RunArgs& a, int mode, int logmw, hipStream_t st);
+}  // namespace apx
+
 using apx::KState;
 
 struct apx_ctx_s {
@@ -34,6 +42,7 @@ struct apx_kernel_s {
     apx_params params{};
     int core = APX_CORE_TIME;
     int logF = 0;
+    int fft1_logmw = 0;  // > 0: the fixed packed mode runs k_fft1 at 2^fft1_logmw complex points
     int32_t S[4] = {0, 0, 0, 0}, K[4] = {0, 0, 0, 0};
     int64_t R[4] = {0, 0, 0, 0};
     int32_t T[4] = {0, 0, 0, 0};

@@ -123,6 +123,12 @@ __device__ __forceinline__ void dftn(cx<T>* v) {
     else static_assert(R == 2, "unsupported in-register DFT size");
 }
 
+// row[off / sizeof(V)] for a wave-uniform row pointer and a per-lane byte offset below 4 GiB
+template <typename V>
+__device__ __forceinline__ V ld_row(const V* row, uint32_t off) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(row) + off);
+}
+
 // An opaque copy of the lane id (0..63 in every wave of the workgroup): address arithmetic derived from it cannot be shared between
 // phases, so nothing computed for one phase stays live (in registers) through the next.
 __device__ __forceinline__ int lane_id_fresh() {
@@ -133,16 +139,31 @@ __device__ __forceinline__ int lane_id_fresh() {
 
 // Complex FFT of M points by one wave: lane l holds v[r] = z[l + 64 r] on entry and
 // v[t] = Z[l + 64 t] on exit.  It passes WAVE_FFT_BARRIERS workgroup barriers (a wave of a
-// larger workgroup that has no transform to run passes the same number).  tw[t TS] = W_M^t.  Passes: radix E (= M/64, registers only), radix 8, radix 8.
+// larger workgroup that has no transform to run passes the same number).  Passes: radix E (= M/64, registers only), radix 8, radix 8.
 // The two exchanges use the wave's LDS slice in a padded layout, point i at i + floor(i/E)
 // (rows of E points padded by one: the strided writes of the first pass spread over the
-// banks); every address below is that mapping in closed form.  tw: W_M^t, t < M.
+// banks); every address below is that mapping in closed form.
+// Twiddles: TS > 1 reads W_M^t at tw[t TS] (a sub-transform of a longer table).  TS = 1 reads
+// the per-pass copies that follow the M-entry table: W_M^{8 r k} at tw[M + (r-1) E + k] and
+// W_M^{r j} at tw[M + 7 E + (r-1) M/8 + j], so that the 64 lanes of one load read adjacent
+// entries (a few cache lines) instead of entries r or 8 r apart.
 template <typename T, int M, bool INV, int TS = 1>
 __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw_of<T>::type* tw) {
     constexpr int E = M / 64;
     static_assert(E % 8 == 0, "points per lane must be a multiple of 8");
     constexpr int NB = E / 8;  // radix-8 butterflies per lane in passes B and C
     constexpr int S = E + 1;   // padded row
+    using TW = typename tw_of<T>::type;
+    // per-pass entries: a uniform row base plus the lane's unsigned 32-bit byte offset, so each
+    // load is one instruction on a scalar base (no 64-bit address arithmetic per load)
+    auto twB = [&](int r, int k) {
+        if constexpr (TS == 1) return ld_row(tw + M + (r - 1) * E, (uint32_t)k * (uint32_t)sizeof(TW));
+        else return tw[r * k * 8 * TS];
+    };
+    auto twC = [&](int r, int j) {
+        if constexpr (TS == 1) return ld_row(tw + M + 7 * E + (r - 1) * (M / 8), (uint32_t)j * (uint32_t)sizeof(TW));
+        else return tw[r * j * TS];
+    };
     // pass A: radix E, no twiddles (sub-transform size 1); output i = l E + r
     dftn<T, E, INV>(v);
     {
@@ -166,7 +187,7 @@ __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw
             for (int r = 0; r < 8; ++r) u[b][r] = rp[8 * r * S];
 #pragma unroll
             for (int r = 1; r < 8; ++r) {
-                auto w = tw[r * k * 8 * TS];  // W_{8E}^{rk} = W_M^{8rk}
+                auto w = twB(r, k);  // W_{8E}^{rk} = W_M^{8rk}
                 u[b][r] = cmul(u[b][r], cx<T>{w.x, INV ? -w.y : w.y});
             }
             dft8<T, INV>(u[b]);
@@ -193,7 +214,7 @@ __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw
             for (int r = 0; r < 8; ++r) x[r] = rp[8 * r * S];
 #pragma unroll
             for (int r = 1; r < 8; ++r) {
-                auto w = tw[r * j * TS];
+                auto w = twC(r, j);
                 x[r] = cmul(x[r], cx<T>{w.x, INV ? -w.y : w.y});
             }
             dft8<T, INV>(x);
@@ -228,12 +249,12 @@ __device__ __forceinline__ void wave_spectral(cx<T>* v, cx<T>* lds, const typena
     {
         const int l = lane_id_fresh();
         const cx<T>* rb = lds + (M - l) - 64 * (E - 1);  // rb[64 (E-1-t)] = Z[M - l - 64 t]
-        const auto* cp = coef + 2 * l;
+        const uint32_t co = (uint32_t)l * (uint32_t)(2 * sizeof(*coef));  // lane's (alpha, beta) pair
 #pragma unroll
         for (int t = 0; t < E; ++t) {
             const cx<T> zb = rb[64 * (E - 1 - t)];
-            const auto al = cp[128 * t];
-            const auto be = cp[128 * t + 1];
+            const auto al = ld_row(coef + 128 * t, co);
+            const auto be = ld_row(coef + 128 * t + 1, co);
             const cx<T> z = v[t];
             v[t] = cmul(z, cx<T>{al.x, al.y}) + cmul(conj(zb), cx<T>{be.x, be.y});
             if ((t & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight

@@ -666,8 +666,65 @@ __global__ void __launch_bounds__(NT) k_fft(RunArgs a) {
     }
 }
 
+// One fixed packed mode at a transform of its own length, 2 MW words (MW = 2^LOGMW complex
+// points): the asymmetric modes pack T + N - 1 words and the symmetric mode W_block / 2, so
+// they need shorter transforms than the W_block words of the FP32 slot that k_fft is sized by.
+template <int MODE, int LOGMW>
+__global__ void __launch_bounds__(NT) k_fft1(RunArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char lds[];  // MW complex FP64 points
+    const Item it = make_item(a, blockIdx.x, true);
+    const BlockStats st = block_stats(a.s, it.start, it.nwin);
+    const Choice c = choose(a, st);  // a fixed mode: c.mode == MODE
+    write_info(a, it, c, st, blockIdx.x < a.P);
+    if (c.flags & APX_FLAG_NONFINITE) {
+        fill_block(a, it, NAN);
+        return;
+    }
+    if (c.flags & APX_FLAG_ZERO) {
+        fill_block(a, it, 0.0f);
+        return;
+    }
+    if (it.j_hi <= it.j_lo) return;
+    fft_item<MODE, 1 << LOGMW>(a, it, c, lds);
+}
+
 int fft_min_logF() { return 9; }
 int fft_max_logF() { return 14; }
+
+#define APX_FFT1_SIZES(X, MODE) X(MODE, 7) X(MODE, 8) X(MODE, 9) X(MODE, 10) X(MODE, 11) X(MODE, 12) X(MODE, 13)
+
+static const void* fft1_fn(int mode, int logmw) {
+#define APX_FN(M_, L_) \
+    if (mode == M_ && logmw == L_) return (const void*)k_fft1<M_, L_>;
+    APX_FFT1_SIZES(APX_FN, MD_SYM)
+    APX_FFT1_SIZES(APX_FN, MD_ASYM2)
+    APX_FFT1_SIZES(APX_FN, MD_ASYM3)
+#undef APX_FN
+    return nullptr;
+}
+
+bool fft1_supported(int mode, int logmw) { return fft1_fn(mode, logmw) != nullptr; }
+
+hipError_t fft1_set_lds(int mode, int logmw) {
+    const void* f = fft1_fn(mode, logmw);
+    if (!f) return hipErrorInvalidValue;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(((size_t)16) << logmw));
+}
+
+hipError_t launch_fft1(const RunArgs& a, int mode, int logmw, hipStream_t st) {
+    dim3 g((unsigned)(a.P + 1));
+    const size_t lds = ((size_t)16) << logmw;
+#define APX_GO(M_, L_)                                                          \
+    if (mode == M_ && logmw == L_) {                                            \
+        hipLaunchKernelGGL((k_fft1<M_, L_>), g, dim3(NT), lds, st, a);           \
+        return hipGetLastError();                                               \
+    }
+    APX_FFT1_SIZES(APX_GO, MD_SYM)
+    APX_FFT1_SIZES(APX_GO, MD_ASYM2)
+    APX_FFT1_SIZES(APX_GO, MD_ASYM3)
+#undef APX_GO
+    return hipErrorInvalidValue;
+}
 
 static size_t fft_lds(int logF) { return ((size_t)1 << logF) * sizeof(double); }
 

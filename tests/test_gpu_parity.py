@@ -141,6 +141,39 @@ def test_fft_core_packed_small(ctx, mode, L, N, Wb, variant):
     _check_packed(s, k, Wb, mode, S, got, fields, info)
 
 
+@pytest.mark.parametrize("mode,N,Wb", [(O.ASYM2, 800, 8994), (O.ASYM3, 800, 8994), (O.SYM, 800, 17186),
+                                       (O.ASYM2, 800, 17186), (O.ASYM3, 800, 17186), (O.ASYM3, 800, 33570),
+                                       (O.SYM, 101, 32768), (O.ASYM2, 40, 600)])
+def test_fft_block_core_own_length(ctx, mode, N, Wb):
+    """LDS core of one fixed packed mode at the transform length of its own words (W_block / 2
+    symmetric, T + N - 1 asymmetric), up to the longest transform one workgroup holds (16384
+    words, W_block beyond 16384): three blocks and a ragged tail, U[-128, 128] inputs."""
+    No = N if N % 2 else N + 1
+    L = 3 * (Wb - No - 1) + 555
+    _say("case: FFT block core, own length", mode, L, N, Wb)
+    s = synth.uniform(L, 51 + N) * np.float32(128.0)
+    k = synth.uniform(N, 52 + N) * np.float32(128.0)
+    S = O.max_q(mode, No)
+    kern = apx.Kernel(ctx, _dev(k), Wb, mode=MODES[mode], core=apx.APX_CORE_FFT, Sq=S, Kq=S,
+                      fft_variant=apx.FFT_BLOCK)
+    desc = kern.describe()
+    kern.close()
+    _say(" ", desc)
+    assert "k_fft1" in desc
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "fft", S, S, variant=apx.FFT_BLOCK)
+    _check_packed(s, k, Wb, mode, S, got, fields, info)
+
+
+def test_fft_block_core_limits(ctx):
+    """Beyond one workgroup's transform (16384 words): FP32 above W_block = 16384, symmetric
+    above W_block = 32768, asymmetric M=2 above 16384 words."""
+    k = _dev(synth.uniform(800, 9))
+    for mode, Wb in ((apx.APX_FULL_FP32, 17186), (apx.APX_ASYM2, 33570), (apx.APX_SYM, 33570)):
+        with pytest.raises(apx.ApxError) as e:
+            apx.Kernel(ctx, k, Wb, mode=mode, core=apx.APX_CORE_FFT)
+        assert e.value.status == apx.APX_E_UNSUPPORTED, (mode, Wb)
+
+
 @pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3])
 @pytest.mark.parametrize("L,N,Wb", GROUP_SHAPES)
 def test_fft_group_packed(ctx, mode, L, N, Wb):
