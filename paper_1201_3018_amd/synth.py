@@ -9,7 +9,8 @@ shapes and value distributions follow the paper's experiments and the measured w
 * Hann-windowed sinc low-pass and band-pass FIR kernels;
 * pink (1/f) noise channels;
 * U[-128, 128] data as in Section IV.A;
-* batched correlation sets (references, noisy template excerpts) and Poisson request streams.
+* batched correlation sets (references, noisy template excerpts) and Poisson request streams;
+* two-channel audio with a known delay per segment (the multi-channel delay application).
 """
 from __future__ import annotations
 
@@ -94,6 +95,34 @@ def xcorr_batch(n_templates: int = 4096, n_refs: int = 64, seed_refs: int = 3001
         ridx.append(j)
         offs.append(off)
     return refs, tmpls, np.array(ridx), np.array(offs)
+
+
+def two_channel(L: int, seed: int, seg: int = 44100, max_delay: int = 200, mono_frac: float = 0.25,
+                snr_db: float = 30.0):
+    """Two-channel audio with a known inter-channel delay per segment of `seg` samples.  Channel a
+    is AR(1) audio; in a mono segment channel b equals a, in a stereo segment b[n] = a[n - d] with
+    1 <= |d| <= max_delay plus white noise at snr_db (zeros before the start of a).  Returns
+    (a, b, delays, mono) with one delay and one mono flag per segment."""
+    a = ar1(L, seed)
+    rng = np.random.default_rng(seed + 1)
+    nseg = -(-L // seg)
+    mono = rng.random(nseg) < mono_frac
+    mag = rng.integers(1, max_delay + 1, nseg)
+    delays = np.where(mono, 0, mag * rng.choice([-1, 1], nseg)).astype(np.int64)
+    a64 = a.astype(np.float64)
+    b = np.empty(L, np.float64)
+    for i in range(nseg):
+        s0, s1 = i * seg, min(L, (i + 1) * seg)
+        d = int(delays[i])
+        src = np.arange(s0, s1) - d
+        ok = (src >= 0) & (src < L)
+        x = np.zeros(s1 - s0)
+        x[ok] = a64[src[ok]]
+        if not mono[i]:
+            rms = math.sqrt(float(np.mean(x * x))) if s1 > s0 else 0.0
+            x = x + rng.standard_normal(s1 - s0) * rms * 10.0 ** (-snr_db / 20.0)
+        b[s0:s1] = x
+    return a, b.astype(np.float32), delays, mono
 
 
 def poisson_requests(rate: float = 2000.0, duration: float = 10.0, seed: int = 5001,
