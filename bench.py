@@ -157,6 +157,25 @@ def main():
                               "blocks": {"full_fp32": int(m_t[0]), "sym": int(m_t[1]), "asym2": int(m_t[2])}})
             kt.close()
 
+    # the integer matrix-core core (Tier-2 swap: same companding, exact int8 digit products, no
+    # FP64 packing) on the same input, at the fixed modes' largest in-bound S_q = K_q; its outputs
+    # are compared with the packed FFT core's
+    int8_core = []
+    if args.workload == "c2":
+        for name, mode, q in (("sym", apx.APX_SYM, 0), ("asym2", apx.APX_ASYM2, 0), ("asym2_8bit", apx.APX_ASYM2, 127)):
+            ki = apx.Kernel(ctx, tk, Wb, mode=mode, core=apx.APX_CORE_INT8, Sq=q, Kq=q)
+            kf_ = apx.Kernel(ctx, tk, Wb, mode=mode, core=apx.APX_CORE_FFT, Sq=q, Kq=q)
+            ms_i = timed(ki, max(1, args.steps // 4), 2)
+            ms_f = timed(kf_, max(1, args.steps // 4), 2)
+            oi, of_ = ki.run(ts[0]), kf_.run(ts[0])
+            torch.cuda.synchronize()
+            same = bool(torch.equal(oi, of_))
+            int8_core.append({"mode": name, "Sq": q or None, "ms_per_step": ms_i, "fft_core_ms_per_step": ms_f,
+                              "int8_over_fft": ms_f / ms_i, "outputs_equal_fft_core": same,
+                              "kernel": ki.describe()[:80]})
+            ki.close()
+            kf_.close()
+
     # per-call latency as a caller sees it (enqueue + completion), packed path
     lat = []
     for i in range(50):
@@ -244,6 +263,8 @@ def main():
     }
     if snr_sweep:
         res["snr_sweep"] = snr_sweep
+    if int8_core:
+        res["int8_core"] = int8_core
     if args.copy_probe:
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)

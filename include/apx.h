@@ -50,7 +50,12 @@ typedef enum {
     APX_FULL_FP64 = 5    /* no packing, FP64 arithmetic (time-domain core only) */
 } apx_mode;
 
-typedef enum { APX_CORE_AUTO = 0, APX_CORE_TIME = 1, APX_CORE_FFT = 2 } apx_core;
+/* Tier-2 convolution core.  APX_CORE_INT8 computes the companded block convolution
+   r~ = s~ * k~ (eq. 2 on both operands) of a fixed packed mode's S_q, K_q exactly on the int8
+   matrix cores (balanced base-128 digits when S_q or K_q exceed 127, up to 16319), then eq. (16):
+   no FP64 packing, so it is exact whatever Table 1's bound says and its outputs equal the packed
+   cores' wherever their unpacking is exact.  Fixed packed modes only; one wavefront per block. */
+typedef enum { APX_CORE_AUTO = 0, APX_CORE_TIME = 1, APX_CORE_FFT = 2, APX_CORE_INT8 = 3 } apx_core;
 typedef enum { APX_CONV = 0, APX_XCORR = 1 } apx_op;
 
 typedef struct {

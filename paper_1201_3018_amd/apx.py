@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libapx.so")
 
 APX_OK, APX_E_INVALID, APX_E_BOUND, APX_E_NOMEM, APX_E_DEVICE, APX_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 APX_FULL_FP32, APX_SYM, APX_ASYM2, APX_ASYM3, APX_AUTO_SNR, APX_FULL_FP64 = 0, 1, 2, 3, 4, 5
-APX_CORE_AUTO, APX_CORE_TIME, APX_CORE_FFT = 0, 1, 2
+APX_CORE_AUTO, APX_CORE_TIME, APX_CORE_FFT, APX_CORE_INT8 = 0, 1, 2, 3
 APX_CONV, APX_XCORR = 0, 1
 APX_FLAG_NONFINITE, APX_FLAG_ZERO = 1, 2
 APX_FB_F16X3, APX_FB_BF16X3 = 0, 1

@@ -242,7 +242,9 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
 }
 
 apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
-    if (k->core == APX_CORE_FFT && k->group) {
+    if (k->core == APX_CORE_INT8) {
+        HIPCHK(launch_i8(a, k->i8frag, k->S[k->params.mode] > 127, k->i8_splitk, k->i8_plane, st));
+    } else if (k->core == APX_CORE_FFT && k->group) {
         HIPCHK(launch_fftg(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
     } else if (k->core == APX_CORE_FFT && k->wave) {
         HIPCHK(launch_fftw(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
@@ -350,7 +352,7 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
     if (r != APX_OK) return r;
     const apx_params p = *params;
     if (p.mode < APX_FULL_FP32 || p.mode > APX_FULL_FP64) return fail(APX_E_INVALID, "unknown mode %d", p.mode);
-    if (p.core < APX_CORE_AUTO || p.core > APX_CORE_FFT) return fail(APX_E_INVALID, "unknown core %d", p.core);
+    if (p.core < APX_CORE_AUTO || p.core > APX_CORE_INT8) return fail(APX_E_INVALID, "unknown core %d", p.core);
     if (p.Sq < 0 || p.Kq < 0) return fail(APX_E_INVALID, "negative companding range");
     if (p.mode == APX_AUTO_SNR && !isfinite(p.snr_min_db)) return fail(APX_E_INVALID, "snr_min_db must be finite");
 
@@ -379,12 +381,13 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         if (k->S[m] < 1 || k->K[m] < 1) {
             return fail(APX_E_BOUND, "no companding range S_q = K_q >= 1 fits the bound for N = %d", N_odd);
         }
-        if (k->R[m] > bound_of(m) && !p.allow_unsafe) {
+        // the integer core carries no packing: exact for any S_q, K_q its digits hold
+        if (k->R[m] > bound_of(m) && !p.allow_unsafe && p.core != APX_CORE_INT8) {
             int64_t Rm = k->R[m];
             return fail(APX_E_BOUND, "R_max = N S_q K_q = %lld exceeds the bound %lld (Table 1)", (long long)Rm,
                         (long long)bound_of(m));
         }
-        if (k->R[m] > ((int64_t)1 << 40)) {
+        if (k->R[m] > ((int64_t)1 << (p.core == APX_CORE_INT8 ? 52 : 40))) {
             return fail(APX_E_UNSUPPORTED, "R_max too large");
         }
         k->use[m] = true;
@@ -410,6 +413,19 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
     if (core == APX_CORE_AUTO) core = (N_odd <= 129) ? APX_CORE_TIME : APX_CORE_FFT;
     if (fft_words > 0) core = APX_CORE_FFT;
     k->core = core;
+    if (core == APX_CORE_INT8) {
+        if (p.mode < APX_SYM || p.mode > APX_ASYM3)
+            return fail(APX_E_UNSUPPORTED, "the integer core runs a fixed packed mode's companding only");
+        const int m = p.mode;
+        if (k->S[m] > 16319 || k->K[m] > 16319)
+            return fail(APX_E_UNSUPPORTED, "the integer core takes S_q, K_q <= 16319 (two int8 digits)");
+        if ((int64_t)N_odd + 31 >= (1 << 17)) return fail(APX_E_UNSUPPORTED, "N too large for int32 digit sums");
+        k->i8_plane = i8_plane_len(N_odd, W);
+        k->i8_splitk = k->K[m] > 127;
+        const size_t lds = i8_lds_bytes(k->i8_plane, W_block);
+        if (lds > (size_t)ctx->max_lds)
+            return fail(APX_E_UNSUPPORTED, "integer core block needs %zu bytes of LDS (> %d)", lds, ctx->max_lds);
+    }
     if (fft_words > 0) {
         if (p.mode == APX_AUTO_SNR || p.mode == APX_FULL_FP64)
             return fail(APX_E_UNSUPPORTED, "a forced FFT length needs a fixed mode");
@@ -481,6 +497,8 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         if (p.fft_variant == 3 && !k->group) {
             return fail(APX_E_UNSUPPORTED, "no compiled group size set covers W_block = %d, N = %d", W_block, N);
         }
+    } else if (core == APX_CORE_INT8) {
+        // sized above
     } else {
         k->td_lds = td_lds_bytes(p.mode, N_odd, W_block, k->T[MD_ASYM2], k->T[MD_ASYM3]);
         if (k->td_lds > (size_t)ctx->max_lds) {
@@ -518,6 +536,7 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             if (r == APX_OK) r = get_table(ctx, 2 * k->wM[m], nullptr, nullptr);
         }
     }
+    if (r == APX_OK && core == APX_CORE_INT8) r = dalloc(k, &k->i8frag, (size_t)2 * i8_kpad(N_odd) * 64 * 4);
     if (r != APX_OK) {
         free_kernel(k);
         return r;
@@ -542,6 +561,11 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             get_table(ctx, 2 * k->wM[0], &tF, nullptr);
             e = launch_coef32(k->kd, N_odd, k->wM[0], tF, k->coef32, st);
         }
+    }
+    if (e == hipSuccess && core == APX_CORE_INT8) {
+        e = launch_i8_frag(k->kf, k->ks, p.mode, N_odd, k->i8_splitk, k->i8frag, st);
+        const size_t lds = i8_lds_bytes(k->i8_plane, W_block);
+        if (e == hipSuccess && lds > 65536) e = i8_set_lds((int)lds);
     }
     if (e == hipSuccess && core == APX_CORE_FFT && !k->wave && fft_words == 0)
         e = k->fft1_logmw > 0 ? fft1_set_lds(p.mode, k->fft1_logmw) : fft_set_lds(k->logF);
@@ -672,6 +696,9 @@ apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {
     int n;
     if (k->core == APX_CORE_TIME) {
         n = snprintf(tmp, sizeof tmp, "core=time kernel=k_td lds=%zu", k->td_lds);
+    } else if (k->core == APX_CORE_INT8) {
+        n = snprintf(tmp, sizeof tmp, "core=int8 kernel=k_i8 ksteps=%d lds=%zu split_k=%d", i8_ksteps(k->N_odd),
+                     i8_lds_bytes(k->i8_plane, k->W_block), k->i8_splitk);
     } else if (k->wave) {
         n = snprintf(tmp, sizeof tmp, "core=fft kernel=%s<%d,%d,%d,%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d",
                      k->group ? "k_fftg" : "k_fftw", k->wM[1], k->wM[2], k->wM[3], k->wM[0], 2 * k->wM[0],

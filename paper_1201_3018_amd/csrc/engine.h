@@ -20,6 +20,15 @@ namespace apx {
 bool fft1_supported(int mode, int logmw);
 hipError_t fft1_set_lds(int mode, int logmw);
 hipError_t launch_fft1(const RunArgs& a, int mode, int logmw, hipStream_t st);
+// integer matrix-core core (kernels.hip)
+int i8_ksteps(int N_odd);
+int i8_kpad(int N_odd);
+int i8_plane_len(int N_odd, int W);
+size_t i8_lds_bytes(int plane_len, int W_block);
+hipError_t launch_i8_frag(const float* kf, const KState* ks, int mode, int N_odd, int split, void* frag,
+                          hipStream_t st);
+hipError_t i8_set_lds(int bytes);
+hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, hipStream_t st);
 }  // namespace apx
 
 using apx::KState;
@@ -43,6 +52,10 @@ struct apx_kernel_s {
     int core = APX_CORE_TIME;
     int logF = 0;
     int fft1_logmw = 0;  // > 0: the fixed packed mode runs k_fft1 at 2^fft1_logmw complex points
+    // integer matrix-core core: B fragments (two digit planes), LDS digit-plane length, K split
+    int32_t* i8frag = nullptr;
+    int i8_plane = 0;
+    int i8_splitk = 0;
     int32_t S[4] = {0, 0, 0, 0}, K[4] = {0, 0, 0, 0};
     int64_t R[4] = {0, 0, 0, 0};
     int32_t T[4] = {0, 0, 0, 0};

@@ -217,8 +217,8 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
 }
 
 __device__ __forceinline__ void write_info(const RunArgs& a, const Item& it, const Choice& c, const BlockStats& st,
-                                           bool is_report) {
-    if (a.info && is_report && threadIdx.x == 0) {
+                                           bool is_report, bool lead = threadIdx.x == 0) {
+    if (a.info && is_report && lead) {
         apx_block_info b;
         b.mode = c.mode;
         b.flags = c.flags;
@@ -1104,6 +1104,317 @@ __global__ void k_calib_finish(const double* __restrict__ partial, int32_t npart
 hipError_t launch_calib_finish(const double* partial, int32_t nparts, const KState* ks, int32_t Q, double* out,
                                hipStream_t st) {
     hipLaunchKernelGGL(k_calib_finish, dim3(1), dim3(64), 0, st, partial, nparts, ks, Q, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Integer matrix-core core.  The companded block convolution r~ = s~ * k~ (eq. 2 applied to
+// both operands: the integers every packing of Section III carries) is computed exactly with
+// int8 MFMA and int32 accumulation, then dequantized by eq. (16).  There is no FP64 packing:
+// this is another Tier-2 convolution under the same companding, and its outputs equal those of
+// the packed cores wherever their unpacking is exact.
+// One block is a Toeplitz product.  Output m = m0 + 32 i + j (tile row i, column j < 32):
+//   r~[m] = sum_kappa A[i][kappa] B[kappa][j],  A[i][kappa] = s~[m0 + 32 i + kappa - (N - 1)],
+//   B[kappa][j] = k~[j - kappa + N - 1] (zero outside the taps), kappa < 32 ksteps, ksteps =
+//   ceil((N + 31) / 32).
+// An operand wider than int8 (S_q or K_q above 127) is split into balanced base-128 digits,
+// v = 128 hi + lo with lo in [-64, 63]; the digit products are summed in int32 (exact for any
+// N below 2^17) and joined in int64.
+// ------------------------------------------------------------------------------------------
+typedef int i8x16 __attribute__((ext_vector_type(4)));   // 16 int8 per lane
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int I8_TILE = 1024;  // outputs per 32 x 32 tile
+constexpr int I8_TM = 3;       // tiles per pass over the taps
+
+__device__ __forceinline__ void i8_digits(int v, bool split, int& lo, int& hi) {
+    if (split) {
+        hi = (v + 64) >> 7;  // floor((v + 64) / 128): arithmetic shift
+        lo = v - hi * 128;
+    } else {
+        hi = 0;
+        lo = v;
+    }
+}
+
+// B fragments, [plane][k-step][lane] x 16 bytes: plane 0 the low digits (or the value), plane 1
+// the high digits.  Lane l holds column l % 32 and kappa = 32 s + 16 (l / 32) + byte; A uses the
+// same kappa for the same (lane half, byte), so the k order the hardware assigns is immaterial.
+__global__ void __launch_bounds__(NT) k_i8_frag(const float* __restrict__ kf, const KState* __restrict__ ks,
+                                                int mode, int N, int ksteps, int split, i8x16* __restrict__ frag) {
+    const double ck = ks->ck[mode];
+    const int n = 2 * ksteps * 64;
+    for (int f = blockIdx.x * NT + threadIdx.x; f < n; f += gridDim.x * NT) {
+        const int plane = f / (ksteps * 64);
+        const int s = (f / 64) % ksteps;
+        const int l = f % 64;
+        int w[4] = {0, 0, 0, 0};
+        for (int b = 0; b < 16; ++b) {
+            const int kappa = 32 * s + 16 * (l >> 5) + b;
+            const int t = (l & 31) - kappa + N - 1;
+            const int v = (t >= 0 && t < N) ? (int)rint(ck * (double)kf[t]) : 0;  // eq. (2), as k_prepare
+            int lo, hi;
+            i8_digits(v, split != 0, lo, hi);
+            w[b >> 2] |= ((plane ? hi : lo) & 255) << (8 * (b & 3));
+        }
+        i8x16 r;
+        r.x = w[0];
+        r.y = w[1];
+        r.z = w[2];
+        r.w = w[3];
+        frag[f] = r;
+    }
+}
+
+// One wavefront per block (time-domain items: block 0 yields its outputs from 0), up to I8_WPB
+// blocks per workgroup (fewer workgroups to launch); the waves share nothing and never wait for each
+// other.  A wave's LDS region holds the block's companded samples as two digit planes of plane_len bytes (byte i + N - 1 of a plane is
+// digit p of s~[i], zero outside [0, nvalid)), so every A fragment is one aligned 16-byte read,
+// and behind them the raw window (W_block floats) that the planes are built from.  The taps'
+// B fragments stream from L2 in chunks of I8_KC k-steps, the next chunk in flight while the
+// current one runs.
+constexpr int I8_KC = 4;
+constexpr int I8_WPB = 1;  // most waves (blocks) per workgroup (2 measured no faster)
+
+// LDS order point between the lanes of one wave (the LDS unit runs a wave's instructions in
+// order; the fence keeps the compiler from moving LDS accesses across it)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// SS, SK: the samples' / the taps' companding range exceeds 127 (two digit planes)
+template <bool SS, bool SK>
+__global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a, const i8x16* __restrict__ frag, int ksteps,
+                                                       int plane_len, int region) {
+    extern __shared__ __attribute__((aligned(16))) char lds_all[];
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (blk >= a.P) return;
+    char* lds_i8 = lds_all + (size_t)(threadIdx.x >> 6) * region;
+    const Item it = make_item(a, blk, false);
+    float* win = reinterpret_cast<float*>(lds_i8 + 2 * plane_len);
+    // window into LDS with its statistics; start is even (8-byte aligned float2 loads)
+    BlockStats st;
+    {
+        double m = 0.0, q = 0.0;
+        int nf = 0;
+        const float* p = a.s + it.start;
+        constexpr int CH = 16;
+        for (int base = 0; base < a.W_block; base += 128 * CH) {
+            float2 f[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + 2 * lane + 128 * c;
+                f[c] = make_float2(0.0f, 0.0f);
+                if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
+                else if (i < it.nwin) f[c].x = p[i];
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + 2 * lane + 128 * c;
+                if (i < a.W_block) {
+                    const float x0 = f[c].x, x1 = f[c].y;
+                    if (!isfinite(x0) || !isfinite(x1)) nf = 1;
+                    const double d0 = isfinite(x0) ? (double)x0 : 0.0, d1 = isfinite(x1) ? (double)x1 : 0.0;
+                    m = fmax(m, fmax(fabs(d0), fabs(d1)));
+                    q += d0 * d0 + d1 * d1;
+                    *reinterpret_cast<float2*>(win + i) = f[c];
+                }
+            }
+        }
+        st.smax = wave_max(m);
+        st.sumsq = wave_sum(q);
+        st.nonfinite = wave_or(nf);
+    }
+    const Choice c = choose(a, st);
+    write_info(a, it, c, st, true, lane == 0);
+    if ((c.flags & APX_FLAG_NONFINITE) || (c.flags & APX_FLAG_ZERO)) {
+        const float v = (c.flags & APX_FLAG_NONFINITE) ? NAN : 0.0f;
+        for (int j = it.j_lo + lane; j < it.j_hi; j += 64) {
+            a.out[it.o0 + (j - it.j_lo)] = v;
+            if (a.fields) a.fields[it.o0 + (j - it.j_lo)] = 0.0;
+        }
+        return;
+    }
+    // companded samples (eq. 2, as sq_at), as digit planes
+    const bool split_s = SS;
+    const int off = a.N - 1;
+    int* p0 = reinterpret_cast<int*>(lds_i8);
+    int* p1 = reinterpret_cast<int*>(lds_i8 + plane_len);
+    // branch-free: every read is a clamped in-window index, samples outside [0, nvalid) select 0
+    const int wmax = a.W_block - 1;
+#pragma unroll 4
+    for (int w4 = lane; w4 < plane_len / 4; w4 += 64) {
+        int lo4 = 0, hi4 = 0;
+        float x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = win[min(max(4 * w4 + e - off, 0), wmax)];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 4 * w4 + e - off;
+            const int q = (int)rint(c.cs * (double)x[e]);
+            const int v = (i >= 0 && i < it.nvalid) ? q : 0;
+            int lo, hi;
+            i8_digits(v, split_s, lo, hi);
+            lo4 |= (lo & 255) << (8 * e);
+            hi4 |= (hi & 255) << (8 * e);
+        }
+        p0[w4] = lo4;
+        if (split_s) p1[w4] = hi4;
+    }
+    wave_lds_sync();
+    const int j0 = it.j_lo & ~15;
+    const int ntiles = (it.j_hi - j0 + I8_TILE - 1) / I8_TILE;
+    const int row = lane & 31, half = lane >> 5;
+    const char* a0p = lds_i8 + 32 * row + 16 * half;
+    const char* a1p = a0p + plane_len;
+    // every pass computes I8_TM tiles over kpad k-steps (the planes and the zero-padded fragment
+    // rows cover them); a last pass with fewer tiles repeats the last tile, and outputs past j_hi
+    // are not stored.  Blocks walk the k-steps from different starting chunks (the integer sums
+    // do not depend on the order), so the waves of the GPU do not all read the same fragment
+    // rows of the table at once.
+    const int kpad = (ksteps + I8_KC - 1) / I8_KC * I8_KC;
+    const int nchunk = kpad / I8_KC;
+    const int c_first = (int)(blk % nchunk);
+    constexpr int NACC = SS && SK ? 3 : (SS || SK ? 2 : 1);
+    // one-digit operands: two accumulator sets (even and odd k-steps) for independent MFMA chains
+    constexpr int AS = NACC == 1 ? 2 : 1;
+    for (int t0 = 0; t0 < ntiles; t0 += I8_TM) {
+        i32x16 acc[NACC * AS][I8_TM];
+#pragma unroll
+        for (int g = 0; g < NACC * AS; ++g)
+#pragma unroll
+            for (int u = 0; u < I8_TM; ++u)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[g][u][r] = 0;
+        i8x16 bc[I8_KC][SK ? 2 : 1], bn[I8_KC][SK ? 2 : 1];
+        int tofs[I8_TM];  // tile origin in the planes
+#pragma unroll
+        for (int u = 0; u < I8_TM; ++u) tofs[u] = j0 + min(t0 + u, ntiles - 1) * I8_TILE;
+        {
+            const int kc = c_first * I8_KC;
+#pragma unroll
+            for (int kk = 0; kk < I8_KC; ++kk) {
+                bc[kk][0] = frag[(kc + kk) * 64 + lane];
+                if constexpr (SK) bc[kk][SK ? 1 : 0] = frag[(kpad + kc + kk) * 64 + lane];
+            }
+        }
+        for (int ci = 0; ci < nchunk; ++ci) {
+            int c = c_first + ci;
+            if (c >= nchunk) c -= nchunk;
+            const int k0 = c * I8_KC;
+            int cn = c + 1;
+            if (cn >= nchunk) cn -= nchunk;
+            const int kn = cn * I8_KC;  // next chunk (after the last one: the first again, unused)
+#pragma unroll
+            for (int kk = 0; kk < I8_KC; ++kk) {
+                bn[kk][0] = frag[(kn + kk) * 64 + lane];
+                if constexpr (SK) bn[kk][SK ? 1 : 0] = frag[(kpad + kn + kk) * 64 + lane];
+            }
+#pragma unroll
+            for (int kk = 0; kk < I8_KC; ++kk) {
+#pragma unroll
+                for (int u = 0; u < I8_TM; ++u) {
+                    const int ofs = tofs[u] + 32 * (k0 + kk);
+                    const i8x16 x0 = *reinterpret_cast<const i8x16*>(a0p + ofs);
+                    const int g0 = AS == 2 ? (kk & 1) : 0;  // static once the k-step loop is unrolled
+                    acc[g0][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x0, bc[kk][0], acc[g0][u], 0, 0, 0);
+                    if constexpr (SK)
+                        acc[1][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x0, bc[kk][SK ? 1 : 0], acc[SK ? 1 : 0][u],
+                                                                          0, 0, 0);
+                    if constexpr (SS) {
+                        const i8x16 x1 = *reinterpret_cast<const i8x16*>(a1p + ofs);
+                        acc[1][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x1, bc[kk][0], acc[NACC > 1 ? 1 : 0][u],
+                                                                          0, 0, 0);
+                        if constexpr (SK)
+                            acc[NACC - 1][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x1, bc[kk][SK ? 1 : 0],
+                                                                                     acc[NACC - 1][u], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < I8_KC; ++kk) {
+                bc[kk][0] = bn[kk][0];
+                if constexpr (SK) bc[kk][SK ? 1 : 0] = bn[kk][SK ? 1 : 0];
+            }
+        }
+        // D[r] of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+#pragma unroll
+        for (int u = 0; u < I8_TM; ++u) {
+            if (t0 + u >= ntiles) continue;
+            const int m0 = j0 + (t0 + u) * I8_TILE;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = m0 + 32 * (8 * (r >> 2) + 4 * half + (r & 3)) + row;
+                if (m >= it.j_lo && m < it.j_hi) {
+                    long long v = (long long)acc[0][u][r];
+                    if constexpr (AS == 2) v += (long long)acc[AS - 1][u][r];
+                    if constexpr (NACC > 1) v += 128LL * (long long)acc[NACC > 1 ? 1 : 0][u][r];
+                    if constexpr (NACC > 2) v += 16384LL * (long long)acc[NACC - 1][u][r];
+                    put(a, it, m, (double)v, c.inv);  // eq. (16)
+                }
+            }
+        }
+    }
+}
+
+// Host side of the integer core.  frag: 2 planes of i8_kpad(N) rows of 64 entries of 16 bytes
+// (rows from ksteps on are zero).
+int i8_ksteps(int N_odd) { return (N_odd + 31 + 31) / 32; }
+int i8_kpad(int N_odd) { return (i8_ksteps(N_odd) + I8_KC - 1) / I8_KC * I8_KC; }
+
+int i8_plane_len(int N_odd, int W) {
+    const int nt0 = (W + N_odd - 1 + I8_TILE - 1) / I8_TILE;     // block 0: outputs from 0
+    const int j0 = (N_odd + 1) & ~15;                             // later blocks
+    const int nt1 = (N_odd + 1 + W - j0 + I8_TILE - 1) / I8_TILE;
+    const int need = std::max(nt0 * I8_TILE, j0 + nt1 * I8_TILE) + 32 * i8_kpad(N_odd);
+    return (need + 15) & ~15;
+}
+
+hipError_t launch_i8_frag(const float* kf, const KState* ks, int mode, int N_odd, int split, void* frag,
+                          hipStream_t st) {
+    const int n = 2 * i8_kpad(N_odd) * 64;
+    hipLaunchKernelGGL(k_i8_frag, dim3((n + NT - 1) / NT), dim3(NT), 0, st, kf, ks, mode, N_odd, i8_kpad(N_odd),
+                       split, reinterpret_cast<i8x16*>(frag));
+    return hipGetLastError();
+}
+
+hipError_t i8_set_lds(int bytes) {
+    const void* fs[4] = {(const void*)k_i8<false, false>, (const void*)k_i8<false, true>,
+                         (const void*)k_i8<true, false>, (const void*)k_i8<true, true>};
+    for (const void* f : fs) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// LDS region of one block: two digit planes and the raw window.  A workgroup holds I8_WPB
+// regions while that leaves room for two workgroups per CU, else one.
+static size_t i8_region(int plane_len, int W_block) {
+    return ((size_t)2 * plane_len + 4 * (size_t)W_block + 15) & ~(size_t)15;
+}
+static int i8_wpb(size_t region) { return I8_WPB * region <= 81920 ? I8_WPB : 1; }
+size_t i8_lds_bytes(int plane_len, int W_block) {
+    const size_t rg = i8_region(plane_len, W_block);
+    return (size_t)i8_wpb(rg) * rg;
+}
+
+// split_s: the fixed mode's S_q > 127 (every block of the call uses it)
+hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, hipStream_t st) {
+    const int rg = (int)i8_region(plane_len, a.W_block);
+    const int wpb = i8_wpb((size_t)rg);
+    const dim3 g((unsigned)((a.P + wpb - 1) / wpb)), b(64 * wpb);
+    const size_t lds = (size_t)wpb * rg;
+    const i8x16* fr = reinterpret_cast<const i8x16*>(frag);
+    const int ks = i8_ksteps(a.N);
+    if (split_s && split_k) hipLaunchKernelGGL((k_i8<true, true>), g, b, lds, st, a, fr, ks, plane_len, rg);
+    else if (split_s) hipLaunchKernelGGL((k_i8<true, false>), g, b, lds, st, a, fr, ks, plane_len, rg);
+    else if (split_k) hipLaunchKernelGGL((k_i8<false, true>), g, b, lds, st, a, fr, ks, plane_len, rg);
+    else hipLaunchKernelGGL((k_i8<false, false>), g, b, lds, st, a, fr, ks, plane_len, rg);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ from paper_1201_3018_amd import apx  # noqa: E402
 
 DEV = torch.device("cuda:0")
 MODES = {O.SYM: apx.APX_SYM, O.ASYM2: apx.APX_ASYM2, O.ASYM3: apx.APX_ASYM3}
-CORES = {"td": apx.APX_CORE_TIME, "fft": apx.APX_CORE_FFT}
+CORES = {"td": apx.APX_CORE_TIME, "fft": apx.APX_CORE_FFT, "int8": apx.APX_CORE_INT8}
 
 
 @pytest.fixture(scope="module")
@@ -245,7 +245,7 @@ def test_fp32_small_shapes(ctx, core, variant):
 
 
 # ------------------------------------------------------------------------- edge cases
-@pytest.mark.parametrize("core,variant", [("td", "block"), ("fft", "block"), ("fft", "wave")])
+@pytest.mark.parametrize("core,variant", [("td", "block"), ("fft", "block"), ("fft", "wave"), ("int8", "block")])
 def test_zero_and_nonfinite_blocks(ctx, core, variant):
     _say("case: zero / non-finite blocks", core, variant)
     s = synth.gaussian(10000, 3)
@@ -311,6 +311,48 @@ def test_c2_fft_full_size(ctx, c2, mode, S, variant):
     s, k = c2
     got, fields, info = _run_fixed(ctx, s, k, 4096, mode, "fft", S, S, variant=VARIANTS[variant])
     _check_packed(s, k, 4096, mode, S, got, fields, info)
+
+
+@pytest.mark.parametrize("mode,S", [(O.ASYM2, 205), (O.SYM, 9), (O.ASYM3, 9), (O.ASYM2, 127), (O.SYM, 16)])
+def test_c2_int8_full_size(ctx, c2, mode, S):
+    """Integer matrix-core core on the FFT-block workload: every output and every integer field
+    equal to the oracle's, including symmetric S_q = K_q = 16 beyond Table 1's bound (no packing
+    here), and equal to the packed FFT core where that one is exact."""
+    _say("case: C2 full size int8 core", mode, S)
+    s, k = c2
+    got, fields, info = _run_fixed(ctx, s, k, 4096, mode, "int8", S, S)
+    _check_packed(s, k, 4096, mode, S, got, fields, info)
+    if O.max_q(mode, 1025) >= S:
+        fft, _, _ = _run_fixed(ctx, s, k, 4096, mode, "fft", S, S)
+        assert np.array_equal(got, fft)  # equal values (a zero may carry either sign)
+
+
+@pytest.mark.parametrize("mode,S", [(O.SYM, 0), (O.ASYM2, 0), (O.ASYM3, 0), (O.ASYM2, 127), (O.SYM, 40),
+                                    (O.ASYM2, 300), (O.ASYM3, 16319)])
+@pytest.mark.parametrize("L,N,Wb", [(50000, 256, 1024), (9000, 101, 512), (300, 33, 128), (7, 7, 64),
+                                    (40000, 1024, 4096), (30001, 2000, 8192), (5000, 64, 20000)])
+def test_int8_core_small(ctx, mode, S, L, N, Wb):
+    """Integer core against the oracle: several tiles per block, ragged tails, block 0's leading
+    outputs, one-digit and two-digit operands (S_q above 127), S_q beyond the packing bounds."""
+    No = N if N % 2 else N + 1
+    Sq = S or O.max_q(mode, No)
+    _say("case: int8 core", mode, Sq, L, N, Wb)
+    s, k = synth.ar1(L, 61 + N), synth.hann_lowpass(N, 0.2)
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "int8", Sq, Sq)
+    _check_packed(s, k, Wb, mode, Sq, got, fields, info)
+
+
+def test_int8_core_xcorr_and_errors(ctx):
+    s, k = synth.gaussian(30000, 71), synth.uniform(300, 72)
+    S = O.max_q(O.ASYM2, 301)
+    got, fields, info = _run_fixed(ctx, s, k, 2048, O.ASYM2, "int8", S, S, op=apx.APX_XCORR)
+    _check_packed(s, k, 2048, O.ASYM2, S, got, fields, info, kernel_for_oracle=k[::-1].copy())
+    tk = _dev(k)
+    for mode, kw in ((apx.APX_FULL_FP32, {}), (apx.APX_AUTO_SNR, {"snr_min_db": 30.0}),
+                     (apx.APX_ASYM2, {"Sq": 16320, "Kq": 16320})):
+        with pytest.raises(apx.ApxError) as e:
+            apx.Kernel(ctx, tk, 2048, mode=mode, core=apx.APX_CORE_INT8, **kw)
+        assert e.value.status == apx.APX_E_UNSUPPORTED, mode
 
 
 def test_c2_auto_snr_selection(ctx, c2):
