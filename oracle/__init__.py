@@ -5,3 +5,4 @@ Shares no code with the HIP library and imports nothing from it.
 """
 from .core import *  # noqa: F401,F403
 from .core import _packed_core  # noqa: F401
+from . import marginal  # noqa: F401

@@ -10,7 +10,8 @@ shapes and value distributions follow the paper's experiments and the measured w
 * pink (1/f) noise channels;
 * U[-128, 128] data as in Section IV.A;
 * batched correlation sets (references, noisy template excerpts) and Poisson request streams;
-* two-channel audio with a known delay per segment (the multi-channel delay application).
+* two-channel audio with a known delay per segment (the multi-channel delay application);
+* Weibull-marginal correlated features (the music-matching features of Fig. 4(a)).
 """
 from __future__ import annotations
 
@@ -95,6 +96,17 @@ def xcorr_batch(n_templates: int = 4096, n_refs: int = 64, seed_refs: int = 3001
         ridx.append(j)
         offs.append(off)
     return refs, tmpls, np.array(ridx), np.array(offs)
+
+
+def weibull_features(L: int, seed: int, lam: float = 0.248, kappa: float = 1.191, a: float = 0.9) -> np.ndarray:
+    """Nonnegative, temporally correlated feature sequence with a Weibull(lam, kappa) marginal
+    (the music-matching features' fit of Fig. 4(a)): a unit-variance Gaussian AR(1) with
+    coefficient a, mapped through the normal CDF and the Weibull inverse CDF."""
+    from scipy.special import ndtr
+    e = np.random.default_rng(seed).standard_normal(L)
+    g = lfilter([math.sqrt(1.0 - a * a)], [1.0, -a], e)
+    u = np.clip(ndtr(g), 0.0, 1.0 - 1e-16)
+    return (lam * (-np.log1p(-u)) ** (1.0 / kappa)).astype(np.float32)
 
 
 def two_channel(L: int, seed: int, seg: int = 44100, max_delay: int = 200, mono_frac: float = 0.25,

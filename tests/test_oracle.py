@@ -332,3 +332,61 @@ def test_selector_deterministic_cases():
     assert p.mode == O.ASYM2
     p = O.select_mode(0.0, 0.0, 1.0, 0.4, N, 200.0)
     assert p.mode == O.SYM
+
+
+# ---------------------------------------------------------------- Section IV.D, Fig. 4: marginal fits
+def test_laplace_fit_matches_library_mle():
+    import scipy.stats as ss
+    x = np.random.default_rng(91).laplace(0.0, 0.37, 20000)
+    f = O.marginal.fit_laplace(x)
+    loc, scale = ss.laplace.fit(x, floc=0.0)
+    assert loc == 0.0 and abs(f.scale - scale) <= 1e-12 * scale
+    assert abs(f.sigma - math.sqrt(2.0) * scale) <= 1e-12 * scale
+
+
+def test_weibull_fit_matches_library_mle():
+    import scipy.stats as ss
+    for lam, kap, seed in ((0.248, 1.191, 92), (2.0, 0.7, 93), (1.0, 3.5, 94)):
+        x = lam * np.random.default_rng(seed).weibull(kap, 20000)
+        f = O.marginal.fit_weibull(x)
+        c, loc, scale = ss.weibull_min.fit(x, floc=0.0)
+        # same maximum as the library's optimizer (to its tolerance), and no lower a likelihood
+        assert abs(f.shape - c) <= 1e-4 * c and abs(f.scale - scale) <= 1e-4 * scale, (f, c, scale)
+        ll_f = ss.weibull_min.logpdf(x, f.shape, 0.0, f.scale).sum()
+        ll_s = ss.weibull_min.logpdf(x, c, 0.0, scale).sum()
+        assert ll_f >= ll_s - 1e-9 * abs(ll_s)
+
+
+def test_marginal_second_moments_closed_forms():
+    """sigma^2 = 2 b^2 (Laplacian) and lambda^2 Gamma(1 + 2/kappa) (Weibull) against the sample
+    second moment of a million draws; the fit recovers Fig. 4(a)'s lambda = 0.248, kappa = 1.191."""
+    rng = np.random.default_rng(95)
+    xl = rng.laplace(0.0, 0.3, 1_000_000)
+    fl = O.marginal.fit_laplace(xl)
+    assert abs(fl.sigma ** 2 / np.mean(xl ** 2) - 1.0) < 0.01
+    xw = 0.248 * rng.weibull(1.191, 1_000_000)
+    fw = O.marginal.fit_weibull(xw)
+    assert abs(fw.scale / 0.248 - 1.0) < 0.005 and abs(fw.shape / 1.191 - 1.0) < 0.005
+    assert abs(fw.sigma ** 2 / np.mean(xw ** 2) - 1.0) < 0.01
+    # zero samples carry no Weibull likelihood (reading R19)
+    fz = O.marginal.fit_weibull(np.concatenate([xw[:5000], np.zeros(300)]))
+    assert fz.n == 5000
+
+
+def test_source_sigma_selection_reduces_to_block_rms():
+    """With every block's root second moment and maximum equal (a +-1 square wave whose period
+    divides the block stride), source-level sigmas equal to them select exactly as the per-block
+    selector does."""
+    N, Wb = 101, 1024
+    W = Wb - N - 1
+    s = np.where((np.arange(40 * W) // 1) % 2 == 0, 1.0, -1.0).astype(np.float32)
+    k = synth.hann_lowpass(N, 0.1)
+    kmax, krms = O.kernel_stats(k)
+    for target in (20.0, 40.0, 60.0, 200.0):
+        a = O.auto_params(s, k, Wb, target, 1.5)
+        b = O.marginal.auto_params_sigma(s, k, Wb, target, 1.0, krms, 1.5)
+        full = [p.rms == 1.0 for p in a]  # the ragged last window is zero padded: lower rms
+        assert sum(full) >= len(a) - 1
+        assert [p.mode for p, f in zip(a, full) if f] == [q.mode for q, f in zip(b, full) if f]
+        assert all(abs(p.snr_pred_db - q.snr_pred_db) < 1e-9 for p, q, f in zip(a, b, full)
+                   if f and p.mode != O.FULL)
