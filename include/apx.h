@@ -70,6 +70,10 @@ typedef struct {
                              per block with LDS passes, 2 = one wavefront per block, 3 = a group
                              of 512-point wavefront transforms per block (2 and 3: supported
                              sizes only) */
+    double sigma_s;       /* > 0: the signal's sigma in eq. (18) for every block (a source-level
+                             value, e.g. from apx_fit_marginal, Section IV.D); 0 = each block's
+                             root second moment.  The block maximum still sets sigma_v. */
+    double sigma_k;       /* > 0: the kernel's sigma in eq. (18); 0 = the taps' root second moment */
 } apx_params;
 
 #define APX_FLAG_NONFINITE 1
@@ -128,6 +132,18 @@ apx_status apx_debug_fields(apx_ctx ctx, apx_kernel kern, const float* s_in, int
  * params.calib_db is NaN) and in *offset_db (host).  Synchronizes `stream`. */
 apx_status apx_calibrate(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t L, int32_t block, int32_t Q,
                          void* stream, double* offset_db);
+
+/* Marginal-CDF fit of a source's samples (Section IV.D, Fig. 4), for the sigma of eq. (18).
+ * x: device, n FP32 samples.  model: APX_MARGINAL_LAPLACE (zero-mean Laplacian, scale b = mean |x|
+ * by maximum likelihood, sigma = sqrt(2) b) or APX_MARGINAL_WEIBULL (two-parameter Weibull of
+ * the positive samples by maximum likelihood: Newton's method on the shape equation, then the
+ * scale; sigma = lambda sqrt(Gamma(1 + 2/kappa)); samples <= 0 are left out).
+ * out (host, 4 doubles): scale (b or lambda), shape (1 or kappa), sigma, samples used.  One
+ * workgroup runs the whole fit on the device; synchronizes `stream`.
+ * APX_E_INVALID: null pointers, n < 1, unknown model, or fewer than 2 positive samples for a
+ * Weibull fit. */
+typedef enum { APX_MARGINAL_LAPLACE = 0, APX_MARGINAL_WEIBULL = 1 } apx_marginal;
+apx_status apx_fit_marginal(apx_ctx ctx, const float* x, int64_t n, int32_t model, double* out, void* stream);
 
 /* One-shot convolution / correlation: kernel_create + run + kernel_destroy. Synchronizes. */
 apx_status apx_conv(apx_ctx ctx, const float* s_in, int64_t L, const float* k, int32_t N, int32_t W_block,

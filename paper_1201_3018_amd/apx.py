@@ -23,6 +23,7 @@ APX_CORE_AUTO, APX_CORE_TIME, APX_CORE_FFT, APX_CORE_INT8 = 0, 1, 2, 3
 APX_CONV, APX_XCORR = 0, 1
 APX_FLAG_NONFINITE, APX_FLAG_ZERO = 1, 2
 APX_FB_F16X3, APX_FB_BF16X3 = 0, 1
+APX_MARGINAL_LAPLACE, APX_MARGINAL_WEIBULL = 0, 1
 
 MODE_NAMES = {APX_FULL_FP32: "full", APX_SYM: "sym", APX_ASYM2: "asym2", APX_ASYM3: "asym3",
               APX_AUTO_SNR: "auto", APX_FULL_FP64: "full64"}
@@ -33,13 +34,14 @@ EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "ap
            "apx_batch_run", "apx_batch_blocks", "apx_batch_describe", "apx_batch_destroy", "apx_xcorr_argmax_batch",
            "apx_fbank_create", "apx_fbank_run", "apx_fbank_describe", "apx_fbank_destroy", "apx_workspace_bytes",
            "apx_run_auto", "apx_server_create", "apx_server_submit", "apx_server_poll", "apx_server_drain",
-           "apx_server_stats", "apx_server_destroy", "apx_server_now", "apx_status_str", "apx_last_error")
+           "apx_server_stats", "apx_server_destroy", "apx_server_now", "apx_fit_marginal", "apx_status_str",
+           "apx_last_error")
 
 
 class apx_params(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("core", ctypes.c_int32), ("Sq", ctypes.c_int32), ("Kq", ctypes.c_int32),
                 ("snr_min_db", ctypes.c_double), ("calib_db", ctypes.c_double), ("allow_unsafe", ctypes.c_int32),
-                ("fft_variant", ctypes.c_int32)]
+                ("fft_variant", ctypes.c_int32), ("sigma_s", ctypes.c_double), ("sigma_k", ctypes.c_double)]
 
 
 class apx_block_info(ctypes.Structure):
@@ -125,6 +127,7 @@ def lib() -> ctypes.CDLL:
         L.apx_server_destroy.argtypes = [vp]
         L.apx_server_now.argtypes = []
         L.apx_server_now.restype = dp
+        L.apx_fit_marginal.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
         L.apx_status_str.argtypes = [ctypes.c_int]
         L.apx_status_str.restype = ctypes.c_char_p
         L.apx_last_error.restype = ctypes.c_char_p
@@ -144,9 +147,9 @@ FFT_AUTO, FFT_BLOCK, FFT_WAVE, FFT_GROUP = 0, 1, 2, 3
 
 
 def params(mode=APX_FULL_FP32, core=APX_CORE_AUTO, Sq=0, Kq=0, snr_min_db=0.0, calib_db=float("nan"),
-           allow_unsafe=False, fft_variant=FFT_AUTO) -> apx_params:
+           allow_unsafe=False, fft_variant=FFT_AUTO, sigma_s=0.0, sigma_k=0.0) -> apx_params:
     return apx_params(int(mode), int(core), int(Sq), int(Kq), float(snr_min_db), float(calib_db),
-                      1 if allow_unsafe else 0, int(fft_variant))
+                      1 if allow_unsafe else 0, int(fft_variant), float(sigma_s), float(sigma_k))
 
 
 def _dev_ptr(t, dtype_name: str):
@@ -208,6 +211,13 @@ def apx_calibrate(ctx, kern, s, block: int = 0, Q: int = 8, stream=None) -> floa
     _check(lib().apx_calibrate(ctx, kern, _dev_ptr(s, "float32"), s.numel(), block, Q, _stream(stream),
                                ctypes.byref(off)))
     return off.value
+
+
+def apx_fit_marginal(ctx, x, model: int, stream=None):
+    """(scale, shape, sigma, samples used) of the marginal fit of the device samples x."""
+    out = (ctypes.c_double * 4)()
+    _check(lib().apx_fit_marginal(ctx, _dev_ptr(x, "float32"), x.numel(), int(model), out, _stream(stream)))
+    return tuple(out)
 
 
 def apx_workspace_bytes() -> int:
@@ -341,12 +351,12 @@ class Kernel:
 
     def __init__(self, ctx: Context, k, W_block: int, mode=APX_FULL_FP32, core=APX_CORE_AUTO, Sq=0, Kq=0,
                  snr_min_db=0.0, calib_db=float("nan"), op=APX_CONV, allow_unsafe=False, fft_variant=FFT_AUTO,
-                 stream=None):
+                 sigma_s=0.0, sigma_k=0.0, stream=None):
         self.ctx = ctx
         self.N = int(k.numel())
         self.W_block = W_block
         self.op = op
-        self.prm = params(mode, core, Sq, Kq, snr_min_db, calib_db, allow_unsafe, fft_variant)
+        self.prm = params(mode, core, Sq, Kq, snr_min_db, calib_db, allow_unsafe, fft_variant, sigma_s, sigma_k)
         self.h = apx_kernel_create(ctx.h, k, W_block, self.prm, op, stream)
 
     def geometry(self, L: int):

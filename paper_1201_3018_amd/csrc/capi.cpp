@@ -226,6 +226,8 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
     a.spec32 = k->spec32;
     a.twd = k->ctx->twd;
     a.twf = k->ctx->twf;
+    a.sigma_s = k->params.sigma_s > 0.0 ? k->params.sigma_s : 0.0;
+    a.sigma_k = k->params.sigma_k > 0.0 ? k->params.sigma_k : 0.0;
     if (k->wave) {
         for (int m = 0; m < 4; ++m) {
             if (!k->use[m]) continue;
@@ -651,20 +653,40 @@ apx_status apx_calibrate(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, i
         pr += h[2 * i];
         pe += h[2 * i + 1];
     }
-    const double smax = h[2 * nparts], rms = h[2 * nparts + 1];
-    if (pe <= 0.0 || pr <= 0.0 || rms <= 0.0 || ks.krms <= 0.0)
+    const double smax = h[2 * nparts], rms = h[2 * nparts + 1];  // rms: the source sigma when one is set
+    const double krms = ks.krms > 0.0 && k->params.sigma_k > 0.0 ? k->params.sigma_k : ks.krms;
+    if (pe <= 0.0 || pr <= 0.0 || rms <= 0.0 || krms <= 0.0)
         return fail(APX_E_INVALID, "calibration block has no quantization error or no signal");
     const double measured = 10.0 * log10(pr / pe);
     const double r12 = sqrt(12.0);
     const double svs = smax / (Q * r12), svk = ks.kmax / (Q * r12);
-    const double D = (rms * svk) * (rms * svk) + (ks.krms * svs) * (ks.krms * svs) + (svk * svs) * (svk * svs);
-    const double model = 10.0 * log10((rms * ks.krms) * (rms * ks.krms) / D);
+    const double D = (rms * svk) * (rms * svk) + (krms * svs) * (krms * svs) + (svk * svs) * (svk * svs);
+    const double model = 10.0 * log10((rms * krms) * (rms * krms) / D);
     k->calib_db = measured - model;
     if (offset_db) *offset_db = k->calib_db;
     return APX_OK;
 }
 
 size_t apx_workspace_bytes(void) { return 2048; }
+
+apx_status apx_fit_marginal(apx_ctx ctx, const float* x, int64_t n, int32_t model, double* out, void* stream) {
+    if (!ctx || !x || !out) return fail(APX_E_INVALID, "null argument");
+    if (n < 1) return fail(APX_E_INVALID, "n = %lld samples", (long long)n);
+    if (model != APX_MARGINAL_LAPLACE && model != APX_MARGINAL_WEIBULL)
+        return fail(APX_E_INVALID, "unknown marginal model %d", model);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    double* d = nullptr;
+    HIPCHK(hipMalloc((void**)&d, 4 * sizeof(double)));
+    hipError_t e = launch_fit_marginal(x, n, model, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(APX_E_DEVICE, "marginal fit: %s", hipGetErrorString(e));
+    if (model == APX_MARGINAL_WEIBULL && out[3] < 2.0)
+        return fail(APX_E_INVALID, "a Weibull fit needs at least 2 positive samples (%g)", out[3]);
+    return APX_OK;
+}
 
 apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info,
                         double snr_min_db, int32_t calib_block, void* workspace, void* stream) {
@@ -684,7 +706,7 @@ apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, fl
     double* off = part + 2 * nparts + 2;
     RunArgs a = make_args(k, s, L, out, nullptr, info, P);
     HIPCHK(launch_calib(a, calib_block, Q, part, nparts, st));
-    HIPCHK(launch_calib_finish(part, nparts, k->ks, Q, off, st));
+    HIPCHK(launch_calib_finish(part, nparts, k->ks, Q, off, k->params.sigma_k > 0.0 ? k->params.sigma_k : 0.0, st));
     a.calib_dev = off;
     a.snr_min_db = snr_min_db;
     return launch_block_kernel(k, a, st);

@@ -339,8 +339,11 @@ __device__ __forceinline__ double wsnr_ratio(double rms, double smax, double krm
 
 __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& st) {
     WChoice c;
-    const KState ks = *a.ks;
-    const double rms = sqrt(st.sumsq / (double)a.W_block);
+    KState ks = *a.ks;
+    // eq. (18)'s sigmas: the block's and the taps' root second moments, or source-level values
+    const double rms = a.sigma_s > 0.0 ? a.sigma_s : sqrt(st.sumsq / (double)a.W_block);
+    const bool kzero = ks.krms == 0.0;
+    if (a.sigma_k > 0.0) ks.krms = a.sigma_k;
     c.flags = 0;
     c.snr_db = INFINITY;
     c.mode = a.mode;
@@ -354,7 +357,7 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
 #pragma unroll
         for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
             if (!((a.cand_mask >> m) & 1) || a.S[m] < 1) continue;
-            if (st.smax == 0.0 || ks.krms == 0.0) {
+            if (st.smax == 0.0 || kzero) {
                 c.mode = m;
                 break;
             }
@@ -374,7 +377,7 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
         const double ck = s1 ? ks.ck[1] : (s2 ? ks.ck[2] : ks.ck[3]);
         c.cs = st.smax == 0.0 ? 0.0 : (double)c.S / st.smax;
         c.inv = 1.0 / (c.cs * ck);
-        if (a.info && a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
+        if (a.info && a.mode != MD_AUTO && st.smax != 0.0 && !kzero)
             c.snr_db = 10.0 * log10(wsnr_ratio(rms, st.smax, ks.krms, ks.kmax, c.S, c.K));
     } else {
         c.S = c.K = 0;

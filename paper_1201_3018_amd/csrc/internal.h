@@ -66,6 +66,8 @@ struct RunArgs {
     const float2* wtwf;
     const double2* coef[4];
     const float2* coef32;
+    double sigma_s;  // > 0: the signal's sigma in the SNR model for every block (else block rms)
+    double sigma_k;  // > 0: the kernel's sigma in the SNR model (else the taps' root second moment)
 };
 
 // Host launchers (kernels.hip).
@@ -81,9 +83,12 @@ hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st);
 hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st);
 hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts,
                         hipStream_t st);
+// marginal fit (model 0 Laplacian, 1 Weibull) of n samples; out: 4 doubles on the device
+hipError_t launch_fit_marginal(const float* x, int64_t n, int32_t model, double* out, hipStream_t st);
 // offset = measured - model SNR from launch_calib's partials, written to *out (device)
+// (krms_override > 0 replaces the taps' root second moment, as RunArgs::sigma_k)
 hipError_t launch_calib_finish(const double* partial, int32_t nparts, const KState* ks, int32_t Q, double* out,
-                               hipStream_t st);
+                               double krms_override, hipStream_t st);
 hipError_t fft_set_lds(int logF);
 size_t td_lds_bytes(int mode, int N_odd, int W_block, int T2, int T3);
 // wave-per-block FFT core (fftw.hip)

@@ -167,8 +167,11 @@ struct Choice {
 
 __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st) {
     Choice c;
-    const KState ks = *a.ks;
-    const double rms = sqrt(st.sumsq / (double)a.W_block);
+    KState ks = *a.ks;
+    // eq. (18)'s sigmas: each block's and the taps' root second moments, or source-level values
+    const double rms = a.sigma_s > 0.0 ? a.sigma_s : sqrt(st.sumsq / (double)a.W_block);
+    const bool kzero = ks.krms == 0.0;
+    if (a.sigma_k > 0.0) ks.krms = a.sigma_k;
     c.flags = 0;
     c.snr_db = INFINITY;
     c.mode = a.mode;
@@ -182,7 +185,7 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
 #pragma unroll
         for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
             if (!((a.cand_mask >> m) & 1) || a.S[m] < 1) continue;
-            if (st.smax == 0.0 || ks.krms == 0.0) {
+            if (st.smax == 0.0 || kzero) {
                 c.mode = m;
                 break;
             }
@@ -203,7 +206,7 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
         const double ck = s1 ? ks.ck[1] : (s2 ? ks.ck[2] : ks.ck[3]);
         c.cs = st.smax == 0.0 ? 0.0 : (double)c.S / st.smax;
         c.inv = 1.0 / (c.cs * ck);
-        if (a.info && a.mode != MD_AUTO && st.smax != 0.0 && ks.krms != 0.0)
+        if (a.info && a.mode != MD_AUTO && st.smax != 0.0 && !kzero)
             c.snr_db = 10.0 * log10(snr_ratio(rms, st.smax, ks.krms, ks.kmax, c.S, c.K));
     } else {
         c.S = c.K = 0;
@@ -1067,7 +1070,7 @@ __global__ void __launch_bounds__(NT) k_calib(RunArgs a, int64_t block, int32_t 
         partial[2 * blockIdx.x + 1] = a1;
         if (blockIdx.x == 0) {
             partial[2 * G] = st.smax;
-            partial[2 * G + 1] = sqrt(st.sumsq / (double)a.W_block);
+            partial[2 * G + 1] = a.sigma_s > 0.0 ? a.sigma_s : sqrt(st.sumsq / (double)a.W_block);
         }
     }
 }
@@ -1080,7 +1083,7 @@ hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* part
 // Same arithmetic as the host side of apx_calibrate, in the same order.  A block without
 // quantization error or without signal gives offset 0 (the model alone).
 __global__ void k_calib_finish(const double* __restrict__ partial, int32_t nparts, const KState* __restrict__ ks,
-                               int32_t Q, double* out) {
+                               int32_t Q, double* out, double krms_override) {
     if (threadIdx.x != 0) return;
     double pr = 0.0, pe = 0.0;
     for (int i = 0; i < nparts; ++i) {
@@ -1088,7 +1091,7 @@ __global__ void k_calib_finish(const double* __restrict__ partial, int32_t npart
         pe += partial[2 * i + 1];
     }
     const double smax = partial[2 * nparts], rms = partial[2 * nparts + 1];
-    const double kmax = ks->kmax, krms = ks->krms;
+    const double kmax = ks->kmax, krms = ks->krms > 0.0 && krms_override > 0.0 ? krms_override : ks->krms;
     double off = 0.0;
     if (pe > 0.0 && pr > 0.0 && rms > 0.0 && krms > 0.0) {
         const double measured = 10.0 * log10(pr / pe);
@@ -1102,8 +1105,139 @@ __global__ void k_calib_finish(const double* __restrict__ partial, int32_t npart
 }
 
 hipError_t launch_calib_finish(const double* partial, int32_t nparts, const KState* ks, int32_t Q, double* out,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_calib_finish, dim3(1), dim3(64), 0, st, partial, nparts, ks, Q, out);
+                               double krms_override, hipStream_t st) {
+    hipLaunchKernelGGL(k_calib_finish, dim3(1), dim3(64), 0, st, partial, nparts, ks, Q, out, krms_override);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Marginal-CDF fit of a source's samples (Section IV.D, Fig. 4): one workgroup of 1024 threads
+// runs the whole fit.  Laplacian (zero mean): b = mean |x|.  Weibull (positive samples): the
+// shape kappa solves sum(y^k ln y) / sum(y^k) - 1/k - mean(ln y) = 0 (lambda profiled out), by
+// Newton's method from the moment start pi / (sqrt 6 sd(ln y)), with y = x / max(x); then
+// lambda = max(x) (mean y^kappa)^(1/kappa).  sigma: square root of the fitted second moment.
+// ------------------------------------------------------------------------------------------
+constexpr int FIT_NT = 1024;
+
+// sums of three values over the workgroup; every thread gets the totals
+__device__ __forceinline__ void fit_sum3(double& a, double& b, double& c, double* red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();  // red is reused by consecutive calls
+    if ((threadIdx.x & 63) == 0) {
+        red[3 * w] = a;
+        red[3 * w + 1] = b;
+        red[3 * w + 2] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int i = 0; i < FIT_NT / 64; ++i) {
+        a += red[3 * i];
+        b += red[3 * i + 1];
+        c += red[3 * i + 2];
+    }
+}
+
+__global__ void __launch_bounds__(FIT_NT) k_fit_marginal(const float* __restrict__ x, int64_t n, int32_t model,
+                                                         double* out) {
+    __shared__ double red[3 * (FIT_NT / 64)];
+    if (model == 0) {
+        double s = 0.0, z0 = 0.0, z1 = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += FIT_NT) s += fabs((double)x[i]);
+        fit_sum3(s, z0, z1, red);
+        if (threadIdx.x == 0) {
+            const double b = s / (double)n;
+            out[0] = b;
+            out[1] = 1.0;
+            out[2] = sqrt(2.0) * b;
+            out[3] = (double)n;
+        }
+        return;
+    }
+    // positive samples: count and maximum
+    double cnt = 0.0, mx = 0.0, z1 = 0.0, z2 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += FIT_NT) {
+        const double v = (double)x[i];
+        if (v > 0.0) {
+            cnt += 1.0;
+            mx = fmax(mx, v);
+        }
+    }
+    {
+        // the maximum: a reduction of its own
+        double m = mx;
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[w] = m;
+        __syncthreads();
+        mx = 0.0;
+        for (int i = 0; i < FIT_NT / 64; ++i) mx = fmax(mx, red[i]);
+        __syncthreads();
+    }
+    fit_sum3(cnt, z1, z2, red);
+    if (cnt < 2.0) {
+        if (threadIdx.x == 0) {
+            out[0] = 0.0;
+            out[1] = 1.0;
+            out[2] = 0.0;
+            out[3] = cnt;
+        }
+        return;
+    }
+    // mean and spread of ln y
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += FIT_NT) {
+        const double v = (double)x[i];
+        if (v > 0.0) {
+            const double ly = log(v / mx);
+            s1 += ly;
+            s2 += ly * ly;
+        }
+    }
+    fit_sum3(s1, s2, s3, red);
+    const double mly = s1 / cnt;
+    const double var = fmax(s2 / cnt - mly * mly, 0.0);
+    double k = var > 0.0 ? 3.14159265358979323846 / (sqrt(6.0) * sqrt(var)) : 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += FIT_NT) {
+            const double v = (double)x[i];
+            if (v > 0.0) {
+                const double ly = log(v / mx);
+                const double yk = exp(k * ly);
+                a0 += yk;
+                a1 += yk * ly;
+                a2 += yk * ly * ly;
+            }
+        }
+        fit_sum3(a0, a1, a2, red);
+        const double g = a1 / a0 - 1.0 / k - mly;
+        const double dg = (a2 * a0 - a1 * a1) / (a0 * a0) + 1.0 / (k * k);
+        double kn = k - g / dg;
+        if (kn <= 0.0) kn = 0.5 * k;
+        const bool done = fabs(kn - k) <= 1e-13 * k;  // same value in every thread
+        k = kn;
+        if (done) break;
+    }
+    double a0 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += FIT_NT) {
+        const double v = (double)x[i];
+        if (v > 0.0) a0 += exp(k * log(v / mx));
+    }
+    fit_sum3(a0, d1, d2, red);
+    if (threadIdx.x == 0) {
+        const double lam = mx * pow(a0 / cnt, 1.0 / k);
+        out[0] = lam;
+        out[1] = k;
+        out[2] = lam * sqrt(tgamma(1.0 + 2.0 / k));
+        out[3] = cnt;
+    }
+}
+
+hipError_t launch_fit_marginal(const float* x, int64_t n, int32_t model, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_fit_marginal, dim3(1), dim3(FIT_NT), 0, st, x, n, model, out);
     return hipGetLastError();
 }
 
