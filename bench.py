@@ -587,7 +587,8 @@ def bench_c5(args, wl, duration: float = 10.0, rate: float = 2000.0):
 def bench_c1sweep(args, wl):
     """Time-domain core across kernel lengths: per mode, output samples/s, with the measured SNR
     of every mode against the FP64 path on the first 2^18 outputs.  FMAs per output: FP32 and
-    FP64 N, asymmetric M=2 N/2, symmetric ceil(N/2)/2 (one packed word carries two outputs)."""
+    FP64 N, asymmetric M=2 N/2, symmetric ceil(N/2)/2 (one packed word carries two outputs).
+    Beside them, the integer matrix-core core at the same companding (same outputs)."""
     import torch
 
     from paper_1201_3018_amd import apx, synth
@@ -605,10 +606,14 @@ def bench_c1sweep(args, wl):
         tk = torch.from_numpy(k).to(dev)
         out = torch.empty(L + N - 1, dtype=torch.float32, device=dev)
         ref = None
+        first = {}
         row = {"N": N, "W_block": Wb}
-        for name, mode in (("fp64", apx.APX_FULL_FP64), ("fp32", apx.APX_FULL_FP32), ("sym", apx.APX_SYM),
-                           ("asym2", apx.APX_ASYM2)):
-            kern = apx.Kernel(ctx, tk, Wb, mode=mode, core=apx.APX_CORE_TIME)
+        for name, mode, core in (("fp64", apx.APX_FULL_FP64, apx.APX_CORE_TIME),
+                                 ("fp32", apx.APX_FULL_FP32, apx.APX_CORE_TIME), ("sym", apx.APX_SYM, apx.APX_CORE_TIME),
+                                 ("asym2", apx.APX_ASYM2, apx.APX_CORE_TIME),
+                                 ("int8_sym", apx.APX_SYM, apx.APX_CORE_INT8),
+                                 ("int8_asym2", apx.APX_ASYM2, apx.APX_CORE_INT8)):
+            kern = apx.Kernel(ctx, tk, Wb, mode=mode, core=core)
             kern.run(ts, out=out)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -619,6 +624,7 @@ def bench_c1sweep(args, wl):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             r = out[: 1 << 18].cpu().numpy().astype(np.float64)
+            first[name] = r
             if name == "fp64":
                 ref = r
                 snr = float("inf")
@@ -627,6 +633,8 @@ def bench_c1sweep(args, wl):
                 snr = float("inf") if e == 0 else 10 * math.log10(float(np.sum(ref ** 2)) / e)
             row[name] = {"ms": ms, "samples_per_s": (L + N - 1) / (ms * 1e-3), "snr_db": snr}
             kern.close()
+        row["int8_equals_packed"] = bool(np.array_equal(first["int8_sym"], first["sym"]) and
+                                         np.array_equal(first["int8_asym2"], first["asym2"]))
         row["sym_over_fp64"] = row["fp64"]["ms"] / row["sym"]["ms"]
         row["sym_over_fp32"] = row["fp32"]["ms"] / row["sym"]["ms"]
         row["asym2_over_fp32"] = row["fp32"]["ms"] / row["asym2"]["ms"]
