@@ -54,7 +54,9 @@ typedef enum {
    r~ = s~ * k~ (eq. 2 on both operands) of a fixed packed mode's S_q, K_q exactly on the int8
    matrix cores (balanced base-128 digits when S_q or K_q exceed 127, up to 16319), then eq. (16):
    no FP64 packing, so it is exact whatever Table 1's bound says and its outputs equal the packed
-   cores' wherever their unpacking is exact.  Fixed packed modes only; one wavefront per block. */
+   cores' wherever their unpacking is exact.  Fixed packed modes only; one wavefront per block.
+   APX_CORE_AUTO: N <= 129 runs a fixed packed mode on APX_CORE_INT8 (when its LDS fits) and other
+   modes on the time-domain core; longer kernels run on the FFT core. */
 typedef enum { APX_CORE_AUTO = 0, APX_CORE_TIME = 1, APX_CORE_FFT = 2, APX_CORE_INT8 = 3 } apx_core;
 typedef enum { APX_CONV = 0, APX_XCORR = 1 } apx_op;
 

@@ -412,7 +412,16 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         }
         core = APX_CORE_TIME;
     }
-    if (core == APX_CORE_AUTO) core = (N_odd <= 129) ? APX_CORE_TIME : APX_CORE_FFT;
+    if (core == APX_CORE_AUTO) {
+        // short kernels: the integer matrix cores for a fixed packed mode (the same companded
+        // integers as the packed time-domain core, measured several times faster), else the
+        // time-domain core; long kernels: the FFT core
+        core = (N_odd <= 129) ? APX_CORE_TIME : APX_CORE_FFT;
+        if (core == APX_CORE_TIME && p.mode >= APX_SYM && p.mode <= APX_ASYM3 && fft_words == 0 &&
+            k->S[p.mode] <= 16319 && k->K[p.mode] <= 16319 &&
+            i8_lds_bytes(i8_plane_len(N_odd, W), W_block) <= (size_t)ctx->max_lds)
+            core = APX_CORE_INT8;
+    }
     if (fft_words > 0) core = APX_CORE_FFT;
     k->core = core;
     if (core == APX_CORE_INT8) {
