@@ -780,8 +780,11 @@ __device__ __forceinline__ unsigned long long wave_umax64(unsigned long long v) 
     return v;
 }
 
+// two waves per SIMD wherever the LDS of one item lets two workgroups share a CU (measured 1.65x
+// on the symmetric 2^13 length: the latency of one item's passes is hidden by the other's)
 template <int MODE, int LOGW>
-__global__ void __launch_bounds__(NT) k_batch(const RunArgs* __restrict__ targs, const int2* __restrict__ items,
+__global__ void __launch_bounds__(NT, (MODE == MD_FULL32 ? LOGW <= 14 : LOGW <= 13) ? 2 : 1)
+    k_batch(const RunArgs* __restrict__ targs, const int2* __restrict__ items,
                                               int32_t nitems, int32_t chunk, unsigned int* counter,
                                               unsigned long long* keys) {
     constexpr int MW = 1 << (LOGW - 1);  // complex points: 2^LOGW packed words
