@@ -428,8 +428,31 @@ __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem
     int nf = 0;
     const float* p = a.s + it.start;  // start is even: 8-byte aligned
     constexpr int CH = 16;             // float2 loads in flight per lane
+    // statistics of one sample pair (non-finite samples count as zero and flag the block)
+    auto take = [&](float x0, float x1) {
+        const bool f0 = isfinite(x0), f1 = isfinite(x1);
+        if (!(f0 && f1)) nf = 1;
+        const double d0 = (double)(f0 ? x0 : 0.0f), d1 = (double)(f1 ? x1 : 0.0f);
+        m = fmax(m, fmax(fabs(d0), fabs(d1)));
+        q += d0 * d0 + d1 * d1;
+    };
     for (int base = 0; base < a.W_block; base += 128 * CH) {
         float2 f[CH];
+        // wave-uniform: the whole chunk lies inside the signal, the valid part and the window, so
+        // it needs no per-sample bounds (every block but the last)
+        const int end = base + 128 * CH;
+        if (end <= it.nwin && end <= it.nvalid && end <= a.W_block) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) f[c] = *reinterpret_cast<const float2*>(p + base + 2 * threadIdx.x + 128 * c);
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + 2 * threadIdx.x + 128 * c;
+                take(f[c].x, f[c].y);
+                win[i] = f[c].x;
+                win[i + 1] = f[c].y;
+            }
+            continue;
+        }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * threadIdx.x + 128 * c;
@@ -441,13 +464,9 @@ __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * threadIdx.x + 128 * c;
             if (i < a.W_block) {
-                const float x0 = f[c].x, x1 = f[c].y;
-                if (!isfinite(x0) || !isfinite(x1)) nf = 1;
-                const double d0 = isfinite(x0) ? (double)x0 : 0.0, d1 = isfinite(x1) ? (double)x1 : 0.0;
-                m = fmax(m, fmax(fabs(d0), fabs(d1)));
-                q += d0 * d0 + d1 * d1;
-                win[i] = (i < it.nvalid) ? x0 : 0.0f;
-                win[i + 1] = (i + 1 < it.nvalid) ? x1 : 0.0f;
+                take(f[c].x, f[c].y);
+                win[i] = (i < it.nvalid) ? f[c].x : 0.0f;
+                win[i + 1] = (i + 1 < it.nvalid) ? f[c].y : 0.0f;
             }
         }
     }
