@@ -141,6 +141,41 @@ def test_fft_core_packed_small(ctx, mode, L, N, Wb, variant):
     _check_packed(s, k, Wb, mode, S, got, fields, info)
 
 
+@pytest.mark.parametrize("tail", [2047, 2048, 2049, 3000])
+@pytest.mark.parametrize("mode", [O.SYM, O.ASYM2])
+def test_wave_window_chunk_edges(ctx, mode, tail):
+    """The one-wave core loads its window in chunks of 2048 samples and skips the per-sample
+    bounds on a chunk that lies wholly inside the signal.  A last window of 2047..3000 samples
+    puts the signal end just before, on and after a chunk edge."""
+    N, Wb = 1024, 4096
+    W = Wb - (N + 1) - 1
+    L = 5 * W - 2 + tail
+    part = O.partition(L, N, Wb)
+    assert L - int(part.starts[-1]) == tail
+    _say("case: wave window chunk edges", mode, L, tail)
+    s, k = synth.ar1(L, 700 + tail), synth.hann_lowpass(N)
+    S = O.max_q(mode, N + 1)
+    got, fields, info = _run_fixed(ctx, s, k, Wb, mode, "fft", S, S, variant=VARIANTS["wave"])
+    _check_packed(s, k, Wb, mode, S, got, fields, info)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_wave_nonfinite_in_full_chunk(ctx, bad):
+    """A non-finite sample inside a chunk that takes the unguarded loads still flags its
+    blocks: their outputs are NaN, every other block equals the oracle."""
+    N, Wb, L = 1024, 4096, 30000
+    s, k = synth.ar1(L, 731), synth.hann_lowpass(N)
+    s[12345] = bad
+    _say("case: wave non-finite in a full chunk", bad)
+    S = O.max_q(O.ASYM2, N + 1)
+    got, _, info = _run_fixed(ctx, s, k, Wb, O.ASYM2, "fft", S, S, variant=VARIANTS["wave"])
+    ref = O.conv_blocked(s, k, Wb, O.fixed_params(s, k, Wb, O.ASYM2, S, S))
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    fin = ~np.isnan(ref)
+    assert np.array_equal(got[fin], ref[fin])
+    assert np.count_nonzero(info["flags"] & apx.APX_FLAG_NONFINITE) >= 1
+
+
 @pytest.mark.parametrize("mode,N,Wb", [(O.ASYM2, 800, 8994), (O.ASYM3, 800, 8994), (O.SYM, 800, 17186),
                                        (O.ASYM2, 800, 17186), (O.ASYM3, 800, 17186), (O.ASYM3, 800, 33570),
                                        (O.SYM, 101, 32768), (O.ASYM2, 40, 600)])
