@@ -83,6 +83,23 @@ __global__ void __launch_bounds__(NT) k_fb_frag(const float* __restrict__ h, int
     frag[(KS + s) * 64 + lane] = lo;
 }
 
+// Workgroup barrier that orders LDS only: each wave waits for its own LDS operations, not for
+// its global stores (__syncthreads would drain a tile's output stores before the next tile).
+// The wavefront fences keep the compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int KS, int NW>
 struct FbGeom {
     static constexpr int NPAD = 16 * KS;
@@ -91,7 +108,11 @@ struct FbGeom {
     static constexpr int CS = CL + 8;        // copy stride in elements (16 B of bank offset)
     static constexpr size_t B_BYTES = (size_t)2 * KS * 64 * 16;
     static constexpr size_t A_BYTES = (size_t)2 * 8 * CS * 2;
-    static constexpr size_t LDS = B_BYTES + A_BYTES;
+    static constexpr int WS = CL + 8;        // raw window samples (the last chunk reads 7 past CL)
+    static constexpr size_t W_BYTES = (size_t)4 * WS;
+    static constexpr int TS = 36;            // transpose row stride in floats (16 B aligned, banks spread)
+    static constexpr size_t T_BYTES = (size_t)NW * 32 * TS * 4;
+    static constexpr size_t LDS = B_BYTES + A_BYTES + W_BYTES + T_BYTES;
 };
 
 template <int PREC, int KS, int NW>
@@ -107,6 +128,8 @@ __global__ void __launch_bounds__(64 * NW) k_fbank(const float* __restrict__ x, 
     extern __shared__ __attribute__((aligned(16))) char lds[];
     V* Bs = (V*)lds;
     T* As = (T*)(lds + G::B_BYTES);
+    float* Ws = (float*)(lds + G::B_BYTES + G::A_BYTES);
+    float* Tw = (float*)(lds + G::B_BYTES + G::A_BYTES + G::W_BYTES) + (size_t)(threadIdx.x >> 6) * (32 * G::TS);
     for (int i = threadIdx.x; i < 2 * KS * 64; i += NTH) Bs[i] = frag[i];
 
     // contiguous range of (channel, tile) items per workgroup
@@ -119,37 +142,61 @@ __global__ void __launch_bounds__(64 * NW) k_fbank(const float* __restrict__ x, 
     const int i = lane & 31, kh = lane >> 5, rl = i & 7;
     const bool vec_store = (ldy % 4) == 0;
 
-    for (int64_t item = it0; item < it1; ++item) {
+    // The raw window of the next tile is loaded into registers (RPT samples per thread, coalesced)
+    // while the current tile's products run: one workgroup fills a CU's LDS, so no other
+    // workgroup would hide these loads.  The copies are then built from an LDS staging row.
+    constexpr int RPT = (G::WS + NTH - 1) / NTH;
+    float pre[RPT];
+    auto fetch = [&](int64_t item) {
         const int c = (int)(item / ntiles);
         const int64_t t0 = (item - (int64_t)c * ntiles) * G::MT;
         const float* xc = x + (int64_t)c * ldx;
         const int64_t g0 = t0 - (G::NPAD - 1);
-        __syncthreads();  // B visible; the previous tile's reads of the window are done
+        const bool inside = g0 >= 0 && g0 + G::WS <= L;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int m = threadIdx.x + k * NTH;
+            const int64_t g = g0 + m;
+            pre[k] = 0.0f;
+            if (m < G::WS && (inside || (g >= 0 && g < L))) pre[k] = xc[g];
+        }
+    };
+    // the staging row takes the prefetched samples after the products and before the output
+    // stores, so that waiting for the loads never waits for this tile's stores
+    auto stage = [&]() {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int m = threadIdx.x + k * NTH;
+            if (m < G::WS) Ws[m] = pre[k];
+        }
+    };
+    if (it0 < it1) {
+        fetch(it0);
+        stage();
+    }
+
+    for (int64_t item = it0; item < it1; ++item) {
+        const int c = (int)(item / ntiles);
+        const int64_t t0 = (item - (int64_t)c * ntiles) * G::MT;
+        lds_barrier();  // B and the staged window visible; the previous tile's reads of As are done
+        // unconditional (the last tile fetches itself again): a load on every path lets the
+        // compiler see that no load is pending at the top of the loop
+        fetch(item + 1 < it1 ? item + 1 : item);
         // window copies: copy r, chunk q holds xw[8q + r .. 8q + r + 7] (hi and lo parts)
-        const bool inside = g0 >= 0 && g0 + G::CL + 8 <= L;
         for (int ch = threadIdx.x; ch < G::CL; ch += NTH) {
             const int r = ch & 7, q = ch >> 3;
-            const int64_t g = g0 + 8 * q + r;
-            float v[8];
-            if (inside) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = xc[g + j];
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = (g + j >= 0 && g + j < L) ? xc[g + j] : 0.0f;
-            }
             V hi, lo;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 T a, b;
-                S::split(v[j], a, b);
+                S::split(Ws[ch + j], a, b);
                 hi[j] = a;
                 lo[j] = b;
             }
             *(V*)(As + (size_t)r * G::CS + 8 * q) = hi;
             *(V*)(As + (size_t)(8 + r) * G::CS + 8 * q) = lo;
         }
-        __syncthreads();
+        lds_barrier();
 
         // A fragment of ring index j: xw[128 w + i + 8 kh + 16 j + (0..7)] from copy rl
         const T* ah_base = As + (size_t)rl * G::CS + (128 * w + i - rl + 8 * kh);
@@ -186,26 +233,41 @@ __global__ void __launch_bounds__(64 * NW) k_fbank(const float* __restrict__ x, 
             }
         }
 
-        // D[row][f]: lane holds rows 8 (e/4) + 4 kh + (e%4) of each tile, column f = i
-        if (i < F) {
-            float* yc = y + ((int64_t)c * F + i) * ldy;
+        stage();  // every wave read Ws before the barrier above the products
+
+        // D[row][f]: lane holds rows 8 (e/4) + 4 kh + (e%4) of each tile, column f = i.  Each
+        // 32 x 32 block goes through the wave's own LDS region (row f, stride TS) so that one
+        // store instruction writes eight whole 128-byte runs of output rows.
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4; ++r) {
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int64_t t = t0 + 128 * w + 32 * r + 8 * g + 4 * kh;
-                    float o[4];
+            for (int g = 0; g < 4; ++g) {
+                float4 o;
+                o.x = accm[r][4 * g + 0] + accc[r][4 * g + 0] * S::LO_INV;
+                o.y = accm[r][4 * g + 1] + accc[r][4 * g + 1] * S::LO_INV;
+                o.z = accm[r][4 * g + 2] + accc[r][4 * g + 2] * S::LO_INV;
+                o.w = accm[r][4 * g + 3] + accc[r][4 * g + 3] * S::LO_INV;
+                *(float4*)(Tw + i * G::TS + 8 * g + 4 * kh) = o;
+            }
+            wave_lds_order();
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) o[j] = accm[r][4 * g + j] + accc[r][4 * g + j] * S::LO_INV;
+            for (int k = 0; k < 4; ++k) {
+                const int f = 8 * k + (lane >> 3), tc = 4 * (lane & 7);
+                const float4 o = *(const float4*)(Tw + f * G::TS + tc);
+                const int64_t t = t0 + 128 * w + 32 * r + tc;
+                if (f < F) {
+                    float* yr = y + ((int64_t)c * F + f) * ldy;
                     if (vec_store && t + 3 < Lout) {
-                        *(float4*)(yc + t) = make_float4(o[0], o[1], o[2], o[3]);
+                        *(float4*)(yr + t) = o;
                     } else {
+                        const float ov[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
-                            if (t + j < Lout) yc[t + j] = o[j];
+                            if (t + j < Lout) yr[t + j] = ov[j];
                     }
                 }
             }
+            wave_lds_order();  // the next block's writes follow this block's reads
         }
     }
 }
