@@ -57,24 +57,45 @@ __device__ BlockStats block_stats(const float* __restrict__ s, int64_t start, in
     __shared__ int red_f[NT / 64];
     double m = 0.0, q = 0.0;
     int nf = 0;
-    constexpr int CH = 8;  // loads in flight per thread
-    for (int base = 0; base < n; base += NT * CH) {
-        float xs[CH];
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const int i = base + threadIdx.x + NT * c;
-            xs[c] = (i < n) ? s[start + i] : 0.0f;
+    auto take = [&](float x) {
+        if (!isfinite(x)) {
+            nf = 1;
+        } else {
+            const double d = (double)x;
+            m = fmax(m, fabs(d));
+            q += d * d;
         }
+    };
+    if ((reinterpret_cast<uintptr_t>(s + start) & 7) == 0) {
+        // sample pairs, 16 float2 loads in flight per thread
+        constexpr int CH = 16;
+        const float2* s2 = reinterpret_cast<const float2*>(s + start);
+        const int n2 = n >> 1;
+        for (int base = 0; base < n2; base += NT * CH) {
+            float2 xs[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const float x = xs[c];
-            if (!isfinite(x)) {
-                nf = 1;
-            } else {
-                double d = (double)x;
-                m = fmax(m, fabs(d));
-                q += d * d;
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + threadIdx.x + NT * c;
+                xs[c] = (i < n2) ? s2[i] : make_float2(0.0f, 0.0f);
             }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                take(xs[c].x);
+                take(xs[c].y);
+            }
+        }
+        if ((n & 1) && threadIdx.x == 0) take(s[start + n - 1]);
+    } else {
+        constexpr int CH = 8;  // loads in flight per thread
+        for (int base = 0; base < n; base += NT * CH) {
+            float xs[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + threadIdx.x + NT * c;
+                xs[c] = (i < n) ? s[start + i] : 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) take(xs[c]);
         }
     }
     m = wave_max(m);
@@ -272,12 +293,16 @@ __device__ __forceinline__ unsigned long long argmax_key(float v, int64_t o) {
 }
 
 struct ArgmaxSink {
-    unsigned long long best = 0;
+    float bv = 0.0f;
+    int64_t bo = -1;  // -1: no finite output seen
+    // the order of argmax_key: larger value, then smaller index; -0 equals +0; NaN never enters
     __device__ __forceinline__ void consider(int64_t o, float v) {
-        if (v != v) return;
-        const unsigned long long k = argmax_key(v, o);
-        best = k > best ? k : best;
+        if (v == v && (bo < 0 || v > bv || (v == bv && o < bo))) {
+            bv = v;
+            bo = o;
+        }
     }
+    __device__ __forceinline__ unsigned long long key() const { return bo < 0 ? 0ull : argmax_key(bv, bo); }
     __device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double inv) {
         consider(it.o0 + (j - it.j_lo), (float)(inv * rt));  // eq. (16), as stored by StoreSink
     }
@@ -580,17 +605,39 @@ __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char
     }
     // ---- pack: z[n] = x[2n] + i x[2n+1]
     if constexpr (MODE == MD_FULL32) {
-        for (int n = threadIdx.x; n < MW; n += NT) {
-            const int i0 = 2 * n;
-            re[n] = (i0 < it.nvalid) ? a.s[it.start + i0] : 0.0f;
-            im[n] = (i0 + 1 < it.nvalid) ? a.s[it.start + i0 + 1] : 0.0f;
+        const float* sp = a.s + it.start;
+        if (2 * MW <= it.nvalid && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
+            const float2* s2 = reinterpret_cast<const float2*>(sp);
+            for (int n = threadIdx.x; n < MW; n += NT) {
+                const float2 p = s2[n];
+                re[n] = p.x;
+                im[n] = p.y;
+            }
+        } else {
+            for (int n = threadIdx.x; n < MW; n += NT) {
+                const int i0 = 2 * n;
+                re[n] = (i0 < it.nvalid) ? a.s[it.start + i0] : 0.0f;
+                im[n] = (i0 + 1 < it.nvalid) ? a.s[it.start + i0 + 1] : 0.0f;
+            }
         }
     } else if constexpr (MODE == MD_SYM) {
         const double eps = 1.0 / (2.0 * (double)c.R);
-        for (int n = threadIdx.x; n < MW; n += NT) {
-            const int i0 = 4 * n;
-            re[n] = sq_at(a, it, c.cs, i0) + eps * sq_at(a, it, c.cs, i0 + 1);
-            im[n] = sq_at(a, it, c.cs, i0 + 2) + eps * sq_at(a, it, c.cs, i0 + 3);
+        const float* sp = a.s + it.start;
+        if (4 * MW <= it.nvalid && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
+            // every sample of the packed words is valid: sample pairs, no per-sample bounds
+            const float2* s2 = reinterpret_cast<const float2*>(sp);
+            const double cs = c.cs;
+            for (int n = threadIdx.x; n < MW; n += NT) {
+                const float2 p0 = s2[2 * n], p1 = s2[2 * n + 1];
+                re[n] = rint(cs * (double)p0.x) + eps * rint(cs * (double)p0.y);
+                im[n] = rint(cs * (double)p1.x) + eps * rint(cs * (double)p1.y);
+            }
+        } else {
+            for (int n = threadIdx.x; n < MW; n += NT) {
+                const int i0 = 4 * n;
+                re[n] = sq_at(a, it, c.cs, i0) + eps * sq_at(a, it, c.cs, i0 + 1);
+                im[n] = sq_at(a, it, c.cs, i0 + 2) + eps * sq_at(a, it, c.cs, i0 + 3);
+            }
         }
     } else {
         constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
@@ -812,7 +859,7 @@ __global__ void __launch_bounds__(NT, (MODE == MD_FULL32 ? LOGW <= 14 : LOGW <= 
                 else
                     fft_item<MODE, MW>(a, it, c, lds, sk);
             }
-            const unsigned long long k = wave_umax64(sk.best);
+            const unsigned long long k = wave_umax64(sk.key());
             if ((threadIdx.x & 63) == 0 && k != 0) atomicMax(&keys[t], k);
             __syncthreads();
         }
