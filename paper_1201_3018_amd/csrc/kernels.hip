@@ -676,9 +676,29 @@ __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char
         return (m & 1) ? (double)im[m >> 1] : (double)re[m >> 1];
     };
     if constexpr (MODE == MD_FULL32) {
-        for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NT) sk.put32(a, it, j, (float)word(j));
+        // outputs 2u, 2u + 1 are re[u], im[u]
+        const int u_lo = it.j_lo >> 1, u_hi = (it.j_hi + 1) >> 1;
+        for (int u = u_lo + threadIdx.x; u < u_hi; u += NT) {
+            const float v0 = (float)re[u], v1 = (float)im[u];
+            if (2 * u >= it.j_lo) sk.put32(a, it, 2 * u, v0);
+            if (2 * u + 1 < it.j_hi) sk.put32(a, it, 2 * u + 1, v1);
+        }
     } else if constexpr (MODE == MD_SYM) {
-        sym_unpack_store(a, it, c, word, sk);
+        // words 2u, 2u + 1 are re[u], im[u] and give outputs 4u .. 4u + 3 (eq. 9 digits; the side
+        // digit of word 2u - 1 is taken from im[u - 1], word -1 being zero)
+        const double two_r = (double)(2 * c.R), R = (double)c.R, inv_two_r = 1.0 / two_r;
+        const int u_lo = it.j_lo >> 2, u_hi = (it.j_hi + 3) >> 2;
+        for (int u = u_lo + threadIdx.x; u < u_hi; u += NT) {
+            const SymDigits d0 = sym_split((double)re[u], two_r, inv_two_r, R);
+            const SymDigits d1 = sym_split((double)im[u], two_r, inv_two_r, R);
+            const double dprev = u >= 1 ? sym_split((double)im[u - 1], two_r, inv_two_r, R).De : 0.0;
+            const double v[4] = {d0.Dm + dprev, d0.B, d1.Dm + d0.De, d1.B};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int j = 4 * u + h;
+                if (j >= it.j_lo && j < it.j_hi) sk.put(a, it, j, v[h], c.inv);
+            }
+        }
     } else {
         constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
         const bool prefix = it.j_lo == 0;
