@@ -586,7 +586,8 @@ hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st) {
 // FFT core
 // ------------------------------------------------------------------------------------------
 // Complex points of the packed FFT for word length F: MW = F / 2.
-template <int MODE, int MW, typename Sink = StoreSink>
+// PACKED: the caller has already written the packed words into re / im (pack_regs).
+template <int MODE, int MW, bool PACKED = false, typename Sink = StoreSink>
 __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char* lds, Sink&& sk = Sink{}) {
     using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
     using T2 = typename tw_of<T>::type;
@@ -603,67 +604,69 @@ __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char
         tw = a.twd + F;
         H = a.spec[MODE];
     }
-    // ---- pack: z[n] = x[2n] + i x[2n+1]
-    if constexpr (MODE == MD_FULL32) {
-        const float* sp = a.s + it.start;
-        if (2 * MW <= it.nvalid && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
-            const float2* s2 = reinterpret_cast<const float2*>(sp);
-            for (int n = threadIdx.x; n < MW; n += NT) {
-                const float2 p = s2[n];
-                re[n] = p.x;
-                im[n] = p.y;
-            }
-        } else {
-            for (int n = threadIdx.x; n < MW; n += NT) {
-                const int i0 = 2 * n;
-                re[n] = (i0 < it.nvalid) ? a.s[it.start + i0] : 0.0f;
-                im[n] = (i0 + 1 < it.nvalid) ? a.s[it.start + i0 + 1] : 0.0f;
-            }
-        }
-    } else if constexpr (MODE == MD_SYM) {
-        const double eps = 1.0 / (2.0 * (double)c.R);
-        const float* sp = a.s + it.start;
-        if (4 * MW <= it.nvalid && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
-            // every sample of the packed words is valid: sample pairs, no per-sample bounds
-            const float2* s2 = reinterpret_cast<const float2*>(sp);
-            const double cs = c.cs;
-            for (int n = threadIdx.x; n < MW; n += NT) {
-                const float2 p0 = s2[2 * n], p1 = s2[2 * n + 1];
-                re[n] = rint(cs * (double)p0.x) + eps * rint(cs * (double)p0.y);
-                im[n] = rint(cs * (double)p1.x) + eps * rint(cs * (double)p1.y);
-            }
-        } else {
-            for (int n = threadIdx.x; n < MW; n += NT) {
-                const int i0 = 4 * n;
-                re[n] = sq_at(a, it, c.cs, i0) + eps * sq_at(a, it, c.cs, i0 + 1);
-                im[n] = sq_at(a, it, c.cs, i0 + 2) + eps * sq_at(a, it, c.cs, i0 + 3);
-            }
-        }
-    } else {
-        constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
-        const double eps = 1.0 / (2.0 * (double)c.R);
-        const bool prefix = it.j_lo == 0;
-        const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
-        const int base_off = it.j_lo - (N - 1);
-        const int lw = Tit + N - 1;
-        for (int n = threadIdx.x; n < MW; n += NT) {
-            double v[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int m = 2 * n + h;
-                double acc = 0.0;
-                if (m < lw) {
-                    double e = 1.0;
-#pragma unroll
-                    for (int q = 0; q < MM; ++q) {
-                        acc += e * sq_at(a, it, c.cs, base_off + q * Tit + m);
-                        e *= eps;
-                    }
+    if constexpr (!PACKED) {
+        // ---- pack: z[n] = x[2n] + i x[2n+1]
+        if constexpr (MODE == MD_FULL32) {
+            const float* sp = a.s + it.start;
+            if (2 * MW <= it.nvalid && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
+                const float2* s2 = reinterpret_cast<const float2*>(sp);
+                for (int n = threadIdx.x; n < MW; n += NT) {
+                    const float2 p = s2[n];
+                    re[n] = p.x;
+                    im[n] = p.y;
                 }
-                v[h] = acc;
+            } else {
+                for (int n = threadIdx.x; n < MW; n += NT) {
+                    const int i0 = 2 * n;
+                    re[n] = (i0 < it.nvalid) ? a.s[it.start + i0] : 0.0f;
+                    im[n] = (i0 + 1 < it.nvalid) ? a.s[it.start + i0 + 1] : 0.0f;
+                }
             }
-            re[n] = v[0];
-            im[n] = v[1];
+        } else if constexpr (MODE == MD_SYM) {
+            const double eps = 1.0 / (2.0 * (double)c.R);
+            const float* sp = a.s + it.start;
+            if (4 * MW <= it.nvalid && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
+                // every sample of the packed words is valid: sample pairs, no per-sample bounds
+                const float2* s2 = reinterpret_cast<const float2*>(sp);
+                const double cs = c.cs;
+                for (int n = threadIdx.x; n < MW; n += NT) {
+                    const float2 p0 = s2[2 * n], p1 = s2[2 * n + 1];
+                    re[n] = rint(cs * (double)p0.x) + eps * rint(cs * (double)p0.y);
+                    im[n] = rint(cs * (double)p1.x) + eps * rint(cs * (double)p1.y);
+                }
+            } else {
+                for (int n = threadIdx.x; n < MW; n += NT) {
+                    const int i0 = 4 * n;
+                    re[n] = sq_at(a, it, c.cs, i0) + eps * sq_at(a, it, c.cs, i0 + 1);
+                    im[n] = sq_at(a, it, c.cs, i0 + 2) + eps * sq_at(a, it, c.cs, i0 + 3);
+                }
+            }
+        } else {
+            constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
+            const double eps = 1.0 / (2.0 * (double)c.R);
+            const bool prefix = it.j_lo == 0;
+            const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+            const int base_off = it.j_lo - (N - 1);
+            const int lw = Tit + N - 1;
+            for (int n = threadIdx.x; n < MW; n += NT) {
+                double v[2];
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int m = 2 * n + h;
+                    double acc = 0.0;
+                    if (m < lw) {
+                        double e = 1.0;
+    #pragma unroll
+                        for (int q = 0; q < MM; ++q) {
+                            acc += e * sq_at(a, it, c.cs, base_off + q * Tit + m);
+                            e *= eps;
+                        }
+                    }
+                    v[h] = acc;
+                }
+                re[n] = v[0];
+                im[n] = v[1];
+            }
         }
     }
     __syncthreads();
@@ -830,6 +833,112 @@ hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st) {
 }
 
 
+// Fixed symmetric or FP32 items of the batched kernel read their window once: point n =
+// threadIdx.x + NT k holds samples SPP n .. SPP n + SPP - 1 of the window in registers (zero at
+// or past nwin); the block statistics are taken from them and the packed words are written from
+// them (block_stats + the packing of fft_item, with one read of the window instead of two).
+template <int MODE, int MW>
+struct WinRegs {
+    static constexpr int SPP = MODE == MD_SYM ? 4 : 2;  // samples per complex point
+    static constexpr int PPT = MW / NT;                 // points per thread (at most 64 samples)
+    static_assert(MW % NT == 0, "points must fill the threads");
+    float x[PPT][SPP];
+};
+
+template <int MODE, int MW>
+__device__ BlockStats window_regs(const RunArgs& a, const Item& it, WinRegs<MODE, MW>& wr) {
+    using R = WinRegs<MODE, MW>;
+    __shared__ double red_m[NT / 64], red_s[NT / 64];
+    __shared__ int red_f[NT / 64];
+    const float* sp = a.s + it.start;
+    if (R::SPP * MW <= it.nwin && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
+        const float2* s2 = reinterpret_cast<const float2*>(sp);
+#pragma unroll
+        for (int k = 0; k < R::PPT; ++k) {
+            const int n = threadIdx.x + NT * k;
+#pragma unroll
+            for (int h = 0; h < R::SPP / 2; ++h) {
+                const float2 v = s2[(R::SPP / 2) * n + h];
+                wr.x[k][2 * h] = v.x;
+                wr.x[k][2 * h + 1] = v.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < R::PPT; ++k) {
+            const int n = threadIdx.x + NT * k;
+#pragma unroll
+            for (int h = 0; h < R::SPP; ++h) {
+                const int i = R::SPP * n + h;
+                wr.x[k][h] = (i < it.nwin) ? sp[i] : 0.0f;
+            }
+        }
+    }
+    double m = 0.0, q = 0.0;
+    int nf = 0;
+#pragma unroll
+    for (int k = 0; k < R::PPT; ++k) {
+#pragma unroll
+        for (int h = 0; h < R::SPP; ++h) {
+            const float v = wr.x[k][h];
+            if (!isfinite(v)) {
+                nf = 1;
+            } else {
+                const double d = (double)v;
+                m = fmax(m, fabs(d));
+                q += d * d;
+            }
+        }
+    }
+    m = wave_max(m);
+    q = wave_sum(q);
+    nf = wave_or(nf);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red_m[wv] = m;
+        red_s[wv] = q;
+        red_f[wv] = nf;
+    }
+    __syncthreads();
+    BlockStats r;
+    r.smax = red_m[0];
+    r.sumsq = red_s[0];
+    r.nonfinite = red_f[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) {
+        r.smax = fmax(r.smax, red_m[i]);
+        r.sumsq += red_s[i];
+        r.nonfinite |= red_f[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// The packed words of fft_item from the registers: samples at or past nvalid are zero.
+template <int MODE, int MW>
+__device__ void pack_regs(const Item& it, const Choice& c, const WinRegs<MODE, MW>& wr, char* lds) {
+    using R = WinRegs<MODE, MW>;
+    using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+    T* re = (T*)lds;
+    T* im = re + MW;
+    const bool full = R::SPP * MW <= it.nvalid;
+#pragma unroll
+    for (int k = 0; k < R::PPT; ++k) {
+        const int n = threadIdx.x + NT * k;
+        float v[R::SPP];
+#pragma unroll
+        for (int h = 0; h < R::SPP; ++h) v[h] = (full || R::SPP * n + h < it.nvalid) ? wr.x[k][h] : 0.0f;
+        if constexpr (MODE == MD_FULL32) {
+            re[n] = v[0];
+            im[n] = v[1];
+        } else {
+            const double eps = 1.0 / (2.0 * (double)c.R), cs = c.cs;
+            re[n] = rint(cs * (double)v[0]) + eps * rint(cs * (double)v[1]);
+            im[n] = rint(cs * (double)v[2]) + eps * rint(cs * (double)v[3]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Batched cross-correlation matching: one persistent launch over a work list of (pair, block)
 // items.  Each workgroup takes `chunk` consecutive items at a time from a global counter, runs
@@ -871,13 +980,27 @@ __global__ void __launch_bounds__(NT, (MODE == MD_FULL32 ? LOGW <= 14 : LOGW <= 
             const RunArgs& a = targs[t];
             ArgmaxSink sk;
             const Item it = make_item(a, w, true);
-            const BlockStats st = block_stats(a.s, it.start, it.nwin);
-            const Choice c = choose(a, st);
-            if (!(c.flags & APX_FLAG_NONFINITE) && it.j_hi > it.j_lo) {
-                if ((c.flags & APX_FLAG_ZERO) && MODE != MD_FULL32)
-                    sk.consider(it.o0, 0.0f);  // all outputs of the block are zero
-                else
-                    fft_item<MODE, MW>(a, it, c, lds, sk);
+            if constexpr ((MODE == MD_SYM || MODE == MD_FULL32) && WinRegs<MODE, MW>::PPT * WinRegs<MODE, MW>::SPP <= 64) {
+                WinRegs<MODE, MW> wr;
+                const BlockStats st = window_regs<MODE, MW>(a, it, wr);
+                const Choice c = choose(a, st);
+                if (!(c.flags & APX_FLAG_NONFINITE) && it.j_hi > it.j_lo) {
+                    if ((c.flags & APX_FLAG_ZERO) && MODE != MD_FULL32) {
+                        sk.consider(it.o0, 0.0f);  // all outputs of the block are zero
+                    } else {
+                        pack_regs<MODE, MW>(it, c, wr, lds);
+                        fft_item<MODE, MW, true>(a, it, c, lds, sk);
+                    }
+                }
+            } else {
+                const BlockStats st = block_stats(a.s, it.start, it.nwin);
+                const Choice c = choose(a, st);
+                if (!(c.flags & APX_FLAG_NONFINITE) && it.j_hi > it.j_lo) {
+                    if ((c.flags & APX_FLAG_ZERO) && MODE != MD_FULL32)
+                        sk.consider(it.o0, 0.0f);  // all outputs of the block are zero
+                    else
+                        fft_item<MODE, MW>(a, it, c, lds, sk);
+                }
             }
             const unsigned long long k = wave_umax64(sk.key());
             if ((threadIdx.x & 63) == 0 && k != 0) atomicMax(&keys[t], k);
