@@ -426,7 +426,8 @@ __device__ __forceinline__ void wsym_split(double rb, double two_r, double inv_t
 __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem& it, float* win) {
     double m = 0.0, q = 0.0;
     int nf = 0;
-    const float* p = a.s + it.start;  // start is even: 8-byte aligned
+    const float* p = a.s + it.start;  // start is even: pairs are 8-byte aligned if s_in is
+    const bool al = (reinterpret_cast<uintptr_t>(p) & 7) == 0;
     constexpr int CH = 16;             // float2 loads in flight per lane
     // statistics of one sample pair (non-finite samples count as zero and flag the block)
     auto take = [&](float x0, float x1) {
@@ -441,7 +442,7 @@ __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem
         // wave-uniform: the whole chunk lies inside the signal, the valid part and the window, so
         // it needs no per-sample bounds (every block but the last)
         const int end = base + 128 * CH;
-        if (end <= it.nwin && end <= it.nvalid && end <= a.W_block) {
+        if (al && end <= it.nwin && end <= it.nvalid && end <= a.W_block) {
 #pragma unroll
             for (int c = 0; c < CH; ++c) f[c] = *reinterpret_cast<const float2*>(p + base + 2 * threadIdx.x + 128 * c);
 #pragma unroll
@@ -457,8 +458,12 @@ __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * threadIdx.x + 128 * c;
             f[c] = make_float2(0.0f, 0.0f);
-            if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
-            else if (i < it.nwin) f[c].x = p[i];
+            if (al && i + 1 < it.nwin) {
+                f[c] = *reinterpret_cast<const float2*>(p + i);
+            } else {
+                if (i < it.nwin) f[c].x = p[i];
+                if (i + 1 < it.nwin) f[c].y = p[i + 1];
+            }
         }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -762,6 +767,7 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
     double m = 0.0, q = 0.0;
     int nf = 0;
     const float* p = a.s + it.start;
+    const bool al = (reinterpret_cast<uintptr_t>(p) & 7) == 0;
     constexpr int CH = 8;
     for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
         float2 f[CH];
@@ -769,8 +775,12 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * ((int)threadIdx.x + NTH * c);
             f[c] = make_float2(0.0f, 0.0f);
-            if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
-            else if (i < it.nwin) f[c].x = p[i];
+            if (al && i + 1 < it.nwin) {
+                f[c] = *reinterpret_cast<const float2*>(p + i);
+            } else {
+                if (i < it.nwin) f[c].x = p[i];
+                if (i + 1 < it.nwin) f[c].y = p[i + 1];
+            }
         }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
