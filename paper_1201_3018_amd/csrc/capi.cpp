@@ -260,10 +260,15 @@ apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
     return APX_OK;
 }
 
+// The window loaders read sample pairs: signal pointers must be 8-byte aligned (blocks start at
+// even sample offsets).
+static bool aligned8(const float* p) { return (reinterpret_cast<uintptr_t>(p) & 7) == 0; }
+
 apx_status run_impl(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, double* fields,
                     apx_block_info* info, hipStream_t st) {
     if (!ctx || !k) return fail(APX_E_INVALID, "null context or kernel");
     if (!s || !out) return fail(APX_E_INVALID, "null input or output pointer");
+    if (!aligned8(s)) return fail(APX_E_INVALID, "s_in must be 8-byte aligned");
     if (L < k->N) return fail(APX_E_INVALID, "input length L = %lld shorter than the kernel N = %d", (long long)L, k->N);
     int64_t P = 0;
     apx_status r = geometry(L, k->N, k->W_block, nullptr, nullptr, &P);
@@ -637,6 +642,7 @@ apx_status apx_debug_fields(apx_ctx ctx, apx_kernel k, const float* s, int64_t L
 apx_status apx_calibrate(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, int32_t block, int32_t Q, void* stream,
                          double* offset_db) {
     if (!ctx || !k || !s) return fail(APX_E_INVALID, "null argument");
+    if (!aligned8(s)) return fail(APX_E_INVALID, "s_in must be 8-byte aligned");
     if (Q < 1) return fail(APX_E_INVALID, "Q must be >= 1");
     int64_t P = 0;
     apx_status r = geometry(L, k->N, k->W_block, nullptr, nullptr, &P);
@@ -700,6 +706,7 @@ apx_status apx_fit_marginal(apx_ctx ctx, const float* x, int64_t n, int32_t mode
 apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info,
                         double snr_min_db, int32_t calib_block, void* workspace, void* stream) {
     if (!ctx || !k || !s || !out || !workspace) return fail(APX_E_INVALID, "null argument");
+    if (!aligned8(s)) return fail(APX_E_INVALID, "s_in must be 8-byte aligned");
     if (k->params.mode != APX_AUTO_SNR) return fail(APX_E_INVALID, "apx_run_auto needs an APX_AUTO_SNR kernel");
     if (!isfinite(snr_min_db)) return fail(APX_E_INVALID, "snr_min_db must be finite");
     if (L < k->N) return fail(APX_E_INVALID, "input length L = %lld shorter than the kernel N = %d", (long long)L, k->N);
@@ -949,6 +956,7 @@ apx_status apx_batch_create(apx_ctx ctx, int32_t n, const float* const* refs, co
         return fail(APX_E_INVALID, "log2 FFT length %d outside [%d, %d]", logW, BATCH_LOGW_MIN, BATCH_LOGW_MAX);
     for (int i = 0; i < n; ++i) {
         if (!refs[i] || !tmpl[i]) return fail(APX_E_INVALID, "pair %d: null pointer", i);
+        if (!aligned8(refs[i])) return fail(APX_E_INVALID, "pair %d: reference must be 8-byte aligned", i);
         if (N[i] < 1 || L[i] < N[i]) return fail(APX_E_INVALID, "pair %d: need 1 <= N <= L", i);
         if (L[i] + N[i] - 1 > (int64_t)0xFFFFFFFEll) return fail(APX_E_UNSUPPORTED, "pair %d: too long", i);
     }

@@ -426,8 +426,7 @@ __device__ __forceinline__ void wsym_split(double rb, double two_r, double inv_t
 __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem& it, float* win) {
     double m = 0.0, q = 0.0;
     int nf = 0;
-    const float* p = a.s + it.start;  // start is even: pairs are 8-byte aligned if s_in is
-    const bool al = (reinterpret_cast<uintptr_t>(p) & 7) == 0;
+    const float* p = a.s + it.start;  // start is even and s_in 8-byte aligned (checked on the host)
     constexpr int CH = 16;             // float2 loads in flight per lane
     // statistics of one sample pair (non-finite samples count as zero and flag the block)
     auto take = [&](float x0, float x1) {
@@ -442,7 +441,7 @@ __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem
         // wave-uniform: the whole chunk lies inside the signal, the valid part and the window, so
         // it needs no per-sample bounds (every block but the last)
         const int end = base + 128 * CH;
-        if (al && end <= it.nwin && end <= it.nvalid && end <= a.W_block) {
+        if (end <= it.nwin && end <= it.nvalid && end <= a.W_block) {
 #pragma unroll
             for (int c = 0; c < CH; ++c) f[c] = *reinterpret_cast<const float2*>(p + base + 2 * threadIdx.x + 128 * c);
 #pragma unroll
@@ -458,12 +457,8 @@ __device__ __forceinline__ WStats wave_load_window(const RunArgs& a, const WItem
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * threadIdx.x + 128 * c;
             f[c] = make_float2(0.0f, 0.0f);
-            if (al && i + 1 < it.nwin) {
-                f[c] = *reinterpret_cast<const float2*>(p + i);
-            } else {
-                if (i < it.nwin) f[c].x = p[i];
-                if (i + 1 < it.nwin) f[c].y = p[i + 1];
-            }
+            if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
+            else if (i < it.nwin) f[c].x = p[i];
         }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -533,17 +528,20 @@ __device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, con
                 v[r].x = sqd(4 * n) + eps * sqd(4 * n + 1);
                 v[r].y = sqd(4 * n + 2) + eps * sqd(4 * n + 3);
             } else {
-                double w2[2];
+                double w2[2] = {0.0, 0.0};
+                // words 128 r .. 128 r + 127 of this step: none is packed past lw (wave-uniform)
+                if (128 * r < lw) {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int m = 2 * n + h;
-                    double acc = 0.0, e = 1.0;
+                    for (int h = 0; h < 2; ++h) {
+                        const int m = 2 * n + h;
+                        double acc = 0.0, e = 1.0;
 #pragma unroll
-                    for (int q = 0; q < MM; ++q) {
-                        acc += e * sqd(base_off + q * Tit + m);
-                        e *= eps;
+                        for (int q = 0; q < MM; ++q) {
+                            acc += e * sqd(base_off + q * Tit + m);
+                            e *= eps;
+                        }
+                        w2[h] = (m < lw) ? acc : 0.0;
                     }
-                    w2[h] = (m < lw) ? acc : 0.0;
                 }
                 v[r].x = w2[0];
                 v[r].y = w2[1];
@@ -605,6 +603,8 @@ __device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, con
         // word m, digit q -> staging index q Tit + m (= local output - j_lo + N - 1)
 #pragma unroll
         for (int t = 0; t < E; ++t) {
+            // words 128 t .. 128 t + 127 of this step: none is kept before N - 1 or from lw on
+            if (128 * t + 127 < N - 1 || 128 * t >= lw) continue;
             const int n = l + 64 * t;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -767,7 +767,6 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
     double m = 0.0, q = 0.0;
     int nf = 0;
     const float* p = a.s + it.start;
-    const bool al = (reinterpret_cast<uintptr_t>(p) & 7) == 0;
     constexpr int CH = 8;
     for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
         float2 f[CH];
@@ -775,12 +774,8 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * ((int)threadIdx.x + NTH * c);
             f[c] = make_float2(0.0f, 0.0f);
-            if (al && i + 1 < it.nwin) {
-                f[c] = *reinterpret_cast<const float2*>(p + i);
-            } else {
-                if (i < it.nwin) f[c].x = p[i];
-                if (i + 1 < it.nwin) f[c].y = p[i + 1];
-            }
+            if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
+            else if (i < it.nwin) f[c].x = p[i];
         }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {

@@ -1523,13 +1523,12 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a, const i8x16* _
     char* lds_i8 = lds_all + (size_t)(threadIdx.x >> 6) * region;
     const Item it = make_item(a, blk, false);
     float* win = reinterpret_cast<float*>(lds_i8 + 2 * plane_len);
-    // window into LDS with its statistics; start is even (float2 loads where s_in is 8-byte aligned)
+    // window into LDS with its statistics; start is even and s_in 8-byte aligned (float2 loads)
     BlockStats st;
     {
         double m = 0.0, q = 0.0;
         int nf = 0;
         const float* p = a.s + it.start;
-        const bool al = (reinterpret_cast<uintptr_t>(p) & 7) == 0;
         constexpr int CH = 16;
         for (int base = 0; base < a.W_block; base += 128 * CH) {
             float2 f[CH];
@@ -1537,12 +1536,8 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a, const i8x16* _
             for (int c = 0; c < CH; ++c) {
                 const int i = base + 2 * lane + 128 * c;
                 f[c] = make_float2(0.0f, 0.0f);
-                if (al && i + 1 < it.nwin) {
-                    f[c] = *reinterpret_cast<const float2*>(p + i);
-                } else {
-                    if (i < it.nwin) f[c].x = p[i];
-                    if (i + 1 < it.nwin) f[c].y = p[i + 1];
-                }
+                if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
+                else if (i < it.nwin) f[c].x = p[i];
             }
 #pragma unroll
             for (int c = 0; c < CH; ++c) {

@@ -369,6 +369,7 @@ double apx_server_now(void) { return now_s(); }
 apx_status apx_server_submit(apx_server srv, const apx_request* r, uint64_t* ticket) {
     if (!srv || !r) return APX_E_INVALID;
     if (!r->s || !r->k || !r->r_out || r->N < 1 || r->L < r->N) return APX_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(r->s) & 7) return APX_E_INVALID;  // s_in must be 8-byte aligned
     if (r->op != APX_CONV && r->op != APX_XCORR) return APX_E_INVALID;
     if (r->mode < APX_FULL_FP32 || r->mode > APX_FULL_FP64) return APX_E_INVALID;
     if (r->mode == APX_AUTO_SNR && !isfinite(r->snr_min_db)) return APX_E_INVALID;

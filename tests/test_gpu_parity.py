@@ -159,30 +159,35 @@ def test_wave_window_chunk_edges(ctx, mode, tail):
     _check_packed(s, k, Wb, mode, S, got, fields, info)
 
 
-@pytest.mark.parametrize("core,variant", [("td", "block"), ("fft", "block"), ("fft", "wave"), ("fft", "group"),
-                                          ("int8", "block")])
-def test_unaligned_input(ctx, core, variant):
-    """s_in 4 bytes past an 8-byte boundary (a view one float into a buffer): the window loaders
-    fall back to single-sample loads.  Fixed asymmetric M=2 outputs equal those of an aligned
-    copy bit for bit; on the one-wave core the per-block choice and its outputs too."""
+def test_unaligned_input_rejected(ctx):
+    """s_in 4 bytes past an 8-byte boundary (a view one float into a buffer) is rejected on the
+    host with APX_E_INVALID before any launch, on every entry point that takes a signal; the
+    same data in its own buffer runs."""
     L, N, Wb = 40000, 1024, 4096
     s, k = synth.ar1(L, 93), synth.hann_lowpass(N)
     buf = torch.zeros(L + 1, dtype=torch.float32, device=DEV)
     buf[1:] = _dev(s)
     mis = buf[1:]
     assert mis.data_ptr() % 8 == 4
-    _say("case: unaligned input", core, variant)
     S = O.max_q(O.ASYM2, N + 1)
-    modes = [(apx.APX_ASYM2, dict(Sq=S, Kq=S))]
-    if variant == "wave":
-        modes.append((apx.APX_AUTO_SNR, dict(snr_min_db=40.0, calib_db=16.0)))
-    for mode, kw in modes:
-        kern = apx.Kernel(ctx, _dev(k), Wb, mode=mode, core=CORES[core], fft_variant=VARIANTS[variant], **kw)
-        a = kern.run(_dev(s))
-        b = kern.run(mis)
-        torch.cuda.synchronize()
+    for core in ("td", "fft", "int8"):
+        kern = apx.Kernel(ctx, _dev(k), Wb, mode=apx.APX_ASYM2, core=CORES[core], Sq=S, Kq=S)
+        with pytest.raises(apx.ApxError) as e:
+            kern.run(mis)
+        assert e.value.status == apx.APX_E_INVALID
+        kern.run(_dev(s))
         kern.close()
-        assert torch.equal(a, b), (core, variant, mode)
+    kauto = apx.Kernel(ctx, _dev(k), Wb, mode=apx.APX_AUTO_SNR, snr_min_db=40.0)
+    with pytest.raises(apx.ApxError) as e:
+        apx.apx_calibrate(ctx.h, kauto.h, mis, block=1, Q=8)
+    assert e.value.status == apx.APX_E_INVALID
+    ws = torch.empty(apx.apx_workspace_bytes(), dtype=torch.uint8, device=DEV)
+    out = torch.empty(L + N - 1, dtype=torch.float32, device=DEV)
+    with pytest.raises(apx.ApxError) as e:
+        apx.apx_run_auto(ctx.h, kauto.h, mis, out, 40.0, 1, ws, None)
+    assert e.value.status == apx.APX_E_INVALID
+    torch.cuda.synchronize()
+    kauto.close()
 
 
 @pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
