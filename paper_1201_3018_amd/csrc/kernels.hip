@@ -57,45 +57,24 @@ __device__ BlockStats block_stats(const float* __restrict__ s, int64_t start, in
     __shared__ int red_f[NT / 64];
     double m = 0.0, q = 0.0;
     int nf = 0;
-    auto take = [&](float x) {
-        if (!isfinite(x)) {
-            nf = 1;
-        } else {
-            const double d = (double)x;
-            m = fmax(m, fabs(d));
-            q += d * d;
+    constexpr int CH = 8;  // loads in flight per thread
+    for (int base = 0; base < n; base += NT * CH) {
+        float xs[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = base + threadIdx.x + NT * c;
+            xs[c] = (i < n) ? s[start + i] : 0.0f;
         }
-    };
-    if ((reinterpret_cast<uintptr_t>(s + start) & 7) == 0) {
-        // sample pairs, 16 float2 loads in flight per thread
-        constexpr int CH = 16;
-        const float2* s2 = reinterpret_cast<const float2*>(s + start);
-        const int n2 = n >> 1;
-        for (int base = 0; base < n2; base += NT * CH) {
-            float2 xs[CH];
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int i = base + threadIdx.x + NT * c;
-                xs[c] = (i < n2) ? s2[i] : make_float2(0.0f, 0.0f);
+        for (int c = 0; c < CH; ++c) {
+            const float x = xs[c];
+            if (!isfinite(x)) {
+                nf = 1;
+            } else {
+                double d = (double)x;
+                m = fmax(m, fabs(d));
+                q += d * d;
             }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                take(xs[c].x);
-                take(xs[c].y);
-            }
-        }
-        if ((n & 1) && threadIdx.x == 0) take(s[start + n - 1]);
-    } else {
-        constexpr int CH = 8;  // loads in flight per thread
-        for (int base = 0; base < n; base += NT * CH) {
-            float xs[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int i = base + threadIdx.x + NT * c;
-                xs[c] = (i < n) ? s[start + i] : 0.0f;
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) take(xs[c]);
         }
     }
     m = wave_max(m);
