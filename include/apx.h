@@ -12,10 +12,10 @@
  * Conventions for every call below.
  *   - Array pointers are DEVICE pointers unless the comment says "host".  The caller owns every
  *     buffer it passes; the library keeps no caller pointer after the enqueued work completes.
- *   - Signal inputs (s_in, and the batch's references and a served request's s) must be 8-byte
- *     aligned: the window loaders read sample pairs.  A misaligned one gives APX_E_INVALID before
- *     anything is launched.  (Every device allocation is; a view that starts an odd number of
- *     floats into one is not.)
+ *   - Signal inputs s_in (and a served request's s) must be 8-byte aligned: the window loaders
+ *     read sample pairs.  A misaligned one gives APX_E_INVALID before anything is launched.
+ *     (Every device allocation is; a view that starts an odd number of floats into one is not.)
+ *     The batch's references may start anywhere.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is enqueued on it
  *     and the call returns without waiting, unless the comment says the call synchronizes.
  *   - Return codes only; nothing throws across this boundary.  Shape and bound errors are found
