@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(64 * NW) k_fbank(const float* __restrict__ x, 
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 31, kh = lane >> 5, rl = i & 7;
-    const bool vec_store = (ldy % 4) == 0;
+    const bool vec_store = (ldy % 4) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0;  // 16-byte rows
 
     // The raw window of the next tile is loaded into registers (RPT samples per thread, coalesced)
     // while the current tile's products run: one workgroup fills a CU's LDS, so no other

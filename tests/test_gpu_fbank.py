@@ -98,6 +98,14 @@ def test_fbank_strides_and_errors(ctx):
     yc = y.view(C, F, ldy).cpu().numpy()
     assert np.all(yc[:, :, L + N - 1:] == 7.0)                # padding untouched
     _check_bank(x[:, :L], h, yc, apx.APX_FB_F16X3, L)
+    # an output buffer 4 bytes past a 16-byte boundary (row stride a multiple of 4): scalar stores
+    ldy4 = (L + N - 1 + 3) // 4 * 4
+    buf = torch.full((C * F * ldy4 + 1,), 7.0, device=DEV)
+    y4 = buf[1:].view(C * F, ldy4)
+    assert y4.data_ptr() % 16 == 4
+    fb.run(torch.from_numpy(x).to(DEV), y=y4, L=L)
+    torch.cuda.synchronize()
+    assert np.array_equal(y4.view(C, F, ldy4).cpu().numpy()[:, :, :L + N - 1], yc[:, :, :L + N - 1])
     with pytest.raises(apx.ApxError):
         apx.FilterBank(ctx, torch.zeros(33, 10, device=DEV))
     with pytest.raises(apx.ApxError) as e:
