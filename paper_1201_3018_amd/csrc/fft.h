@@ -190,11 +190,76 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 // Full complex FFT of M points in LDS.  Caller synchronizes before (data written by others);
 // the last pass ends with a barrier.  Forward: exp(-2 pi i ...); inverse: unnormalized.
+// LDS bytes that fft_lds<T, M> needs from re on: the two rows of M values, or for FP64 at
+// M = 16 NT the padded complex layout of the register-resident transform (group_fft16).
+__host__ __device__ constexpr size_t fft_lds_bytes(bool fp64, int M) {
+    const size_t rows = 2 * (size_t)M * (fp64 ? 8 : 4);
+    const size_t padded = (fp64 && M == 16 * NT) ? (size_t)(M + M / 16) * 16 : 0;
+    return rows > padded ? rows : padded;
+}
+
+// Complex FFT of M = 16 NT points in FP64: three radix-16 passes with 16 points per thread in
+// registers and two exchanges through LDS in a padded layout (point i at i + floor(i / 16), which
+// spreads a pass's strided accesses over the banks), where the Stockham form takes four passes
+// through LDS and twice the barriers.  In and out: natural order in re[], im[]; the padded layout
+// takes fft_lds_bytes(true, M) from re on.  tw: W_F^t, F = 2M.
+template <bool INV>
+__device__ __forceinline__ void group_fft16(double* re, double* im, const double2* tw) {
+    constexpr int E = 16, S = E + 1;
+    cx<double>* cl = reinterpret_cast<cx<double>*>(re);
+    const int t = threadIdx.x;
+    cx<double> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = {re[t + NT * r], im[t + NT * r]};
+    __syncthreads();  // every natural-order read is done before the padded layout overwrites it
+    // pass A: DFT-16 over stride NT; point t E + r goes to t S + r
+    dft16<double, INV>(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) cl[t * S + r] = v[r];
+    __syncthreads();
+    // pass B: radix 16 over the sub-transforms of size E, twiddles W_(16E)^(r k) = W_F^(32 r k)
+    {
+        const int q = t / E, k = t - q * E;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = cl[t + q + 16 * S * r];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+            const double2 w = tw[32 * r * k];
+            v[r] = cmul(v[r], cx<double>{w.x, INV ? -w.y : w.y});
+        }
+        dft16<double, INV>(v);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cl[16 * S * q + k + S * r] = v[r];
+        __syncthreads();
+    }
+    // pass C: radix 16 over the sub-transforms of size 16 E, twiddles W_M^(r t) = W_F^(2 r t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cl[t + t / E + 16 * S * r];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) {
+        const double2 w = tw[2 * r * t];
+        v[r] = cmul(v[r], cx<double>{w.x, INV ? -w.y : w.y});
+    }
+    dft16<double, INV>(v);
+    __syncthreads();  // every padded read is done before the natural-order writes
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        re[t + NT * r] = v[r].x;
+        im[t + NT * r] = v[r].y;
+    }
+    __syncthreads();
+}
+
 // FP32: radix-16 passes (fewer passes and barriers; measured 12% faster on the batched FP32
-// path).  FP64: radix-8 passes (radix 16 holds twice the registers per point and measured 5-6%
-// slower).
+// path).  FP64: radix-8 passes (radix-16 Stockham passes hold twice the registers per point and
+// measured 5-6% slower), except at M = 16 NT, which runs group_fft16.
 template <typename T, int M, bool INV>
 __device__ __forceinline__ void fft_lds(T* re, T* im, const typename tw_of<T>::type* tw) {
+    if constexpr (std::is_same<T, double>::value && M == 16 * NT) {
+        group_fft16<INV>(re, im, tw);
+        return;
+    }
     constexpr int L2 = ilog2(M);
     constexpr int RB = std::is_same<T, float>::value ? 4 : 3;  // log2 of the main radix
     constexpr int NP = L2 / RB;

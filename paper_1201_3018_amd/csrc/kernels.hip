@@ -760,12 +760,12 @@ bool fft1_supported(int mode, int logmw) { return fft1_fn(mode, logmw) != nullpt
 hipError_t fft1_set_lds(int mode, int logmw) {
     const void* f = fft1_fn(mode, logmw);
     if (!f) return hipErrorInvalidValue;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(((size_t)16) << logmw));
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds_bytes(true, 1 << logmw));
 }
 
 hipError_t launch_fft1(const RunArgs& a, int mode, int logmw, hipStream_t st) {
     dim3 g((unsigned)(a.P + 1));
-    const size_t lds = ((size_t)16) << logmw;
+    const size_t lds = fft_lds_bytes(true, 1 << logmw);
 #define APX_GO(M_, L_)                                                          \
     if (mode == M_ && logmw == L_) {                                            \
         hipLaunchKernelGGL((k_fft1<M_, L_>), g, dim3(NT), lds, st, a);           \
@@ -778,7 +778,11 @@ hipError_t launch_fft1(const RunArgs& a, int mode, int logmw, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
-static size_t fft_lds(int logF) { return ((size_t)1 << logF) * sizeof(double); }
+// the FP64 rows of the asymmetric / FP32 slot (F/2 points) or the symmetric slot (F/4 points)
+static size_t fft_lds(int logF) {
+    const size_t a = fft_lds_bytes(true, 1 << (logF - 1)), b = fft_lds_bytes(true, 1 << (logF - 2));
+    return a > b ? a : b;
+}
 
 // Raises the LDS limit of the kernel for logF (once, at kernel preparation: launches may be
 // captured into a graph).
@@ -1014,8 +1018,7 @@ __global__ void __launch_bounds__(NT) k_batch_final(const unsigned long long* __
 }
 
 size_t batch_lds_bytes(int mode, int logW) {
-    const size_t esz = mode == MD_FULL32 ? sizeof(float) : sizeof(double);
-    return ((size_t)1 << logW) * esz;  // 2^(LOGW-1) complex points
+    return fft_lds_bytes(mode != MD_FULL32, 1 << (logW - 1));  // 2^(LOGW-1) complex points
 }
 
 namespace {
@@ -1165,7 +1168,7 @@ template <typename T, int MW>
 hipError_t spectrum_one(const T* taps, int32_t ntaps, const typename tw_of<T>::type* tw,
                         typename tw_of<T>::type* spec, hipStream_t st) {
     auto kern = k_spectrum<T, MW>;
-    const size_t lds = 2 * (size_t)MW * sizeof(T);
+    const size_t lds = fft_lds_bytes(std::is_same<T, double>::value, MW);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(1), dim3(NT), lds, st, taps, ntaps, tw, spec);
