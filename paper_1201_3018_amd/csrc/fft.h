@@ -191,73 +191,116 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 // Full complex FFT of M points in LDS.  Caller synchronizes before (data written by others);
 // the last pass ends with a barrier.  Forward: exp(-2 pi i ...); inverse: unnormalized.
 // LDS bytes that fft_lds<T, M> needs from re on: the two rows of M values, or for FP64 at
-// M = 16 NT the padded complex layout of the register-resident transform (group_fft16).
+// M = 16 NT and 32 NT the padded complex layout of the register-resident transform (group_fft).
 __host__ __device__ constexpr size_t fft_lds_bytes(bool fp64, int M) {
     const size_t rows = 2 * (size_t)M * (fp64 ? 8 : 4);
-    const size_t padded = (fp64 && M == 16 * NT) ? (size_t)(M + M / 16) * 16 : 0;
+    const size_t padded = (fp64 && (M == 16 * NT || M == 32 * NT)) ? (size_t)(M + NT) * 16 : 0;
     return rows > padded ? rows : padded;
 }
 
-// Complex FFT of M = 16 NT points in FP64: three radix-16 passes with 16 points per thread in
-// registers and two exchanges through LDS in a padded layout (point i at i + floor(i / 16), which
-// spreads a pass's strided accesses over the banks), where the Stockham form takes four passes
-// through LDS and twice the barriers.  In and out: natural order in re[], im[]; the padded layout
-// takes fft_lds_bytes(true, M) from re on.  tw: W_F^t, F = 2M.
-template <bool INV>
-__device__ __forceinline__ void group_fft16(double* re, double* im, const double2* tw) {
-    constexpr int E = 16, S = E + 1;
+// DFT of E = 16 or 32 points in registers; the 32-point one is two 16-point DFTs (even and odd
+// points) joined by W_32^k, read from the W_F table (F = 64 NT: W_32^k = tw[2 NT k]).
+template <int E, bool INV>
+__device__ __forceinline__ void dft_group(cx<double>* v, const double2* tw) {
+    if constexpr (E == 16) {
+        dft16<double, INV>(v);
+    } else {
+        static_assert(E == 32, "16 or 32 points per thread");
+        cx<double> ev[16], od[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            ev[i] = v[2 * i];
+            od[i] = v[2 * i + 1];
+        }
+        dft16<double, INV>(ev);
+        dft16<double, INV>(od);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double2 w = tw[2 * NT * k];
+            const cx<double> tk = cmul(od[k], cx<double>{w.x, INV ? -w.y : w.y});
+            v[k] = ev[k] + tk;
+            v[k + 16] = ev[k] - tk;
+        }
+    }
+}
+
+// Complex FFT of M = E NT points in FP64 (E = 16 or 32 per thread): a DFT-E in registers, then
+// two radix-16 passes (E / 16 butterflies per thread), with two exchanges through LDS in a padded
+// layout (point i at i + floor(i / E), which spreads a pass's strided accesses over the banks),
+// where the Stockham form takes five passes through LDS and twice the barriers.  In and out:
+// natural order in re[], im[]; the padded layout takes fft_lds_bytes(true, M) from re on.
+// tw: W_F^t, F = 2M.
+template <int E, bool INV>
+__device__ __forceinline__ void group_fft(double* re, double* im, const double2* tw) {
+    constexpr int M = E * NT, S = E + 1, NB = E / 16, H = M / 16;
     cx<double>* cl = reinterpret_cast<cx<double>*>(re);
     const int t = threadIdx.x;
-    cx<double> v[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = {re[t + NT * r], im[t + NT * r]};
-    __syncthreads();  // every natural-order read is done before the padded layout overwrites it
-    // pass A: DFT-16 over stride NT; point t E + r goes to t S + r
-    dft16<double, INV>(v);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) cl[t * S + r] = v[r];
-    __syncthreads();
-    // pass B: radix 16 over the sub-transforms of size E, twiddles W_(16E)^(r k) = W_F^(32 r k)
     {
-        const int q = t / E, k = t - q * E;
+        cx<double> v[E];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = cl[t + q + 16 * S * r];
+        for (int r = 0; r < E; ++r) v[r] = {re[t + NT * r], im[t + NT * r]};
+        __syncthreads();  // every natural-order read is done before the padded layout overwrites it
+        // first pass: DFT-E over stride NT; point t E + r goes to t S + r
+        dft_group<E, INV>(v, tw);
+#pragma unroll
+        for (int r = 0; r < E; ++r) cl[t * S + r] = v[r];
+    }
+    __syncthreads();
+    cx<double> u[NB][16];
+    // second pass: radix 16 over the sub-transforms of size E, twiddles W_(16E)^(r k) = W_F^(32 r k)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + NT * b, q = j / E, k = j - q * E;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) u[b][r] = cl[j + q + 16 * S * r];
 #pragma unroll
         for (int r = 1; r < 16; ++r) {
             const double2 w = tw[32 * r * k];
-            v[r] = cmul(v[r], cx<double>{w.x, INV ? -w.y : w.y});
+            u[b][r] = cmul(u[b][r], cx<double>{w.x, INV ? -w.y : w.y});
         }
-        dft16<double, INV>(v);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) cl[16 * S * q + k + S * r] = v[r];
-        __syncthreads();
+        dft16<double, INV>(u[b]);
     }
-    // pass C: radix 16 over the sub-transforms of size 16 E, twiddles W_M^(r t) = W_F^(2 r t)
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cl[t + t / E + 16 * S * r];
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + NT * b, q = j / E, k = j - q * E;
 #pragma unroll
-    for (int r = 1; r < 16; ++r) {
-        const double2 w = tw[2 * r * t];
-        v[r] = cmul(v[r], cx<double>{w.x, INV ? -w.y : w.y});
+        for (int r = 0; r < 16; ++r) cl[16 * S * q + k + S * r] = u[b][r];
     }
-    dft16<double, INV>(v);
+    __syncthreads();
+    // third pass: radix 16 over the sub-transforms of size M / 16, twiddles W_M^(r j) = W_F^(2 r j)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + NT * b;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) u[b][r] = cl[j + j / E + 16 * S * r];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+            const double2 w = tw[2 * r * j];
+            u[b][r] = cmul(u[b][r], cx<double>{w.x, INV ? -w.y : w.y});
+        }
+        dft16<double, INV>(u[b]);
+    }
     __syncthreads();  // every padded read is done before the natural-order writes
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        re[t + NT * r] = v[r].x;
-        im[t + NT * r] = v[r].y;
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + NT * b;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            re[j + H * r] = u[b][r].x;
+            im[j + H * r] = u[b][r].y;
+        }
     }
     __syncthreads();
 }
 
 // FP32: radix-16 passes (fewer passes and barriers; measured 12% faster on the batched FP32
 // path).  FP64: radix-8 passes (radix-16 Stockham passes hold twice the registers per point and
-// measured 5-6% slower), except at M = 16 NT, which runs group_fft16.
+// measured 5-6% slower), except at M = 16 NT and 32 NT, which run group_fft.
 template <typename T, int M, bool INV>
 __device__ __forceinline__ void fft_lds(T* re, T* im, const typename tw_of<T>::type* tw) {
-    if constexpr (std::is_same<T, double>::value && M == 16 * NT) {
-        group_fft16<INV>(re, im, tw);
+    if constexpr (std::is_same<T, double>::value && (M == 16 * NT || M == 32 * NT)) {
+        group_fft<M / NT, INV>(re, im, tw);
         return;
     }
     constexpr int L2 = ilog2(M);
