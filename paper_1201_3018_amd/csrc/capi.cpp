@@ -154,10 +154,15 @@ apx_status get_table(apx_ctx c, int F, double2** d, float2** f) {
         for (int i = 0; i < n; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
         double2* dd = nullptr;
         float2* ff = nullptr;
-        HIPCHK(hipMalloc((void**)&dd, n * sizeof(double2)));
-        HIPCHK(hipMalloc((void**)&ff, n * sizeof(float2)));
-        HIPCHK(hipMemcpy(dd, hd.data(), n * sizeof(double2), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(ff, hf.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+        hipError_t e = hipMalloc((void**)&dd, n * sizeof(double2));
+        if (e == hipSuccess) e = hipMalloc((void**)&ff, n * sizeof(float2));
+        if (e == hipSuccess) e = hipMemcpy(dd, hd.data(), n * sizeof(double2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(ff, hf.data(), n * sizeof(float2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (dd) (void)hipFree(dd);
+            if (ff) (void)hipFree(ff);
+            return fail(APX_E_DEVICE, "twiddle table of %d points: %s", F, hipGetErrorString(e));
+        }
         it = c->tables.emplace(F, std::make_pair(dd, ff)).first;
     }
     if (d) *d = it->second.first;
@@ -626,7 +631,8 @@ apx_status apx_run(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* 
 }
 
 apx_status apx_debug_fields(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, double* fields, void* stream) {
-    if (!k || !fields) return fail(APX_E_INVALID, "null argument");
+    if (!ctx || !k || !s || !fields) return fail(APX_E_INVALID, "null argument");
+    if (L < k->N) return fail(APX_E_INVALID, "input shorter than the kernel");
     if (k->params.mode < APX_SYM || k->params.mode > APX_ASYM3)
         return fail(APX_E_INVALID, "integer fields exist for fixed packed modes only");
     float* tmp = nullptr;

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -97,7 +98,7 @@ struct Req {
 struct DevPool {
     std::map<size_t, std::vector<void*>> free_;
     std::vector<void*> all_;
-    size_t reserved = 0;
+    std::atomic<size_t> reserved{0};  // read by the stats call on other threads
     void* get(size_t cls) {
         auto& v = free_[cls];
         if (!v.empty()) {
@@ -249,10 +250,17 @@ struct apx_server_s {
             in_use += e.bytes;
             lru.push_front(key);
             e.lru = lru.begin();
-            it = cache.emplace(key, e).first;
-            st.kernel_misses++;
+            {
+                // the stats call reads the cache and the counters under the same lock
+                std::lock_guard<std::mutex> g(mu);
+                it = cache.emplace(key, e).first;
+                st.kernel_misses++;
+            }
         } else {
-            st.kernel_hits++;
+            {
+                std::lock_guard<std::mutex> g(mu);
+                st.kernel_hits++;
+            }
             lru.splice(lru.begin(), lru, it->second.lru);
             if (hipStreamWaitEvent(s, it->second.ready, 0) != hipSuccess) return APX_E_DEVICE;
         }
@@ -316,7 +324,10 @@ struct apx_server_s {
                 }
                 q->t_admit = now_s();
                 int rc = launch(q);
-                st.peak_bytes = std::max<int64_t>(st.peak_bytes, (int64_t)in_use);
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    st.peak_bytes = std::max<int64_t>(st.peak_bytes, (int64_t)in_use);
+                }
                 if (rc != APX_OK) {
                     // work may be enqueued on the stream: let it end before the buffers go back
                     if (q->stream) (void)hipStreamSynchronize(q->stream);
@@ -423,7 +434,7 @@ apx_status apx_server_stats(apx_server srv, apx_server_counters* out) {
     if (!srv || !out) return APX_E_INVALID;
     std::lock_guard<std::mutex> g(srv->mu);
     *out = srv->st;
-    out->reserved_bytes = (int64_t)srv->pool.reserved;
+    out->reserved_bytes = (int64_t)srv->pool.reserved.load();
     out->cached_kernels = (int32_t)srv->cache.size();
     return APX_OK;
 }
