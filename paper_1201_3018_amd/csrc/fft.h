@@ -227,24 +227,19 @@ __device__ __forceinline__ void dft_group(cx<double>* v, const double2* tw) {
 // Complex FFT of M = E NT points in FP64 (E = 16 or 32 per thread): a DFT-E in registers, then
 // two radix-16 passes (E / 16 butterflies per thread), with two exchanges through LDS in a padded
 // layout (point i at i + floor(i / E), which spreads a pass's strided accesses over the banks),
-// where the Stockham form takes five passes through LDS and twice the barriers.  In and out:
-// natural order in re[], im[]; the padded layout takes fft_lds_bytes(true, M) from re on.
+// where the Stockham form takes five passes through LDS and twice the barriers.  In: point
+// t + NT r in v[r] of thread t; no thread may still read or write the fft_lds_bytes(true, M)
+// bytes from re on (a barrier since their last use).  Out: natural order in re[], im[].
 // tw: W_F^t, F = 2M.
 template <int E, bool INV>
-__device__ __forceinline__ void group_fft(double* re, double* im, const double2* tw) {
+__device__ __forceinline__ void group_fft_regs(cx<double>* v, double* re, double* im, const double2* tw) {
     constexpr int M = E * NT, S = E + 1, NB = E / 16, H = M / 16;
     cx<double>* cl = reinterpret_cast<cx<double>*>(re);
     const int t = threadIdx.x;
-    {
-        cx<double> v[E];
+    // first pass: DFT-E over stride NT; point t E + r goes to t S + r
+    dft_group<E, INV>(v, tw);
 #pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = {re[t + NT * r], im[t + NT * r]};
-        __syncthreads();  // every natural-order read is done before the padded layout overwrites it
-        // first pass: DFT-E over stride NT; point t E + r goes to t S + r
-        dft_group<E, INV>(v, tw);
-#pragma unroll
-        for (int r = 0; r < E; ++r) cl[t * S + r] = v[r];
-    }
+    for (int r = 0; r < E; ++r) cl[t * S + r] = v[r];
     __syncthreads();
     cx<double> u[NB][16];
     // second pass: radix 16 over the sub-transforms of size E, twiddles W_(16E)^(r k) = W_F^(32 r k)
@@ -292,6 +287,16 @@ __device__ __forceinline__ void group_fft(double* re, double* im, const double2*
         }
     }
     __syncthreads();
+}
+
+// The same transform from natural order in re[], im[].
+template <int E, bool INV>
+__device__ __forceinline__ void group_fft(double* re, double* im, const double2* tw) {
+    cx<double> v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = {re[threadIdx.x + NT * r], im[threadIdx.x + NT * r]};
+    __syncthreads();  // every natural-order read is done before the padded layout overwrites it
+    group_fft_regs<E, INV>(v, re, im, tw);
 }
 
 // FP32: radix-16 passes (fewer passes and barriers; measured 12% faster on the batched FP32

@@ -566,7 +566,11 @@ hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st) {
 // ------------------------------------------------------------------------------------------
 // Complex points of the packed FFT for word length F: MW = F / 2.
 // PACKED: the caller has already written the packed words into re / im (pack_regs).
-template <int MODE, int MW, bool PACKED = false, typename Sink = StoreSink>
+template <int MODE, int MW, typename Sink>
+__device__ void fft_item_tail(const RunArgs& a, const Item& it, const Choice& c, char* lds, Sink& sk);
+
+// REGPACK: the register route of the 16 NT and 32 NT point FP64 transforms (below) is allowed.
+template <int MODE, int MW, bool PACKED = false, typename Sink = StoreSink, bool REGPACK = true>
 __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char* lds, Sink&& sk = Sink{}) {
     using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
     using T2 = typename tw_of<T>::type;
@@ -575,15 +579,68 @@ __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char
     T* im = re + MW;
     const int N = a.N;
     const T2* tw;
-    const T2* H;
-    if constexpr (MODE == MD_FULL32) {
+    if constexpr (MODE == MD_FULL32)
         tw = a.twf + F;
-        H = a.spec32;
-    } else {
+    else
         tw = a.twd + F;
-        H = a.spec[MODE];
+    // The FP64 transforms of 16 NT and 32 NT points run in registers: thread t packs its points
+    // t + NT k straight into them, with no pass of the words through LDS (not the symmetric words
+    // at 32 NT, whose 64 sample-pair loads per thread spill).
+    constexpr bool REGF = REGPACK && !PACKED && std::is_same<T, double>::value &&
+                          (MW == 16 * NT || (MW == 32 * NT && MODE != MD_SYM));
+    if constexpr (REGF) {
+        constexpr int E = MW / NT;
+        cx<double> v[E];
+        const double eps = 1.0 / (2.0 * (double)c.R), cs = c.cs;
+        if constexpr (MODE == MD_SYM) {
+            const float* sp = a.s + it.start;
+            if (4 * MW <= it.nvalid && (reinterpret_cast<uintptr_t>(sp) & 7) == 0) {
+                const float2* s2 = reinterpret_cast<const float2*>(sp);
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int n = threadIdx.x + NT * k;
+                    const float2 p0 = s2[2 * n], p1 = s2[2 * n + 1];
+                    v[k] = {rint(cs * (double)p0.x) + eps * rint(cs * (double)p0.y),
+                            rint(cs * (double)p1.x) + eps * rint(cs * (double)p1.y)};
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int i0 = 4 * (threadIdx.x + NT * k);
+                    v[k] = {sq_at(a, it, cs, i0) + eps * sq_at(a, it, cs, i0 + 1),
+                            sq_at(a, it, cs, i0 + 2) + eps * sq_at(a, it, cs, i0 + 3)};
+                }
+            }
+        } else {
+            constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
+            const bool prefix = it.j_lo == 0;
+            const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+            const int base_off = it.j_lo - (N - 1);
+            const int lw = Tit + N - 1;
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int n = threadIdx.x + NT * k;
+                double w2[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int m = 2 * n + h;
+                    double acc = 0.0;
+                    if (m < lw) {
+                        double e = 1.0;
+#pragma unroll
+                        for (int q = 0; q < MM; ++q) {
+                            acc += e * sq_at(a, it, cs, base_off + q * Tit + m);
+                            e *= eps;
+                        }
+                    }
+                    w2[h] = acc;
+                }
+                v[k] = {w2[0], w2[1]};
+            }
+        }
+        group_fft_regs<E, false>(v, (double*)re, (double*)im, (const double2*)tw);
     }
-    if constexpr (!PACKED) {
+    if constexpr (!PACKED && !REGF) {
         // ---- pack: z[n] = x[2n] + i x[2n+1]
         if constexpr (MODE == MD_FULL32) {
             const float* sp = a.s + it.start;
@@ -648,8 +705,32 @@ __device__ void fft_item(const RunArgs& a, const Item& it, const Choice& c, char
             }
         }
     }
-    __syncthreads();
-    fft_lds<T, MW, false>(re, im, tw);
+    if constexpr (!REGF) {
+        __syncthreads();
+        fft_lds<T, MW, false>(re, im, tw);
+    }
+    fft_item_tail<MODE, MW>(a, it, c, lds, sk);
+}
+
+// The steps of fft_item after the forward transform (its spectrum in natural order in the LDS):
+// the spectral step, the inverse transform, then unpacking, dequantization and placement.
+template <int MODE, int MW, typename Sink>
+__device__ void fft_item_tail(const RunArgs& a, const Item& it, const Choice& c, char* lds, Sink& sk) {
+    using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+    using T2 = typename tw_of<T>::type;
+    constexpr int F = 2 * MW;
+    T* re = (T*)lds;
+    T* im = re + MW;
+    const int N = a.N;
+    const T2* tw;
+    const T2* H;
+    if constexpr (MODE == MD_FULL32) {
+        tw = a.twf + F;
+        H = a.spec32;
+    } else {
+        tw = a.twd + F;
+        H = a.spec[MODE];
+    }
     spectral_step<T, MW>(re, im, tw, H);
     fft_lds<T, MW, true>(re, im, tw);
     // ---- unpack + dequantize + place
@@ -710,10 +791,12 @@ __global__ void __launch_bounds__(NT) k_fft(RunArgs a) {
         return;
     }
     if (it.j_hi <= it.j_lo) return;
+    // at 2^14 words the register packing of every mode in one kernel spills: the words go through LDS
+    constexpr bool RP = LOGF < 14;
     switch (c.mode) {
-        case MD_SYM: fft_item<MD_SYM, MS>(a, it, c, lds); break;
-        case MD_ASYM2: fft_item<MD_ASYM2, MA>(a, it, c, lds); break;
-        case MD_ASYM3: fft_item<MD_ASYM3, MA>(a, it, c, lds); break;
+        case MD_SYM: fft_item<MD_SYM, MS, false, StoreSink, RP>(a, it, c, lds); break;
+        case MD_ASYM2: fft_item<MD_ASYM2, MA, false, StoreSink, RP>(a, it, c, lds); break;
+        case MD_ASYM3: fft_item<MD_ASYM3, MA, false, StoreSink, RP>(a, it, c, lds); break;
         default: fft_item<MD_FULL32, MA>(a, it, c, lds); break;
     }
 }
@@ -922,6 +1005,23 @@ __device__ void pack_regs(const Item& it, const Choice& c, const WinRegs<MODE, M
     }
 }
 
+// The symmetric packed points of pack_regs kept in registers: point threadIdx.x + NT k in v[k].
+template <int MW>
+__device__ void pack_regs_points(const Item& it, const Choice& c, const WinRegs<MD_SYM, MW>& wr, cx<double>* v) {
+    using R = WinRegs<MD_SYM, MW>;
+    const bool full = R::SPP * MW <= it.nvalid;
+    const double eps = 1.0 / (2.0 * (double)c.R), cs = c.cs;
+#pragma unroll
+    for (int k = 0; k < R::PPT; ++k) {
+        const int n = threadIdx.x + NT * k;
+        float x[R::SPP];
+#pragma unroll
+        for (int h = 0; h < R::SPP; ++h) x[h] = (full || R::SPP * n + h < it.nvalid) ? wr.x[k][h] : 0.0f;
+        v[k] = {rint(cs * (double)x[0]) + eps * rint(cs * (double)x[1]),
+                rint(cs * (double)x[2]) + eps * rint(cs * (double)x[3])};
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Batched cross-correlation matching: one persistent launch over a work list of (pair, block)
 // items.  Each workgroup takes `chunk` consecutive items at a time from a global counter, runs
@@ -971,8 +1071,16 @@ __global__ void __launch_bounds__(NT, (MODE == MD_FULL32 ? LOGW <= 14 : LOGW <= 
                     if ((c.flags & APX_FLAG_ZERO) && MODE != MD_FULL32) {
                         sk.consider(it.o0, 0.0f);  // all outputs of the block are zero
                     } else {
-                        pack_regs<MODE, MW>(it, c, wr, lds);
-                        fft_item<MODE, MW, true>(a, it, c, lds, sk);
+                        if constexpr (MODE == MD_SYM && MW == 16 * NT) {
+                            // the FP64 transform runs in registers: the packed points go straight in
+                            cx<double> v[16];
+                            pack_regs_points<MW>(it, c, wr, v);
+                            group_fft_regs<16, false>(v, (double*)lds, (double*)lds + MW, a.twd + 2 * MW);
+                            fft_item_tail<MODE, MW>(a, it, c, lds, sk);
+                        } else {
+                            pack_regs<MODE, MW>(it, c, wr, lds);
+                            fft_item<MODE, MW, true>(a, it, c, lds, sk);
+                        }
                     }
                 }
             } else {
