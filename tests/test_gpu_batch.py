@@ -97,8 +97,11 @@ def _check_pair(ref, k, Wb, mode, lag, val, logW):
 
 
 @pytest.mark.parametrize("mode", [O.SYM, O.ASYM2, O.ASYM3, O.FULL])
-@pytest.mark.parametrize("logW", [11, 12])
+@pytest.mark.parametrize("logW", [11, 12, 13, 14])
 def test_batch_small(ctx, mode, logW):
+    """Every mode against the oracle's blocked correlation and argmax, up to the 4096- and
+    8192-point FP64 transforms that run in registers (LOGW 13, 14): several blocks per reference
+    with ragged last blocks, a template as long as its reference, a zero template, NaN inputs."""
     refs, tmpls = _small_pairs()
     _say(f"batch small mode={mode} logW={logW} pairs={len(refs)}")
     b = apx.Batch(ctx, [_dev(r) for r in refs], [_dev(k) for k in tmpls], mode=MODES[mode], logW=logW)

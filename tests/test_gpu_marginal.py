@@ -95,7 +95,8 @@ def _check_auto(s, k, Wb, target, calib, sigma_s, sigma_k, got, info):
 
 
 @pytest.mark.parametrize("N,Wb,core", [(1024, 4096, apx.APX_CORE_FFT), (65, 1024, apx.APX_CORE_TIME),
-                                       (300, 2048, apx.APX_CORE_FFT)])
+                                       (300, 2048, apx.APX_CORE_FFT), (1000, 8192, apx.APX_CORE_FFT),
+                                       (2000, 16384, apx.APX_CORE_FFT)])
 @pytest.mark.parametrize("split", [O.SYM, O.ASYM2])
 def test_source_sigma_selection(ctx, N, Wb, core, split):
     """AUTO selection with the signal's Laplacian sigma and the taps' Laplacian sigma, at the

@@ -207,7 +207,8 @@ def test_wave_nonfinite_in_full_chunk(ctx, bad):
     assert np.count_nonzero(info["flags"] & apx.APX_FLAG_NONFINITE) >= 1
 
 
-@pytest.mark.parametrize("mode,N,Wb", [(O.ASYM2, 800, 8994), (O.ASYM3, 800, 8994), (O.SYM, 800, 17186),
+@pytest.mark.parametrize("mode,N,Wb", [(O.ASYM2, 800, 8994), (O.ASYM3, 800, 8994), (O.SYM, 800, 8994),
+                                       (O.SYM, 800, 17186),
                                        (O.ASYM2, 800, 17186), (O.ASYM3, 800, 17186), (O.ASYM3, 800, 33570),
                                        (O.SYM, 101, 32768), (O.ASYM2, 40, 600)])
 def test_fft_block_core_own_length(ctx, mode, N, Wb):
