@@ -246,13 +246,13 @@ __device__ __forceinline__ void group_fft_regs(cx<double>* v, double* re, double
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + NT * b, q = j / E, k = j - q * E;
+        double2 w[15];  // the pass's twiddles are fetched together, ahead of the LDS reads
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w[r - 1] = tw[32 * r * k];
 #pragma unroll
         for (int r = 0; r < 16; ++r) u[b][r] = cl[j + q + 16 * S * r];
 #pragma unroll
-        for (int r = 1; r < 16; ++r) {
-            const double2 w = tw[32 * r * k];
-            u[b][r] = cmul(u[b][r], cx<double>{w.x, INV ? -w.y : w.y});
-        }
+        for (int r = 1; r < 16; ++r) u[b][r] = cmul(u[b][r], cx<double>{w[r - 1].x, INV ? -w[r - 1].y : w[r - 1].y});
         dft16<double, INV>(u[b]);
     }
     __syncthreads();
@@ -267,13 +267,13 @@ __device__ __forceinline__ void group_fft_regs(cx<double>* v, double* re, double
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + NT * b;
+        double2 w[15];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w[r - 1] = tw[2 * r * j];
 #pragma unroll
         for (int r = 0; r < 16; ++r) u[b][r] = cl[j + j / E + 16 * S * r];
 #pragma unroll
-        for (int r = 1; r < 16; ++r) {
-            const double2 w = tw[2 * r * j];
-            u[b][r] = cmul(u[b][r], cx<double>{w.x, INV ? -w.y : w.y});
-        }
+        for (int r = 1; r < 16; ++r) u[b][r] = cmul(u[b][r], cx<double>{w[r - 1].x, INV ? -w[r - 1].y : w[r - 1].y});
         dft16<double, INV>(u[b]);
     }
     __syncthreads();  // every padded read is done before the natural-order writes
