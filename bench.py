@@ -77,8 +77,8 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the method shards by block ranges "
-                                   "(see the design notes) but no multi-GPU run is part of this build"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the blocks are independent, so the "
+                                   "method would shard by block ranges, but no multi-GPU path is implemented"}))
         sys.exit(2)
 
     import torch
@@ -272,18 +272,24 @@ def main():
     if int8_core:
         res["int8_core"] = int8_core
     if args.copy_probe:
-        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        res["copy_probe_bytes"] = 2 * a.numel() * 4
+        res["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.workload, s, k, Wb, wl, calib, outputs)
     print(json.dumps(res), flush=True)
     for kh in {id(x): x for x in (kern, full, ref64)}.values():
         kh.close()
     ctx.close()
+
+
+def copy_probe(dev):
+    """A 256 MiB device copy of known size, three times: the reference that scales the HBM
+    counters of a rocprofv3 run (bytes read + written per copy returned)."""
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return 2 * src.numel() * 4
 
 
 def bench_c3(args, wl):
@@ -347,7 +353,7 @@ def bench_c3(args, wl):
     else:
         roof = {"bound": "hbm", "achieved": round(head["hbm_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic("c3")  # scaled FETCH_SIZE + WRITE_SIZE of the symmetric kernel
     roof["kernel"] = head["kernel"]
     res = {
         "metric": "correlation lags/s of batched matching (argmax per template), packed vs FP32, 1 GPU",
@@ -358,6 +364,8 @@ def bench_c3(args, wl):
         "roofline": roof, "modes": res_modes,
         "packed_over_fp32": res_modes["full_fp32"]["ms_per_step"] / head["ms_per_step"],
     }
+    if args.copy_probe:
+        res["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu:
         import oracle as O
         t0 = time.perf_counter()
@@ -946,13 +954,19 @@ def bench_calib(args, wl):
     ctx.close()
 
 
+# rocprofv3 counter summary per workload and the kernel sources its figures hold for
+TRAFFIC_SUMMARIES = {"c2": ("fft_c2_hbm_counters.md", ("fftw.hip", "fft.h", "internal.h")),
+                     "c3": ("batch_c3_hbm_counters.md", ("kernels.hip", "fft.h", "internal.h"))}
+
+
 def measured_traffic(workload: str):
-    """HBM bytes per launch of the packed kernel from the committed rocprofv3 counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    if workload != "c2":
+    """HBM bytes per launch of the workload's headline kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since the counters were taken."""
+    if workload not in TRAFFIC_SUMMARIES:
         return None
     import hashlib
-    path = os.path.join(ROOT, "profiles", "fft_c2_hbm_counters.md")
+    fname, srcs = TRAFFIC_SUMMARIES[workload]
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     rec = {}
@@ -961,7 +975,7 @@ def measured_traffic(workload: str):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in ("fftw.hip", "fft.h", "internal.h"):
+    for f in srcs:
         h.update(open(os.path.join(ROOT, "paper_1201_3018_amd", "csrc", f), "rb").read())
     if rec.get("kernel_sources_sha256_16") != h.hexdigest()[:16]:
         return None
