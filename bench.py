@@ -284,6 +284,7 @@ def main():
 def copy_probe(dev):
     """A 256 MiB device copy of known size, three times: the reference that scales the HBM
     counters of a rocprofv3 run (bytes read + written per copy returned)."""
+    import torch
     src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -310,7 +311,9 @@ def bench_c3(args, wl):
     steps = max(1, min(args.steps, 20))
     warm = max(1, min(args.warmup, 3))
     for name, mode in (("sym", apx.APX_SYM), ("asym2", apx.APX_ASYM2), ("full_fp32", apx.APX_FULL_FP32)):
+        print(f"c3: {name}: building and autotuning the batch", file=sys.stderr, flush=True)
         b = apx.Batch(ctx, pr, pk, mode=mode, logW=0)
+        print(f"c3: {name}: timing", file=sys.stderr, flush=True)
         lag = torch.empty(len(pk), dtype=torch.int64, device=dev)
         val = torch.empty(len(pk), dtype=torch.float32, device=dev)
         for _ in range(warm):
