@@ -658,8 +658,11 @@ __global__ void __launch_bounds__(64) k_fftw(RunArgs a) {
     __shared__ __attribute__((aligned(16))) char lds[BYTES];
     // one item per workgroup (a loop here makes the compiler keep every per-lane address of the
     // body live across iterations, which spills)
-    const int64_t item = blockIdx.x;
-    if (item >= a.P + 1) return;
+    // consecutive blocks share N + 1 samples: give consecutive blocks to workgroups of one XCD
+    // (workgroups go to the 8 XCDs in turn), so that the shared samples meet in one L2
+    const int64_t nblk = a.P + 1, q8 = nblk / 8, r8 = nblk % 8, x8 = blockIdx.x % 8;
+    const int64_t item = x8 * q8 + (x8 < r8 ? x8 : r8) + blockIdx.x / 8;
+    if (blockIdx.x >= nblk) return;
     {
         const WItem it = wave_make_item(a, item);
         const WStats st = wave_load_window(a, it, reinterpret_cast<float*>(lds) + 1);
