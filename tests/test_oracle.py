@@ -58,6 +58,51 @@ def test_argmax_ties_smallest_lag():
     assert O.argmax_lag(c, 2) == (0, 3.0)
 
 
+def _argmax_scan(c, N):
+    """The matching rule written as one scan: a later entry replaces the best only when it is
+    strictly larger (so equal maxima keep the smallest lag and -0 ties with +0); NaN never does."""
+    best = None
+    for i, v in enumerate(c):
+        if v != v:
+            continue
+        if best is None or v > c[best]:
+            best = i
+    return (None, None) if best is None else (best - (N - 1), float(c[best]))
+
+
+def test_argmax_lag_finite_hand_cases():
+    """Sections IV.B-C: the match is the lag of the largest correlation.  Hand cases cover NaN
+    entries, an all-NaN input, -0 against +0 and equal maxima (smallest lag)."""
+    for case in _gold("hand_examples.json")["argmax_lag_finite"]:
+        c = np.array([np.nan if v is None else v for v in case["c"]], dtype=np.float64)
+        lag, val = O.argmax_lag_finite(c, case["N"])
+        assert lag == case["lag"], case["cite"]
+        if case["value"] is None:
+            assert math.isnan(val)
+        else:
+            assert val == case["value"], case["cite"]
+        assert _argmax_scan(c, case["N"])[0] == case["lag"]
+        # the same rule in FP32 (the GPU's output type)
+        assert O.argmax_lag_finite(c.astype(np.float32), case["N"])[0] == case["lag"]
+
+
+def test_argmax_lag_finite_against_scan():
+    """Random arrays over a small alphabet (many ties, signed zeros, NaNs) against the scan."""
+    rng = np.random.default_rng(41)
+    alphabet = np.array([-1.0, -0.0, 0.0, 1.0, 2.0, np.nan, np.inf, -np.inf])
+    for trial in range(400):
+        n = int(rng.integers(1, 40))
+        c = alphabet[rng.integers(0, alphabet.size, n)]
+        N = int(rng.integers(1, 6))
+        lag, val = O.argmax_lag_finite(c, N)
+        ref_lag, ref_val = _argmax_scan(c, N)
+        assert lag == ref_lag
+        if ref_lag is None:
+            assert math.isnan(val)
+        else:
+            assert val == ref_val
+
+
 # ---------------------------------------------------------------- partition and placement
 @pytest.mark.parametrize("L,N,Wb", [(65536, 64, 1024), (5000, 65, 1024), (3000, 7, 64), (131, 3, 32),
                                     (40, 40, 200), (1, 1, 8), (958, 64, 1024), (959, 64, 1024)])
@@ -263,11 +308,68 @@ def test_plain_definition_invariants():
     n[5000] = np.nan
     rn = O.conv_blocked(n, k, 512, O.fixed_params(n, k, 512, O.SYM, 20, 20), out_dtype=np.float64)
     assert np.isnan(rn[5010]) and np.isfinite(rn[100])
-    # correlation = convolution with the reversed kernel, also in the quantized domain
-    f1 = O.int_fields(s, k[::-1].copy(), 512, 20, 20)
+    # correlation = convolution with the reversed kernel (eq. 1 form against the textbook sum)
     c = O.xcorr_direct(s[:300], k)
     assert np.allclose(O.xcorr(s[:300], k), c, atol=1e-12)
-    assert f1.size == s.size + k.size - 1
+
+
+# ---------------------------------------------------------------- blocked correlation (Sections IV.B-C)
+def test_xcorr_blocked_hand_cases():
+    """Tiny correlations worked by hand: one block, companding factors 1 and 4 (eq. 2), eq. (16)
+    scaling, and the match (ties to the smallest lag)."""
+    for case in _gold("hand_examples.json")["xcorr_blocked"]:
+        s = np.array(case["s"], dtype=np.float32)
+        k = np.array(case["k"], dtype=np.float32)
+        got = O.xcorr_blocked(s, k, case["W_block"], O.SYM, case["S"], case["K"], out_dtype=np.float64)
+        assert np.array_equal(got, np.array(case["c"], dtype=np.float64)), case["cite"]
+        if "argmax_lag" in case:
+            assert O.argmax_lag_finite(got, k.size) == (case["argmax_lag"], case["argmax_value"])
+        # the full-precision blocks give the textbook correlation
+        full = O.xcorr_blocked(s, k, case["W_block"], O.FULL, out_dtype=np.float64)
+        assert np.allclose(full, np.correlate(s.astype(np.float64), k.astype(np.float64), "full"), atol=1e-12)
+
+
+def _xcorr_blocked_by_library(s, k, Wb, S, K):
+    """Independent composition: per overlap-save block (Section III placement, W = W_block - N - 1,
+    block w >= 1 starting at W w - 2), the companded integers of eq. (2) correlated by
+    numpy.correlate, scaled by eq. (16) and placed by eq. (17)."""
+    s = np.asarray(s, dtype=np.float64)
+    k = np.asarray(k, dtype=np.float64)
+    L, N = s.size, k.size
+    No = N if N % 2 else N + 1
+    W = Wb - No - 1
+    P = -(-L // W)
+    ck = K / np.max(np.abs(k))
+    kq = np.rint(ck * k)
+    out = np.zeros(L + N - 1)
+    for w in range(P):
+        a = 0 if w == 0 else W * w - 2
+        b = np.zeros(Wb)
+        seg = s[a:a + Wb]
+        b[:seg.size] = seg
+        cs = S / np.max(np.abs(b))
+        c = np.correlate(np.rint(cs * b), kq, "full")      # c[j] = conv(s~, reversed k~)[j]
+        j_lo, j_hi, o = (0, W + No - 1, 0) if w == 0 else (No + 1, No + 1 + W, No - 1 + W * w)
+        n = max(0, min(j_hi - j_lo, out.size - o))
+        out[o:o + n] = (1.0 / (cs * ck)) * c[j_lo:j_lo + n]
+    return out
+
+
+@pytest.mark.parametrize("mode,S", [(O.SYM, 0), (O.ASYM2, 0), (O.ASYM3, 0), (O.SYM, 25)])
+@pytest.mark.parametrize("L,N,Wb", [(5000, 64, 1024), (3001, 65, 512), (700, 33, 128), (129, 33, 256)])
+def test_xcorr_blocked_equals_library_correlation(mode, S, L, N, Wb):
+    """xcorr_blocked in a packed mode equals numpy's correlation of the companded integers per
+    block; with full-precision blocks it equals numpy's correlation of the samples."""
+    rng = np.random.default_rng(L + 7 * N)
+    s = rng.standard_normal(L).astype(np.float32)
+    k = rng.uniform(-1.0, 1.0, N).astype(np.float32)
+    No = N if N % 2 else N + 1
+    q = S or O.max_q(mode, No)
+    got = O.xcorr_blocked(s, k, Wb, mode, q, q, out_dtype=np.float64)
+    assert np.array_equal(got, _xcorr_blocked_by_library(s, k, Wb, q, q))
+    full = O.xcorr_blocked(s, k, Wb, O.FULL, out_dtype=np.float64)
+    ref = np.correlate(s.astype(np.float64), k.astype(np.float64), "full")
+    assert np.allclose(full, ref, rtol=0, atol=1e-12 * np.sum(np.abs(k)) * np.max(np.abs(s)))
 
 
 # ---------------------------------------------------------------- distortion model
