@@ -384,9 +384,14 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             if (p.Sq) S = p.Sq;
             if (p.Kq) K = p.Kq;
         }
+        // S, K < 2^31, so S K fits; N_odd S K may not (caller-given ranges)
+        int64_t Rm = 0;
+        if (__builtin_mul_overflow(S * K, (int64_t)N_odd, &Rm))
+            return fail(APX_E_BOUND, "R_max = N S_q K_q overflows 64 bits (N = %d, S_q = %lld, K_q = %lld)", N_odd,
+                        (long long)S, (long long)K);
         k->S[m] = (int32_t)S;
         k->K[m] = (int32_t)K;
-        k->R[m] = (int64_t)N_odd * S * K;
+        k->R[m] = Rm;
         k->T[m] = (m == MD_SYM) ? 0 : (W + (m == MD_ASYM2 ? 2 : 3) - 1) / (m == MD_ASYM2 ? 2 : 3);
     }
     if (p.mode >= APX_SYM && p.mode <= APX_ASYM3) {

@@ -392,9 +392,10 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
 
 
 
-// exact digits of a symmetric-packed word: rb = 2R Dm + B + eps De, |B| <= R.  The quotient
-// estimate uses the rounded reciprocal of 2R; it can be off by one only, which the range
-// corrections below undo, so the digits are exact.
+// digits of a symmetric-packed word: rb = 2R Dm + B + eps De, |B| <= R.  The quotient estimate
+// uses the rounded reciprocal of 2R; it can be off by one only, which the range corrections
+// below undo.  A base digit at |B| = R is ambiguous ((Dm, R) and (Dm + 1, -R) make the same
+// word) and is split toward the smaller |Dm|, as in the block kernels.
 __device__ __forceinline__ void wsym_split(double rb, double two_r, double inv_two_r, double R, double& Dm, double& B,
                                            double& De) {
     const double I = rint(rb);

@@ -301,8 +301,11 @@ __device__ __forceinline__ double sq_at(const RunArgs& a, const Item& it, double
 // ------------------------------------------------------------------------------------------
 // Symmetric packing: rb = 2R Dm + B + eps De with |B| <= R, |Dm|, |De| < R (eq. 9).  The side-eps
 // digit is read from the fraction, the rest split into base and side-eps^-1 digits by a
-// balanced division by 2R (ties at |B| = R resolved toward the smaller |Dm|, which is the only
-// decomposition inside the digit ranges).  Equals eqs. (11)-(15) wherever those are exact.
+// balanced division by 2R.  At |B| = R the integer part 2R Dm + B is the same for (Dm, R) and
+// (Dm + 1, -R): the word does not tell them apart.  The split then takes the one with the
+// smaller |Dm|, which is wrong whenever the true Dm and B have opposite signs; this tie is the
+// case the no-overlap condition excludes (every product of a window at full scale with one
+// sign).  Everywhere else the digits are unique and equal eqs. (11)-(15) where those are exact.
 struct SymDigits {
     double Dm, B, De;
 };

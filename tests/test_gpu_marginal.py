@@ -13,6 +13,7 @@ import pytest
 
 import oracle as O
 from paper_1201_3018_amd import synth
+from gpu_checks import check_mixed_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -82,15 +83,7 @@ def _check_auto(s, k, Wb, target, calib, sigma_s, sigma_k, got, info):
     packed = (info["mode"] != 0) & ~near & np.isfinite([p.snr_pred_db for p in ps])
     pred = np.array([p.snr_pred_db for p in ps])
     assert np.allclose(info["snr_pred_db"][packed], pred[packed], rtol=0, atol=1e-9)
-    for p, m in zip(ps, info["mode"]):
-        p.mode = {1: O.SYM, 2: O.ASYM2, 0: O.FULL}[int(m)]
-    ref = O.conv_blocked(s, k, Wb, ps)
-    part = O.partition(len(s), len(k), Wb)
-    for w in range(part.P):
-        if info["mode"][w] == 0:
-            continue
-        j_lo, j_hi, o = part.keep(w)
-        assert np.array_equal(got[o:o + j_hi - j_lo], ref[o:o + j_hi - j_lo]), w
+    check_mixed_blocks(s, k, Wb, ps, info["mode"], got, "fft")
     return np.bincount(info["mode"], minlength=3)
 
 
