@@ -52,9 +52,9 @@ WORKLOADS = {
                        "2^20-sample sources with a 1025-sample excerpt, W_block=4096; AR(1) audio with a zero-mean "
                        "Laplacian fit and Weibull(0.248, 1.191) features with a Weibull fit; S_q=K_q from 8 to 256 on "
                        "the integer core; model calibrated once at S_q=K_q=8"),
-    "c1": dict(L=65536, N=64, Wb=1024, snr=None, core="td",
-               name="time-domain overlap-save convolution: L=65536 N(0,1), N=64 U(-1,1), W_block=1024, "
-                    "asymmetric M=2 at 8 bits (S_q=K_q=127)"),
+    "c1": dict(L=65536, N=64, Wb=1024, snr=None, core="td", nsig=1024,
+               name="time-domain overlap-save convolution, batch of 1024 signals in one launch: L=65536 N(0,1) each, "
+                    "N=64 U(-1,1), W_block=1024, asymmetric M=2 at 8 bits (S_q=K_q=127)"),
 }
 
 
@@ -100,6 +100,8 @@ def main():
         return bench_delay(args, wl)
     if args.workload == "calib":
         return bench_calib(args, wl)
+    if args.workload == "c1":
+        return bench_c1(args, wl)
     dev = torch.device("cuda:0")
     L, N, Wb = wl["L"], wl["N"], wl["Wb"]
     if args.workload == "c2":
@@ -277,6 +279,123 @@ def main():
         res["cpu_baseline"] = cpu_baseline(args.workload, s, k, Wb, wl, calib, outputs)
     print(json.dumps(res), flush=True)
     for kh in {id(x): x for x in (kern, full, ref64)}.values():
+        kh.close()
+    ctx.close()
+
+
+def c1_batch(n, L, seed=1001):
+    """n distinct N(0,1) signals of L samples: 8 generated rows, circularly shifted and sign-flipped."""
+    from paper_1201_3018_amd import synth
+    base = synth.gaussian(L * 8, seed).reshape(8, L)
+    rng = np.random.default_rng(seed + 10)
+    host = np.empty((n, L), np.float32)
+    for i in range(n):
+        host[i] = np.roll(base[i % 8], int(rng.integers(0, L))) * (1.0 if (i // 8) % 2 == 0 else -1.0)
+    return host
+
+
+def bench_c1(args, wl):
+    """Time-domain workload as a batch: 1024 signals of 65536 samples through one prepared kernel
+    in one launch over every (signal, block) item (apx_many).  A step is one such launch; the
+    steps alternate between two input/output sets (1 GB in all, beyond the last-level cache).
+    value = output samples/s over the batch, asymmetric M=2 at 8 bits on the default core (the
+    integer matrix cores for 65 taps); the packed FP64 time-domain core and the FP32 time-domain
+    path are timed the same way beside it."""
+    import torch
+
+    from paper_1201_3018_amd import apx, synth
+    dev = torch.device("cuda:0")
+    n, L, N, Wb = wl["nsig"], wl["L"], wl["N"], wl["Wb"]
+    host = c1_batch(n, L)
+    k = synth.uniform(N, 1002)
+    sets = 2
+    ins = [torch.from_numpy(host).to(dev) for _ in range(sets)]
+    ctx = apx.Context(0)
+    tk = torch.from_numpy(k).to(dev)
+    N_odd, W, P = apx.apx_geometry(L, N, Wb)
+    outputs = n * (L + N - 1)
+    bytes_alg = n * (P * Wb * 4 + (L + N - 1) * 4)
+
+    def timed(kh, steps, warmup):
+        manys = [apx.Many(kh, [ins[j][i] for i in range(n)]) for j in range(sets)]
+        for i in range(warmup):
+            manys[i % sets].run()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(steps):
+                manys[i % sets].run()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        out = torch.stack(manys[0].outs)
+        desc = manys[0].describe()
+        for m in manys:
+            m.close()
+        return e0.elapsed_time(e1) / steps, out, desc
+
+    steps = max(1, args.steps // 4)
+    packed = apx.Kernel(ctx, tk, Wb, mode=apx.APX_ASYM2, Sq=127, Kq=127)
+    ms_packed, out_p, desc = timed(packed, steps, 3)
+    td = apx.Kernel(ctx, tk, Wb, mode=apx.APX_ASYM2, Sq=127, Kq=127, core=apx.APX_CORE_TIME)
+    ms_td, out_td, _ = timed(td, steps, 3)
+    full = apx.Kernel(ctx, tk, Wb, mode=apx.APX_FULL_FP32, core=apx.APX_CORE_TIME)
+    ms_full, out_f, _ = timed(full, steps, 3)
+    same_td = bool(torch.equal(out_p, out_td))
+    # accuracy on sampled signals against FP64 (the FP64 time-domain path, one signal at a time)
+    ref64 = apx.Kernel(ctx, tk, Wb, mode=apx.APX_FULL_FP64, core=apx.APX_CORE_TIME)
+    snrs, snrs_f = [], []
+    for i in (0, 1, 511, 1023):
+        rr = ref64.run(ins[0][i]).cpu().numpy().astype(np.float64)
+        for arr, dst in ((out_p, snrs), (out_f, snrs_f)):
+            e = np.sum((arr[i].cpu().numpy().astype(np.float64) - rr) ** 2)
+            dst.append(np.inf if e == 0 else 10 * np.log10(np.sum(rr ** 2) / e))
+    value = outputs / (ms_packed * 1e-3)
+    gbs = bytes_alg / (ms_packed * 1e-3) / 1e9
+    res = {
+        "metric": "output samples/s at fixed SNR, packed vs full-precision FP32, 1 GPU",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 3,
+        "ms_per_step": ms_packed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "signals": n, "L": L, "N": N, "W_block": Wb, "blocks_per_signal": P,
+                   "items": n * P},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic("c1"),
+                     "bytes_per_launch": bytes_alg, "bytes_per_output": round(bytes_alg / outputs, 3),
+                     "kernel": desc},
+        "packed_fp64_time_domain": {"ms_per_step": ms_td, "value": outputs / (ms_td * 1e-3),
+                                    "outputs_equal_default_core": same_td},
+        "full_fp32": {"ms_per_step": ms_full, "value": outputs / (ms_full * 1e-3),
+                      "snr_db_min": float(np.min(snrs_f))},
+        "packed_over_fp32": ms_full / ms_packed,
+        "snr_db": {"min": float(np.min(snrs)), "sampled_signals": 4},
+    }
+    if not args.no_cpu:
+        import oracle as O
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < 10.0:
+            x = host[done % n]
+            O.conv_blocked(x, k, Wb, O.fixed_params(x, k, Wb, O.ASYM2, 127, 127))
+            done += 1
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": done * (L + N - 1) / dt, "unit": "samples/s", "cores": O.num_threads(),
+                               "kind": "oracle", "sample": f"{done} of the {n} signals, one after the other: "
+                                                          f"int64 block convolution, {dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+    for kh in (packed, td, full, ref64):
         kh.close()
     ctx.close()
 
@@ -578,6 +697,7 @@ def bench_c5(args, wl, duration: float = 10.0, rate: float = 2000.0):
     collect()
     st = srv.stats()
     srv.close()
+    burst = serve_burst(ctx, sig)
     ctx.close()
     lat = np.array(lat) * 1e3
     span = last_done - t0
@@ -591,8 +711,37 @@ def bench_c5(args, wl, duration: float = 10.0, rate: float = 2000.0):
                        "p99": float(np.percentile(lat, 99)), "max": float(np.max(lat))},
         "served_req_s": len(reqs) / span, "cores": {"time": cores[1], "fft": cores[2]},
         "server": st,
+        "burst": burst,
     }
     print(json.dumps(res), flush=True)
+
+
+def serve_burst(ctx, sig, n=2000, nkern=4, N=256, seed=5002):
+    """Saturation: n requests over nkern kernels (N taps, L log-uniform in [2^14, 2^18], SNR
+    target 40 dB) submitted at once, so that many are admitted together and run as shared
+    launches; against the same requests one at a time (max_inflight = 1, one launch each)."""
+    from paper_1201_3018_amd import apx, synth
+    rng = np.random.default_rng(seed)
+    Ls = np.exp(rng.uniform(np.log(1 << 14), np.log(1 << 18), n)).astype(np.int64)
+    taps = [synth.hann_lowpass(N, 0.05 + 0.1 * j) for j in range(nkern)]
+    outs = [np.empty(int(L) + N - 1, np.float32) for L in Ls]
+    res = {}
+    for name, inflight in (("batched", 256), ("one_at_a_time", 1)):
+        srv = apx.Server(ctx, hbm_budget=32 << 30, n_streams=8, max_inflight=inflight)
+        t0 = apx.Server.now()
+        for i in range(n):
+            j = i % nkern
+            srv.submit(100 + j, taps[j], sig[i % 8], outs[i], 40.0, L=int(Ls[i]))
+        srv.drain()
+        dt = apx.Server.now() - t0
+        srv.poll(max_n=1024)
+        st = srv.stats()
+        srv.close()
+        res[name] = {"s": dt, "samples_per_s": float(np.sum(Ls + N - 1)) / dt, "launches": st["launches"],
+                     "requests": st["completed"]}
+    res["batching_gain"] = res["batched"]["samples_per_s"] / res["one_at_a_time"]["samples_per_s"]
+    res["config"] = f"{n} requests, {nkern} kernels of N={N}, L log-uniform in [2^14, 2^18], SNR 40 dB, host buffers"
+    return res
 
 
 def bench_c1sweep(args, wl):

@@ -174,6 +174,31 @@ apx_status apx_run_auto(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t
  * sizes, companding ranges per mode) written into buf (host, size bytes, NUL-terminated). */
 apx_status apx_kernel_describe(apx_kernel kern, char* buf, int32_t size);
 
+/* ---- Many signals, one kernel -----------------------------------------------------------------
+ * n signals s_i (DEVICE, L_i FP32 samples each, 8-byte aligned, L_i >= N) convolved (or, for an
+ * APX_XCORR kernel, correlated) with one prepared kernel in ONE launch over every (signal, block)
+ * item: the overlap-save blocks of all signals are independent (Section II), so they form one
+ * work list.  r_out_i (DEVICE, L_i + N - 1 FP32) receives exactly what apx_run(kern, s_i) writes,
+ * and info_i (DEVICE, P_i entries, nullable) its block report.  Fixed modes and APX_AUTO_SNR with
+ * the kernel's own calibration (apx_calibrate / params.calib_db), on any core.
+ * apx_many_create: s, r_out, info are HOST arrays of n device pointers (info, or any entry of it,
+ *   may be NULL), L a host array of n lengths.  Builds the signal table and the per-item signal
+ *   index on the device (owned by the handle, 40 + 4 P_i bytes per signal); synchronizes
+ *   `stream`.  The pointers are kept: the memory must stay valid until apx_many_destroy, its
+ *   contents may change between runs.  The kernel handle must outlive the many handle.
+ *   APX_E_INVALID: null or misaligned pointers, n < 1, L_i < N, a geometry error;
+ *   APX_E_UNSUPPORTED: more than 2^31 - 1 work items; APX_E_NOMEM: device allocation failed.
+ * apx_many_run: one launch of the kernel's block core over all items, enqueued on `stream`;
+ *   allocates nothing and can be captured into a HIP graph.  Runs share no scratch memory, so
+ *   they may overlap when their outputs do not.
+ * apx_many_describe (host only): signals, work items and the kernel's launch as text. */
+typedef struct apx_many_s* apx_many;
+apx_status apx_many_create(apx_ctx ctx, apx_kernel kern, int32_t n, const float* const* s, const int64_t* L,
+                           float* const* r_out, apx_block_info* const* info, void* stream, apx_many* out);
+apx_status apx_many_run(apx_ctx ctx, apx_many many, void* stream);
+apx_status apx_many_describe(apx_many many, char* buf, int32_t size);
+apx_status apx_many_destroy(apx_many many);
+
 /* ---- Batched cross-correlation matching ----------------------------------------------------
  * n pairs (reference s_t of L_t samples, template k_t of N_t taps).  For each pair the
  * correlation c_t[l] = sum_n s_t[l+n] k_t[n], l in [-(N_t-1), L_t-1], is computed exactly as
@@ -241,12 +266,15 @@ apx_status apx_fbank_destroy(apx_fbank fb);
  * Section II, with the SNR constraint of Section IV.D per request) are queued by
  * apx_server_submit and served by one scheduler thread per server:
  *   - admission in arrival order while the request's device memory (input, output, workspace,
- *     and its prepared kernel on a cache miss) fits hbm_budget and fewer than max_inflight
- *     requests are on the device; idle cached kernels are evicted (least recently used) to make
- *     room; a request that could never fit is refused at submit (APX_E_NOMEM);
- *   - every admitted request is launched at once on one of n_streams HIP streams (copy in,
- *     per-call calibration and block kernel through apx_run_auto, copy out), so requests that
- *     arrive while others run overlap with them on the device;
+ *     its share of a launch table, and its prepared kernel on a cache miss, sized by a dry run
+ *     of the preparation, with any twiddle tables it adds to the context) fits hbm_budget and
+ *     fewer than max_inflight requests are on the device; idle cached kernels are evicted
+ *     (least recently used) to make room; a request that could never fit is refused at submit
+ *     (APX_E_NOMEM);
+ *   - continuous batching: the requests admitted together that share a prepared kernel run as
+ *     ONE multi-signal launch of its block core (as apx_many_run) after their copies in and
+ *     their per-request calibrations, on one of n_streams HIP streams, then their copies out;
+ *     batches admitted while others run overlap with them on the device;
  *   - prepared kernels stay resident, keyed by (kernel_key, N, op, W_block, mode).
  * Each request is computed exactly as apx_run_auto (APX_AUTO_SNR, calibration on its own block
  * 0) or apx_run (fixed modes) would compute it alone; the mix changes only timing.
@@ -289,6 +317,7 @@ typedef struct {
     int64_t peak_bytes;     /* largest budgeted device memory in use */
     int64_t reserved_bytes; /* device memory held by the server's allocator */
     int32_t cached_kernels, pad;
+    int64_t launches;       /* block-kernel launches: one per batch of requests sharing a kernel */
 } apx_server_counters;
 
 typedef struct apx_server_s* apx_server;

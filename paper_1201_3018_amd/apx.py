@@ -35,7 +35,7 @@ EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "ap
            "apx_fbank_create", "apx_fbank_run", "apx_fbank_describe", "apx_fbank_destroy", "apx_workspace_bytes",
            "apx_run_auto", "apx_server_create", "apx_server_submit", "apx_server_poll", "apx_server_drain",
            "apx_server_stats", "apx_server_destroy", "apx_server_now", "apx_fit_marginal", "apx_status_str",
-           "apx_last_error")
+           "apx_last_error", "apx_many_create", "apx_many_run", "apx_many_describe", "apx_many_destroy")
 
 
 class apx_params(ctypes.Structure):
@@ -74,7 +74,7 @@ class apx_completion(ctypes.Structure):
 class apx_server_counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "rejected", "kernel_hits",
                                               "kernel_misses", "evictions", "peak_bytes", "reserved_bytes")] + \
-               [("cached_kernels", ctypes.c_int32), ("pad", ctypes.c_int32)]
+               [("cached_kernels", ctypes.c_int32), ("pad", ctypes.c_int32), ("launches", ctypes.c_int64)]
 
 
 class ApxError(RuntimeError):
@@ -128,6 +128,10 @@ def lib() -> ctypes.CDLL:
         L.apx_server_now.argtypes = []
         L.apx_server_now.restype = dp
         L.apx_fit_marginal.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
+        L.apx_many_create.argtypes = [vp, vp, i32, pvp, pi64, pvp, pvp, vp, pvp]
+        L.apx_many_run.argtypes = [vp, vp, vp]
+        L.apx_many_describe.argtypes = [vp, ctypes.c_char_p, i32]
+        L.apx_many_destroy.argtypes = [vp]
         L.apx_status_str.argtypes = [ctypes.c_int]
         L.apx_status_str.restype = ctypes.c_char_p
         L.apx_last_error.restype = ctypes.c_char_p
@@ -300,6 +304,35 @@ def apx_xcorr_argmax_batch(ctx, refs, tmpls, prm: apx_params, lag_out, val_out, 
                                         _dev_ptr(val_out, "float32"), _stream(stream)))
 
 
+def apx_many_create(ctx, kern, signals, outs, infos=None, stream=None):
+    """signals / outs / infos: lists of device tensors (infos entries may be None)."""
+    n = len(signals)
+    vp = ctypes.c_void_p
+    sp = (vp * n)(*[_dev_ptr(x, "float32") for x in signals])
+    op = (vp * n)(*[_dev_ptr(x, "float32") for x in outs])
+    Ls = (ctypes.c_int64 * n)(*[int(x.numel()) for x in signals])
+    ip = None
+    if infos is not None:
+        ip = (vp * n)(*[None if x is None else x.data_ptr() for x in infos])
+    h = vp()
+    _check(lib().apx_many_create(ctx, kern, n, sp, Ls, op, ip, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def apx_many_run(ctx, many, stream=None):
+    _check(lib().apx_many_run(ctx, many, _stream(stream)))
+
+
+def apx_many_describe(many) -> str:
+    buf = ctypes.create_string_buffer(1024)
+    _check(lib().apx_many_describe(many, buf, 1024))
+    return buf.value.decode()
+
+
+def apx_many_destroy(many):
+    _check(lib().apx_many_destroy(many))
+
+
 def apx_fbank_create(ctx, h, prec: int = APX_FB_F16X3, stream=None):
     """h: (F, N) contiguous FP32 device tensor."""
     if h.dim() != 2:
@@ -399,6 +432,43 @@ class Kernel:
     def close(self):
         if self.h:
             apx_kernel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Many:
+    """Many signals through one prepared kernel in one launch (apx_many_*).  The signal and
+    output tensors are kept referenced for the handle's lifetime."""
+
+    def __init__(self, kernel: "Kernel", signals, outs=None, info: bool = False, stream=None):
+        import torch
+        self.ctx = kernel.ctx
+        self.kernel = kernel
+        self.signals = list(signals)
+        if outs is None:
+            outs = [torch.empty(x.numel() + kernel.N - 1, dtype=torch.float32, device=x.device) for x in self.signals]
+        self.outs = list(outs)
+        self.infos = None
+        if info:
+            self.infos = [torch.empty(kernel.geometry(x.numel())[2] * BLOCK_INFO_DTYPE.itemsize, dtype=torch.uint8,
+                                      device=x.device) for x in self.signals]
+        self.h = apx_many_create(self.ctx.h, kernel.h, self.signals, self.outs, self.infos, stream)
+
+    def run(self, stream=None):
+        apx_many_run(self.ctx.h, self.h, stream)
+        return self.outs
+
+    def describe(self) -> str:
+        return apx_many_describe(self.h)
+
+    def close(self):
+        if self.h:
+            apx_many_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -24,14 +24,18 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in sources():
+    jobs = []
+    for src in sources():  # every source compiles at once (each is one compiler process)
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
         cmd = [HIPCC] + FLAGS + (["-x", "hip"] if src.endswith(".hip") else []) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        jobs.append((subprocess.Popen(cmd), cmd, obj))
+    objs = []
+    for proc, cmd, obj in jobs:
+        if proc.wait() != 0:
+            raise subprocess.CalledProcessError(proc.returncode, cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs

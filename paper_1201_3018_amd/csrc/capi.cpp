@@ -64,6 +64,11 @@ namespace {
 
 template <typename T>
 apx_status dalloc(apx_kernel k, T** p, size_t n) {
+    if (k->plan_only) {
+        k->dev_bytes += std::max<size_t>(n, 1) * sizeof(T);
+        *p = nullptr;
+        return APX_OK;
+    }
     if (k->pool) {
         const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) / 256 * 256;
         if (k->pool_off + bytes > k->pool_cap) return fail(APX_E_NOMEM, "pair buffer pool exhausted");
@@ -164,6 +169,7 @@ apx_status get_table(apx_ctx c, int F, double2** d, float2** f) {
             return fail(APX_E_DEVICE, "twiddle table of %d points: %s", F, hipGetErrorString(e));
         }
         it = c->tables.emplace(F, std::make_pair(dd, ff)).first;
+        c->table_bytes += (size_t)n * (sizeof(double2) + sizeof(float2));
     }
     if (d) *d = it->second.first;
     if (f) *f = it->second.second;
@@ -209,6 +215,7 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
     a.W = k->W;
     a.mode = k->params.mode;
     a.P = P;
+    a.nitems = P + (k->core == APX_CORE_FFT ? 1 : 0);  // the FFT cores add block 0's prefix item
     a.cand_mask = k->cand_mask;
     for (int m = 0; m < 4; ++m) {
         a.S[m] = k->S[m];
@@ -242,6 +249,10 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
             if (m == 0) a.wtwf = f;
             else a.wtw[m] = d;
             a.coef[m] = k->coef[m];
+            if (k->group) {
+                get_table(k->ctx, group_sub_points(k->wM[1], k->wM[2], k->wM[3], k->wM[0], m), &d, &f);
+                a.gsub[m] = (m == 0) ? (const void*)f : (const void*)d;
+            }
         }
         a.coef32 = k->coef32;
     }
@@ -557,10 +568,17 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         for (int m = MD_SYM; m <= MD_ASYM3 && r == APX_OK; ++m)
             if (k->use[m]) r = dalloc(k, &k->coef[m], 2 * (size_t)k->wM[m]);
         if (r == APX_OK && k->use[0]) r = dalloc(k, &k->coef32, 2 * (size_t)k->wM[0]);
+        auto table = [&](int F) -> apx_status {
+            if (!k->plan_only) return get_table(ctx, F, nullptr, nullptr);
+            if (!ctx->tables.count(F) && std::find(k->plan_tables.begin(), k->plan_tables.end(), F) == k->plan_tables.end())
+                k->plan_tables.push_back(F);
+            return APX_OK;
+        };
         for (int m = 0; m < 4 && r == APX_OK; ++m) {
             if (!k->use[m]) continue;
-            r = get_table(ctx, k->wM[m], nullptr, nullptr);
-            if (r == APX_OK) r = get_table(ctx, 2 * k->wM[m], nullptr, nullptr);
+            r = table(k->wM[m]);
+            if (r == APX_OK) r = table(2 * k->wM[m]);
+            if (r == APX_OK && k->group) r = table(group_sub_points(k->wM[1], k->wM[2], k->wM[3], k->wM[0], m));
         }
     }
     if (r == APX_OK && core == APX_CORE_INT8) r = dalloc(k, &k->i8frag, (size_t)2 * i8_kpad(N_odd) * 64 * 4);
@@ -568,6 +586,7 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         free_kernel(k);
         return r;
     }
+    if (k->plan_only) return APX_OK;
     hipError_t e = launch_prepare_kernel(k_in, N, N_odd, op == APX_XCORR, k->ks, k->kf, k->kd, k->kf_pad + 8,
                                          k->kq[MD_SYM], k->kq[MD_ASYM2], k->kq[MD_ASYM3], k->K, k->R,
                                          k->kq_pad[MD_SYM] + 8, k->kq_pad[MD_ASYM2] + 8, st);
@@ -715,6 +734,73 @@ apx_status apx_fit_marginal(apx_ctx ctx, const float* x, int64_t n, int32_t mode
     return APX_OK;
 }
 
+}  // extern "C"
+
+namespace apx {
+
+apx_status set_error(apx_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+apx_status run_args(apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info, RunArgs* a) {
+    if (!k || !s || !out || !a) return fail(APX_E_INVALID, "null argument");
+    if (!aligned8(s)) return fail(APX_E_INVALID, "s_in must be 8-byte aligned");
+    if (L < k->N) return fail(APX_E_INVALID, "input length L = %lld shorter than the kernel N = %d", (long long)L, k->N);
+    int64_t P = 0;
+    apx_status r = geometry(L, k->N, k->W_block, nullptr, nullptr, &P);
+    if (r != APX_OK) return r;
+    *a = make_args(k, s, L, out, nullptr, info, P);
+    return APX_OK;
+}
+
+// Workspace layout: 64 per-workgroup partial pairs, the block's ||s||_inf and sigma, the offset.
+apx_status calib_on_device(apx_kernel k, const RunArgs& a, int32_t block, void* workspace, const double** off,
+                           hipStream_t st) {
+    constexpr int nparts = 64, Q = 8;
+    static_assert((2 * nparts + 3) * sizeof(double) <= 2048, "calibration workspace");
+    if (block < 0 || block >= a.P) return fail(APX_E_INVALID, "calibration block %d outside [0, %lld)", block, (long long)a.P);
+    double* part = (double*)workspace;
+    double* o = part + 2 * nparts + 2;
+    HIPCHK(launch_calib(a, block, Q, part, nparts, st));
+    HIPCHK(launch_calib_finish(part, nparts, k->ks, Q, o, k->params.sigma_k > 0.0 ? k->params.sigma_k : 0.0, st));
+    *off = o;
+    return APX_OK;
+}
+
+apx_status launch_many(apx_kernel k, const RunArgs& first, const RunArgs* args, const int32_t* item_sig, int64_t nitems,
+                       hipStream_t st) {
+    if (nitems < 1 || nitems > (int64_t)0x7fffffff) return fail(APX_E_UNSUPPORTED, "%lld work items", (long long)nitems);
+    RunArgs a = first;
+    a.many = args;
+    a.many_sig = item_sig;
+    a.nitems = nitems;
+    a.item0 = 0;
+    return launch_block_kernel(k, a, st);
+}
+
+apx_status kernel_plan_bytes(apx_ctx ctx, int32_t N, int32_t op, int32_t W_block, const apx_params* p, size_t* bytes) {
+    if (!bytes) return fail(APX_E_INVALID, "null argument");
+    apx_kernel_s tmp;
+    tmp.plan_only = true;
+    static const float dummy = 0.0f;  // never read: a plan reads no taps
+    apx_status r = init_kernel(&tmp, ctx, &dummy, N, op, W_block, p, nullptr, 0);
+    if (r != APX_OK) return r;
+    size_t tb = 0;
+    for (int F : tmp.plan_tables) tb += (size_t)(F + pass_table_len(F)) * (sizeof(double2) + sizeof(float2));
+    *bytes = tmp.dev_bytes + tb;
+    return APX_OK;
+}
+
+}  // namespace apx
+
+extern "C" {
+
 apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info,
                         double snr_min_db, int32_t calib_block, void* workspace, void* stream) {
     if (!ctx || !k || !s || !out || !workspace) return fail(APX_E_INVALID, "null argument");
@@ -729,12 +815,10 @@ apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, fl
         return fail(APX_E_INVALID, "calibration block %d outside [0, %lld)", calib_block, (long long)P);
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
-    const int nparts = 64, Q = 8;
-    double* part = (double*)workspace;
-    double* off = part + 2 * nparts + 2;
     RunArgs a = make_args(k, s, L, out, nullptr, info, P);
-    HIPCHK(launch_calib(a, calib_block, Q, part, nparts, st));
-    HIPCHK(launch_calib_finish(part, nparts, k->ks, Q, off, k->params.sigma_k > 0.0 ? k->params.sigma_k : 0.0, st));
+    const double* off = nullptr;
+    r = calib_on_device(k, a, calib_block, workspace, &off, st);
+    if (r != APX_OK) return r;
     a.calib_dev = off;
     a.snr_min_db = snr_min_db;
     return launch_block_kernel(k, a, st);
@@ -787,6 +871,110 @@ apx_status apx_conv(apx_ctx ctx, const float* s, int64_t L, const float* k, int3
 apx_status apx_xcorr(apx_ctx ctx, const float* s, int64_t L, const float* k, int32_t N, int32_t W_block,
                      const apx_params* params, float* out, apx_block_info* info, void* stream) {
     return oneshot(ctx, APX_XCORR, s, L, k, N, W_block, params, out, info, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Many signals, one kernel: one launch over every (signal, block) item
+// ------------------------------------------------------------------------------------------
+
+struct apx_many_s {
+    apx_ctx ctx = nullptr;
+    apx_kernel kern = nullptr;
+    int32_t n = 0;
+    int64_t nitems = 0;
+    RunArgs* args = nullptr;      // device, one per signal
+    int32_t* item_sig = nullptr;  // device, the signal of each launch item
+    RunArgs first;                // host copy of signal 0's arguments: the launch's own
+};
+
+namespace {
+
+void many_free(apx_many m) {
+    if (!m) return;
+    if (m->args) (void)hipFree(m->args);
+    if (m->item_sig) (void)hipFree(m->item_sig);
+    delete m;
+}
+
+}  // namespace
+
+extern "C" {
+
+apx_status apx_many_create(apx_ctx ctx, apx_kernel k, int32_t n, const float* const* s, const int64_t* L,
+                           float* const* r_out, apx_block_info* const* info, void* stream, apx_many* out) {
+    if (!out) return fail(APX_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (!ctx || !k || !s || !L || !r_out) return fail(APX_E_INVALID, "null argument");
+    if (n < 1) return fail(APX_E_INVALID, "n = %d signals", n);
+    if (k->ctx != ctx) return fail(APX_E_INVALID, "the kernel belongs to another context");
+    std::vector<RunArgs> ha((size_t)n);
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!s[i] || !r_out[i]) return fail(APX_E_INVALID, "signal %d: null pointer", i);
+        if (!aligned8(s[i])) return fail(APX_E_INVALID, "signal %d: s must be 8-byte aligned", i);
+        if (L[i] < k->N)
+            return fail(APX_E_INVALID, "signal %d: length %lld shorter than the kernel N = %d", i, (long long)L[i], k->N);
+        int64_t P = 0;
+        apx_status r = geometry(L[i], k->N, k->W_block, nullptr, nullptr, &P);
+        if (r != APX_OK) return r;
+        ha[i] = make_args(k, s[i], L[i], r_out[i], nullptr, info ? info[i] : nullptr, P);
+        ha[i].item0 = total;
+        total += ha[i].nitems;
+        if (total > (int64_t)0x7fffffff) return fail(APX_E_UNSUPPORTED, "more than 2^31 - 1 work items");
+    }
+    std::vector<int32_t> hi((size_t)total);
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t j = ha[i].item0; j < ha[i].item0 + ha[i].nitems; ++j) hi[(size_t)j] = i;
+    apx_many m = new (std::nothrow) apx_many_s;
+    if (!m) return fail(APX_E_NOMEM, "host allocation failed");
+    m->ctx = ctx;
+    m->kern = k;
+    m->n = n;
+    m->nitems = total;
+    m->first = ha[0];
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&m->args, ha.size() * sizeof(RunArgs));
+    if (e == hipSuccess) e = hipMalloc((void**)&m->item_sig, hi.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpyAsync(m->args, ha.data(), ha.size() * sizeof(RunArgs), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(m->item_sig, hi.data(), hi.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        many_free(m);
+        return fail(e == hipErrorOutOfMemory ? APX_E_NOMEM : APX_E_DEVICE, "signal table: %s", hipGetErrorString(e));
+    }
+    *out = m;
+    return APX_OK;
+}
+
+apx_status apx_many_run(apx_ctx ctx, apx_many m, void* stream) {
+    if (!ctx || !m) return fail(APX_E_INVALID, "null argument");
+    if (ctx != m->ctx) return fail(APX_E_INVALID, "the handle belongs to another context");
+    HIPCHK(hipSetDevice(ctx->device));
+    RunArgs a = m->first;
+    a.many = m->args;
+    a.many_sig = m->item_sig;
+    a.nitems = m->nitems;
+    a.item0 = 0;
+    return launch_block_kernel(m->kern, a, (hipStream_t)stream);
+}
+
+apx_status apx_many_describe(apx_many m, char* buf, int32_t size) {
+    if (!m || !buf || size < 1) return fail(APX_E_INVALID, "null argument");
+    char kd[512];
+    apx_kernel_describe(m->kern, kd, sizeof kd);
+    snprintf(buf, size, "signals=%d items=%lld launch: %s", m->n, (long long)m->nitems, kd);
+    return APX_OK;
+}
+
+apx_status apx_many_destroy(apx_many m) {
+    if (!m) return APX_OK;
+    (void)hipSetDevice(m->ctx->device);
+    many_free(m);
+    return APX_OK;
 }
 
 }  // extern "C"

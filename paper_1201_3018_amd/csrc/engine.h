@@ -38,8 +38,9 @@ struct apx_ctx_s {
     double2* twd = nullptr;
     float2* twf = nullptr;
     int max_lds = 65536;
-    // W_F^t tables (t < F) of any length F, built on first use
+    // W_F^t tables (t < F) of any length F, built on first use, and their device bytes
     std::map<int, std::pair<double2*, float2*>> tables;
+    size_t table_bytes = 0;
 };
 
 struct apx_kernel_s {
@@ -83,5 +84,29 @@ struct apx_kernel_s {
     // device buffers carved from a caller-owned pool instead of hipMalloc (batched pairs)
     char* pool = nullptr;
     size_t pool_off = 0, pool_cap = 0;
+    // plan only: count the device bytes (dev_bytes, and the context tables it would add in
+    // plan_tables) without allocating or launching anything
+    bool plan_only = false;
+    std::vector<int> plan_tables;
 };
+
+namespace apx {
+// Internal entry points used by the serving engine (capi.cpp).
+// Arguments of one run of k on s (device, L samples), with the checks of apx_run.
+apx_status run_args(apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info, RunArgs* a);
+// The per-call calibration of apx_run_auto on block `block` of a's signal, enqueued on st;
+// workspace: apx_workspace_bytes() device bytes; *off: device address of the offset.
+apx_status calib_on_device(apx_kernel k, const RunArgs& a, int32_t block, void* workspace, const double** off,
+                           hipStream_t st);
+// One launch of k's block core over every item of the signals whose arguments (item0 set) sit at
+// args (device, n entries), item_sig (device, nitems entries) giving each item's signal.
+apx_status launch_many(apx_kernel k, const RunArgs& first, const RunArgs* args, const int32_t* item_sig,
+                       int64_t nitems, hipStream_t st);
+// Device bytes a kernel prepared with these arguments would hold, plus the context tables its
+// preparation would add.
+apx_status kernel_plan_bytes(apx_ctx ctx, int32_t N, int32_t op, int32_t W_block, const apx_params* p,
+                             size_t* bytes);
+// Record a failure message for apx_last_error and return st.
+apx_status set_error(apx_status st, const char* fmt, ...);
+}  // namespace apx
 

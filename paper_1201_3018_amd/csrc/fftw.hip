@@ -15,6 +15,7 @@
 
 #include "fft.h"
 #include "internal.h"
+#include "items.h"
 
 namespace apx {
 
@@ -138,8 +139,7 @@ __device__ __forceinline__ int lane_id_fresh() {
 }
 
 // Complex FFT of M points by one wave: lane l holds v[r] = z[l + 64 r] on entry and
-// v[t] = Z[l + 64 t] on exit.  It passes WAVE_FFT_BARRIERS workgroup barriers (a wave of a
-// larger workgroup that has no transform to run passes the same number).  Passes: radix E (= M/64, registers only), radix 8, radix 8.
+// v[t] = Z[l + 64 t] on exit (one-wave workgroups: its barriers wait on no other wave).  Passes: radix E (= M/64, registers only), radix 8, radix 8.
 // The two exchanges use the wave's LDS slice in a padded layout, point i at i + floor(i/E)
 // (rows of E points padded by one: the strided writes of the first pass spread over the
 // banks); every address below is that mapping in closed form.
@@ -223,13 +223,6 @@ __device__ __forceinline__ void wave_fft(cx<T>* v, cx<T>* lds, const typename tw
         }
     }
     __syncthreads();
-}
-
-constexpr int WAVE_FFT_BARRIERS = 4;
-
-__device__ __forceinline__ void wave_fft_idle() {
-#pragma unroll
-    for (int i = 0; i < WAVE_FFT_BARRIERS; ++i) __syncthreads();
 }
 
 // Real-signal spectral step: V[k] = alpha_k Z[k] + beta_k conj(Z[M-k]) with alpha, beta built
@@ -646,8 +639,8 @@ constexpr size_t wave_lds_bytes(size_t esz) {
 
 // MASK: bit m set = the packing mode m (MD_*) is compiled in; a block whose chosen mode is not
 // compiled in cannot occur (the host launches the instance that holds every mode it can choose).
-template <int MS, int MA2, int MA3, int MF, int MASK, bool FIELDS>
-__global__ void __launch_bounds__(64) k_fftw(RunArgs a) {
+template <int MS, int MA2, int MA3, int MF, int MASK, bool FIELDS, bool MANY>
+__global__ void __launch_bounds__(64) k_fftw(RunArgs a0) {
     constexpr size_t B1 = ((MASK >> MD_SYM) & 1) ? wave_lds_bytes<MS>(8) : 0;
     constexpr size_t B2 = ((MASK >> MD_ASYM2) & 1) ? wave_lds_bytes<MA2>(8) : 0;
     constexpr size_t B3 = ((MASK >> MD_ASYM3) & 1) ? wave_lds_bytes<MA3>(8) : 0;
@@ -661,9 +654,10 @@ __global__ void __launch_bounds__(64) k_fftw(RunArgs a) {
     // body live across iterations, which spills)
     // consecutive blocks share N + 1 samples: give consecutive blocks to workgroups of one XCD
     // (workgroups go to the 8 XCDs in turn), so that the shared samples meet in one L2
-    const int64_t nblk = a.P + 1, q8 = nblk / 8, r8 = nblk % 8, x8 = blockIdx.x % 8;
-    const int64_t item = x8 * q8 + (x8 < r8 ? x8 : r8) + blockIdx.x / 8;
+    const int64_t nblk = a0.nitems, q8 = nblk / 8, r8 = nblk % 8, x8 = blockIdx.x % 8;
+    int64_t item = x8 * q8 + (x8 < r8 ? x8 : r8) + blockIdx.x / 8;
     if (blockIdx.x >= nblk) return;
+    const RunArgs& a = item_args<MANY>(a0, item);
     {
         const WItem it = wave_make_item(a, item);
         const WStats st = wave_load_window(a, it, reinterpret_cast<float*>(lds) + 1);
@@ -724,22 +718,26 @@ template <int A, int B, int C, int D>
 static hipError_t launch_set(const RunArgs& a, unsigned grid, hipStream_t st) {
     constexpr int ALL = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_ASYM3) | (1 << MD_FULL32);
     constexpr int AUTO = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_FULL32);
+#define APX_W(MASK_)                                                                                           \
+    if (a.many) hipLaunchKernelGGL((k_fftw<A, B, C, D, MASK_, false, true>), dim3(grid), dim3(64), 0, st, a);  \
+    else hipLaunchKernelGGL((k_fftw<A, B, C, D, MASK_, false, false>), dim3(grid), dim3(64), 0, st, a);
     if (a.fields) {
-        hipLaunchKernelGGL((k_fftw<A, B, C, D, ALL, true>), dim3(grid), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_fftw<A, B, C, D, ALL, true, false>), dim3(grid), dim3(64), 0, st, a);
     } else {
         switch (a.mode) {
-            case MD_SYM: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_SYM, false>), dim3(grid), dim3(64), 0, st, a); break;
-            case MD_ASYM2: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_ASYM2, false>), dim3(grid), dim3(64), 0, st, a); break;
-            case MD_ASYM3: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_ASYM3, false>), dim3(grid), dim3(64), 0, st, a); break;
-            case MD_FULL32: hipLaunchKernelGGL((k_fftw<A, B, C, D, 1 << MD_FULL32, false>), dim3(grid), dim3(64), 0, st, a); break;
-            default: hipLaunchKernelGGL((k_fftw<A, B, C, D, AUTO, false>), dim3(grid), dim3(64), 0, st, a); break;
+            case MD_SYM: APX_W(1 << MD_SYM) break;
+            case MD_ASYM2: APX_W(1 << MD_ASYM2) break;
+            case MD_ASYM3: APX_W(1 << MD_ASYM3) break;
+            case MD_FULL32: APX_W(1 << MD_FULL32) break;
+            default: APX_W(AUTO) break;
         }
     }
+#undef APX_W
     return hipGetLastError();
 }
 
 hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st) {
-    const unsigned grid = (unsigned)(a.P + 1);
+    const unsigned grid = (unsigned)a.nitems;
 #define APX_LAUNCH(a_, b_, c_, d_) \
     if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return launch_set<a_, b_, c_, d_>(a, grid, st);
     APX_WAVE_SETS(APX_LAUNCH)
@@ -749,31 +747,214 @@ hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipSt
 
 
 // ------------------------------------------------------------------------------------------
-// Group-of-waves FFT core: one workgroup of NW waves per block.  The M = 512 R point transform
-// is split by decimation in time into R transforms of 512 points, one per wave in registers
-// (wave_fft<512>), joined by a radix-R step across the waves in LDS:
-//   Z[k + 512 j] = sum_w W_R^(w j) W_M^(w k) Z_w[k],   Z_w = DFT_512(z[R n + w]);
-// the inverse splits first (decimation in frequency):
-//   x[R n + w] = IDFT_512(y_w)[n],   y_w[k] = W_M^(-w k) sum_j W_R^(-w j) V[k + 512 j].
-// The whole workgroup loads the window, takes the statistics, runs the column steps, the
-// spectral step and the unpacking; each wave's 512-point transforms use its own LDS slice.
+// Multi-wave FFT core: one workgroup of NW waves per block.  A mode's transform of M points is
+// split by decimation in time into R transforms of MS = M / R points, one per wave, each run in
+// the wave's own LDS region with exchanges ordered inside the wave only (no workgroup barrier),
+// and the R results are joined by a radix-R step:
+//   Z[k + MS j] = sum_w W_R^(w j) W_M^(w k) Z_w[k],   Z_w = DFT_MS(z[R n + w]).
+// The spectral step pairs Z[k'] with Z[M - k'].  Both lie in the columns k and MS - k of the
+// join, so the join, the spectral step and the split of the inverse (decimation in frequency)
+//   y_w[k] = W_M^(-w k) sum_j W_R^(-w j) V[k + MS j],   x[R n + w] = IDFT_MS(y_w)[n]
+// run as one pass over column pairs.  The window goes to LDS with its statistics, every wave
+// packs its own decimated points, and the words of the inverse go to LDS, from which
+// consecutive threads unpack consecutive outputs.  Blocks are spread over more waves than one
+// wave per block gives, which hides memory and LDS latency behind other waves' arithmetic.
 // ------------------------------------------------------------------------------------------
-constexpr int GM = 512;                   // points per wave transform
-constexpr int GSLICE = GM + GM / 8 + 1;   // wave_fft slice (E = 8, rows of 8 padded by one)
 
-template <int R, typename T>
-constexpr size_t group_lds_bytes() {
-    return ((size_t)(GM * R + 2) + (size_t)R * GSLICE) * 2 * sizeof(T);
+// Ordering point for an LDS exchange among the lanes of one wave: the wave's own LDS
+// operations have completed, and the fences keep the compiler from moving LDS accesses across
+// it.  No s_barrier: the other waves of the workgroup are not waited for.
+__device__ __forceinline__ void region_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Position of point i in a wave region of rows of E points.  E a power of two: the column is
+// XORed with the row (mod E), so the row writes of the first pass and the strided reads of the
+// next ones spread over the banks with no padding; otherwise each row is padded by one point.
+template <int E>
+__device__ __forceinline__ int gpos(int i) {
+    if constexpr ((E & (E - 1)) == 0) return i ^ ((i / E) & (E - 1));
+    else return i + i / E;
+}
+template <int MS>
+constexpr int greg_points() {
+    constexpr int E = MS / 64;
+    return ((E & (E - 1)) == 0) ? MS : MS + MS / E;
+}
+
+// Complex FFT of MS points by one wave in its region `reg`: lane l holds v[r] = z[l + 64 r] on
+// entry and v[t] = Z[l + 64 t] on exit.  Passes: radix E = MS/64 in registers, then two radix-8
+// passes through the region.  tw: the W_MS^t table followed by its per-pass copies (W^{8 r k} at
+// MS + (r-1) E + k, W^{r j} at MS + 7 E + (r-1) MS/8 + j), read at adjacent entries per load.
+template <typename T, int MS, bool INV>
+__device__ __forceinline__ void gsub_fft(cx<T>* v, cx<T>* reg, const typename tw_of<T>::type* tw) {
+    constexpr int E = MS / 64;
+    static_assert(E % 8 == 0, "points per lane must be a multiple of 8");
+    constexpr int NB = E / 8;
+    using TW = typename tw_of<T>::type;
+    auto twB = [&](int r, int k) { return ld_row(tw + MS + (r - 1) * E, (uint32_t)k * (uint32_t)sizeof(TW)); };
+    auto twC = [&](int r, int j) {
+        return ld_row(tw + MS + 7 * E + (r - 1) * (MS / 8), (uint32_t)j * (uint32_t)sizeof(TW));
+    };
+    dftn<T, E, INV>(v);  // pass A: output i = l E + r
+    {
+        const int l = lane_id_fresh();
+#pragma unroll
+        for (int r = 0; r < E; ++r) reg[gpos<E>(l * E + r)] = v[r];
+    }
+    region_sync();
+    // pass B: radix 8 over sub-transforms of size E; input i = j + 8E r, output 8E q + k + E r
+    {
+        const int l = lane_id_fresh();
+        cx<T> u[NB][8];
+        int q_[NB], k_[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = l + 64 * b;
+            const int q = j / E;
+            const int k = j - q * E;
+            q_[b] = q;
+            k_[b] = k;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) u[b][r] = reg[gpos<E>(j + 8 * E * r)];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) {
+                const auto w = twB(r, k);  // W_{8E}^{rk} = W_MS^{8rk}
+                u[b][r] = cmul(u[b][r], cx<T>{w.x, INV ? -w.y : w.y});
+            }
+            dft8<T, INV>(u[b]);
+        }
+        region_sync();
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) reg[gpos<E>(8 * E * q_[b] + k_[b] + E * r)] = u[b][r];
+    }
+    region_sync();
+    // pass C: radix 8 over sub-transforms of size MS/8; results stay in registers
+    {
+        const int l = lane_id_fresh();
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = l + 64 * b;
+            cx<T> x[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) x[r] = reg[gpos<E>(j + 8 * E * r)];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) {
+                const auto w = twC(r, j);
+                x[r] = cmul(x[r], cx<T>{w.x, INV ? -w.y : w.y});
+            }
+            dft8<T, INV>(x);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[b + NB * r] = x[r];
+        }
+    }
+    region_sync();  // the region is free for the caller
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftr(cx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 3) dft3<T, INV>(v[0], v[1], v[2]);
+    else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    else static_assert(R == 1, "join radix 1..4");
+}
+
+// One pass over column pairs of the R wave regions (plain layout, region w at reg + w RP):
+// join (forward radix R), spectral step V[k'] = alpha_k' Z[k'] + beta_k' conj(Z[(M - k') mod M])
+// with (alpha, beta) from the kernel's real-split table, split (inverse radix R); in place.
+// Thread u takes columns (u, MS - u); thread 0 takes the two self-paired columns 0 and MS / 2.
+template <typename T, int M, int R, int RP, int NTH>
+__device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename tw_of<T>::type* twM,
+                                                     const typename tw_of<T>::type* coef) {
+    constexpr int MS = M / R;
+    for (int u = threadIdx.x; u < MS / 2; u += NTH) {
+        const int ca = u, cb = (u == 0) ? MS / 2 : MS - u;
+        cx<T> A[R], B[R];
+#pragma unroll
+        for (int w = 0; w < R; ++w) {
+            A[w] = reg[w * RP + ca];
+            B[w] = reg[w * RP + cb];
+        }
+#pragma unroll
+        for (int w = 1; w < R; ++w) {
+            const auto ta = twM[w * ca], tb = twM[w * cb];
+            A[w] = cmul(A[w], cx<T>{ta.x, ta.y});
+            B[w] = cmul(B[w], cx<T>{tb.x, tb.y});
+        }
+        dftr<T, R, false>(A);  // A[j] = Z[ca + MS j]
+        dftr<T, R, false>(B);  // B[j] = Z[cb + MS j]
+        __builtin_amdgcn_sched_barrier(0);
+        cx<T> VA[R], VB[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            // partners: (M - ca - MS j) mod M and (M - cb - MS j) mod M
+            cx<T> pa, pb;
+            if (u == 0) {
+                pa = A[(R - j) % R];    // column 0 pairs with itself, row (R - j) mod R
+                pb = B[R - 1 - j];      // column MS/2 pairs with itself, row R - 1 - j
+            } else {
+                pa = B[R - 1 - j];
+                pb = A[R - 1 - j];
+            }
+            const int ka = ca + MS * j, kb = cb + MS * j;
+            const auto aa = coef[2 * ka], ba = coef[2 * ka + 1];
+            const auto ab = coef[2 * kb], bb = coef[2 * kb + 1];
+            VA[j] = cmul(A[j], cx<T>{aa.x, aa.y}) + cmul(conj(pa), cx<T>{ba.x, ba.y});
+            VB[j] = cmul(B[j], cx<T>{ab.x, ab.y}) + cmul(conj(pb), cx<T>{bb.x, bb.y});
+            __builtin_amdgcn_sched_barrier(0);  // one row's coefficients in flight at a time
+        }
+        dftr<T, R, true>(VA);  // VA[w] = sum_j W_R^(-w j) V[ca + MS j]
+        dftr<T, R, true>(VB);
+#pragma unroll
+        for (int w = 1; w < R; ++w) {
+            const auto ta = twM[w * ca], tb = twM[w * cb];
+            VA[w] = cmul(VA[w], cx<T>{ta.x, -ta.y});
+            VB[w] = cmul(VB[w], cx<T>{tb.x, -tb.y});
+        }
+#pragma unroll
+        for (int w = 0; w < R; ++w) {
+            reg[w * RP + ca] = VA[w];
+            reg[w * RP + cb] = VB[w];
+        }
+    }
+}
+
+// Window of the item into LDS (FP32, zero past nvalid, zero sentinels at -1 and W_block) with
+// its statistics from the same loads; per-wave partials are combined through `red` in the same
+// order by every thread.
 template <int NTH>
 __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WItem& it, float* win, double* red) {
     double m = 0.0, q = 0.0;
     int nf = 0;
-    const float* p = a.s + it.start;
-    constexpr int CH = 8;
+    const float* p = a.s + it.start;  // start is even and s_in 8-byte aligned (checked on the host)
+    constexpr int CH = 4;             // float2 loads in flight per thread
+    auto take = [&](float x0, float x1) {
+        const bool f0 = isfinite(x0), f1 = isfinite(x1);
+        if (!(f0 && f1)) nf = 1;
+        const double d0 = (double)(f0 ? x0 : 0.0f), d1 = (double)(f1 ? x1 : 0.0f);
+        m = fmax(m, fmax(fabs(d0), fabs(d1)));
+        q += d0 * d0 + d1 * d1;
+    };
     for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
         float2 f[CH];
+        const int end = base + 2 * NTH * CH;
+        if (end <= it.nwin && end <= it.nvalid && end <= a.W_block) {  // uniform: no per-sample bounds
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                f[c] = *reinterpret_cast<const float2*>(p + base + 2 * ((int)threadIdx.x + NTH * c));
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + 2 * ((int)threadIdx.x + NTH * c);
+                take(f[c].x, f[c].y);
+                *reinterpret_cast<float2*>(win + i) = f[c];
+            }
+            continue;
+        }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * ((int)threadIdx.x + NTH * c);
@@ -785,13 +966,9 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
         for (int c = 0; c < CH; ++c) {
             const int i = base + 2 * ((int)threadIdx.x + NTH * c);
             if (i < a.W_block) {
-                const float x0 = f[c].x, x1 = f[c].y;
-                if (!isfinite(x0) || !isfinite(x1)) nf = 1;
-                const double d0 = isfinite(x0) ? (double)x0 : 0.0, d1 = isfinite(x1) ? (double)x1 : 0.0;
-                m = fmax(m, fmax(fabs(d0), fabs(d1)));
-                q += d0 * d0 + d1 * d1;
-                win[i] = (i < it.nvalid) ? x0 : 0.0f;
-                win[i + 1] = (i + 1 < it.nvalid) ? x1 : 0.0f;
+                take(f[c].x, f[c].y);
+                *reinterpret_cast<float2*>(win + i) =
+                    make_float2(i < it.nvalid ? f[c].x : 0.0f, i + 1 < it.nvalid ? f[c].y : 0.0f);
             }
         }
     }
@@ -814,6 +991,7 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
     r.smax = 0.0;
     r.sumsq = 0.0;
     r.nonfinite = 0;
+#pragma unroll
     for (int i = 0; i < NW; ++i) {  // same order in every thread
         r.smax = fmax(r.smax, red[i]);
         r.sumsq += red[NW + i];
@@ -822,23 +1000,35 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
     return r;
 }
 
-template <int MODE, int R, int NW, bool FIELDS>
-__device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, const WChoice& c, char* lds_raw) {
+// Geometry of one mode in a group set: M points split over R waves of MS points.
+template <int M, int R>
+struct GMode {
+    static constexpr int MS = M / R;
+    static constexpr int RP = greg_points<MS>();  // points per wave region
+    static_assert(M % R == 0 && MS % 512 == 0, "wave transforms of a multiple of 512 points");
+};
+
+template <int MODE, int M, int R, int NW, bool FIELDS>
+__device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, const WChoice& c, char* lds_raw,
+                                           const float* win) {
     using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
-    constexpr int M = GM * R;
+    using TW = typename tw_of<T>::type;
+    using G = GMode<M, R>;
+    constexpr int MS = G::MS, E = MS / 64, RP = G::RP;
     constexpr int NTH = 64 * NW;
     const int N = a.N;
-    cx<T>* Z = reinterpret_cast<cx<T>*>(lds_raw);              // M + 1 points
-    cx<T>* slice0 = Z + (M + 2);                                // R slices
-    const float* win = reinterpret_cast<const float*>(lds_raw) + 1;  // aliases Z until the join
-    const typename tw_of<T>::type* tw;  // W_M^t, t < M
-    const typename tw_of<T>::type* coef;
+    cx<T>* reg = reinterpret_cast<cx<T>*>(lds_raw);  // R regions of RP points (alias the window)
+    const TW* twM;   // W_M^t, t < M
+    const TW* tws;   // W_MS^t with per-pass copies
+    const TW* coef;  // real-split coefficients of the kernel spectrum, (alpha_k, beta_k), k < M
     if constexpr (MODE == MD_FULL32) {
-        tw = a.wtwf;
+        twM = a.wtwf;
+        tws = reinterpret_cast<const TW*>(a.gsub[0]);
         coef = a.coef32;
     } else {
-        tw = (MODE == MD_SYM) ? a.wtw[1] : (MODE == MD_ASYM2 ? a.wtw[2] : a.wtw[3]);
-        coef = (MODE == MD_SYM) ? a.coef[1] : (MODE == MD_ASYM2 ? a.coef[2] : a.coef[3]);
+        twM = a.wtw[MODE];
+        tws = reinterpret_cast<const TW*>(a.gsub[MODE]);
+        coef = a.coef[MODE];
     }
     constexpr int MM = (MODE == MD_ASYM3) ? 3 : 2;
     const bool prefix = it.j_lo == 0;
@@ -853,25 +1043,25 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
     auto sqd = [&](int i) -> double { return rint(c.cs * (double)rd(i)); };
     const int wv = threadIdx.x >> 6;
     const bool active = wv < R;
-    // ---- pack: wave w holds z[R n + w], n = l + 64 r (eq. 4 / eq. 7 on words 2m, 2m + 1)
-    cx<T> v[8];
+    // ---- pack: wave w holds the decimated points z[R n + w], n = l + 64 r (eq. 4 / eq. 7)
+    cx<T> v[E];
     if (active) {
-        const int l = lane_id_fresh() & 63;
+        const int l = lane_id_fresh();
         const double eps = (MODE == MD_FULL32) ? 0.0 : 1.0 / (2.0 * (double)c.R);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int m = R * (l + 64 * r) + wv;  // complex point = words 2m, 2m + 1
+        for (int r = 0; r < E; ++r) {
+            const int p = R * (l + 64 * r) + wv;  // complex point = words 2p, 2p + 1
             if constexpr (MODE == MD_FULL32) {
-                v[r].x = rd(2 * m);
-                v[r].y = rd(2 * m + 1);
+                v[r].x = rd(2 * p);
+                v[r].y = rd(2 * p + 1);
             } else if constexpr (MODE == MD_SYM) {
-                v[r].x = sqd(4 * m) + eps * sqd(4 * m + 1);
-                v[r].y = sqd(4 * m + 2) + eps * sqd(4 * m + 3);
+                v[r].x = sqd(4 * p) + eps * sqd(4 * p + 1);
+                v[r].y = sqd(4 * p + 2) + eps * sqd(4 * p + 3);
             } else {
                 double w2[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int wd = 2 * m + h;
+                    const int wd = 2 * p + h;
                     double acc = 0.0, e = 1.0;
 #pragma unroll
                     for (int q = 0; q < MM; ++q) {
@@ -883,89 +1073,35 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
                 v[r].x = w2[0];
                 v[r].y = w2[1];
             }
+            if (r & 1) __builtin_amdgcn_sched_barrier(0);  // bound the window reads in flight
         }
     }
-    __syncthreads();  // the window (which may overlap the slices) is dead from here on
-    // ---- forward transforms of the decimated sequences
-    if (active) wave_fft<T, GM, false, R>(v, slice0 + wv * GSLICE, tw);
-    else wave_fft_idle();
-    // ---- join: Z[k + 512 j] = DFT_R over w of W_M^(w k) Z_w[k]
+    __syncthreads();  // the window is dead from here on: the regions reuse its bytes
+    cx<T>* mine = reg + wv * RP;
     if (active) {
-        const int l = lane_id_fresh() & 63;
+        gsub_fft<T, MS, false>(v, mine, tws);
+        const int l = lane_id_fresh();
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int k = l + 64 * t;
-            cx<T> z = v[t];
-            if (wv > 0) {
-                const auto w = tw[wv * k];
-                z = cmul(z, cx<T>{w.x, w.y});
-            }
-            Z[wv * GM + k] = z;
-        }
+        for (int t = 0; t < E; ++t) mine[l + 64 * t] = v[t];  // plain layout for the join
     }
     __syncthreads();
-    if constexpr (R > 1) {
-        for (int k = threadIdx.x; k < GM; k += NTH) {
-            cx<T> col[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) col[j] = Z[j * GM + k];
-            dftn<T, R, false>(col);
-#pragma unroll
-            for (int j = 0; j < R; ++j) Z[j * GM + k] = col[j];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) Z[M] = Z[0];
+    gjoin_spectral_split<T, M, R, RP, NTH>(reg, twM, coef);
     __syncthreads();
-    // ---- spectral step on pairs (k, M - k): V[k] = alpha_k Z[k] + beta_k conj(Z[M - k])
-    for (int k = threadIdx.x; k <= M / 2; k += NTH) {
-        const cx<T> za = Z[k], zb = Z[M - k];
-        const auto a0 = coef[2 * k], b0 = coef[2 * k + 1];
-        const cx<T> va = cmul(za, cx<T>{a0.x, a0.y}) + cmul(conj(zb), cx<T>{b0.x, b0.y});
-        if (k > 0 && 2 * k < M) {
-            const auto a1 = coef[2 * (M - k)], b1 = coef[2 * (M - k) + 1];
-            Z[M - k] = cmul(zb, cx<T>{a1.x, a1.y}) + cmul(conj(za), cx<T>{b1.x, b1.y});
-        }
-        Z[k] = va;
-    }
-    __syncthreads();
-    // ---- split: y_w[k] = W_M^(-w k) IDFT_R over j of V[k + 512 j], stored at Z[w 512 + k]
-    if constexpr (R > 1) {
-        for (int k = threadIdx.x; k < GM; k += NTH) {
-            cx<T> col[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) col[j] = Z[j * GM + k];
-            dftn<T, R, true>(col);
-#pragma unroll
-            for (int w = 0; w < R; ++w) {
-                cx<T> y = col[w];
-                if (w > 0) {
-                    const auto tww = tw[w * k];
-                    y = cmul(y, cx<T>{tww.x, -tww.y});
-                }
-                Z[w * GM + k] = y;
-            }
-        }
-        __syncthreads();
-    }
-    // ---- inverse transforms; every wave has read its row before the first barrier inside
     if (active) {
-        const int l = lane_id_fresh() & 63;
+        const int l = lane_id_fresh();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = Z[wv * GM + l + 64 * r];
-        wave_fft<T, GM, true, R>(v, slice0 + wv * GSLICE, tw);
-    } else {
-        wave_fft_idle();
+        for (int r = 0; r < E; ++r) v[r] = mine[l + 64 * r];
+        gsub_fft<T, MS, true>(v, mine, tws);
     }
-    // ---- words of the cyclic convolution: point m = R n + w is (word 2m, word 2m + 1)
-    T* wd = reinterpret_cast<T*>(Z);
+    __syncthreads();  // every region is dead: the words of the cyclic convolution take their bytes
+    T* wd = reinterpret_cast<T*>(lds_raw);
     if (active) {
-        const int l = lane_id_fresh() & 63;
+        const int l = lane_id_fresh();
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int m = R * (l + 64 * t) + wv;
-            wd[2 * m] = v[t].x;
-            wd[2 * m + 1] = v[t].y;
+        for (int t = 0; t < E; ++t) {
+            const int p = R * (l + 64 * t) + wv;
+            wd[2 * p] = v[t].x;
+            wd[2 * p + 1] = v[t].y;
         }
     }
     __syncthreads();
@@ -995,7 +1131,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
             if (FIELDS) a.fields[it.o0 + s] = f;
         }
     } else {
-        // local output j = base_off + q Tit + word  <->  word = j - base_off - q Tit in [N-1, lw)
+        // local output j = base_off + q Tit + word, word in [N - 1, lw)
         const double two_r = (double)(2 * c.R);
         for (int s = threadIdx.x; s < nout; s += NTH) {
             const int jj = it.j_lo + s - base_off;  // = q Tit + word
@@ -1021,37 +1157,45 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
     }
 }
 
-template <int RS, int RA2, int RA3, int RF, int MASK>
+// A compiled group set: points M and waves R per mode (sym, asym2, asym3, fp32).
+template <int MS_, int RS_, int MA2_, int RA2_, int MA3_, int RA3_, int MF_, int RF_, int MASK>
 struct GroupShape {
-    static constexpr int r(int m) {
-        return m == MD_SYM ? RS : (m == MD_ASYM2 ? RA2 : (m == MD_ASYM3 ? RA3 : RF));
-    }
-    static constexpr int used(int m) { return ((MASK >> m) & 1) ? r(m) : 0; }
+    static constexpr bool has(int m) { return (MASK >> m) & 1; }
     static constexpr int mx(int x, int y) { return x > y ? x : y; }
-    static constexpr int NW = mx(mx(used(MD_SYM), used(MD_ASYM2)), mx(used(MD_ASYM3), used(MD_FULL32)));
-    static constexpr size_t bytes(int m) {
-        return !((MASK >> m) & 1) ? 0
-               : m == MD_FULL32   ? group_lds_bytes<RF, float>()
-               : m == MD_SYM      ? group_lds_bytes<RS, double>()
-               : m == MD_ASYM2    ? group_lds_bytes<RA2, double>()
-                                  : group_lds_bytes<RA3, double>();
-    }
     static constexpr size_t mxs(size_t x, size_t y) { return x > y ? x : y; }
-    static constexpr size_t WIN = 4 * (2 * (size_t)GM * RF + 4);  // window + sentinels (W_block <= 2 M_fp32)
-    static constexpr size_t LDS = mxs(mxs(mxs(bytes(MD_SYM), bytes(MD_ASYM2)), mxs(bytes(MD_ASYM3), bytes(MD_FULL32))), WIN);
+    static constexpr int NW = mx(mx(has(MD_SYM) ? RS_ : 1, has(MD_ASYM2) ? RA2_ : 1),
+                                 mx(has(MD_ASYM3) ? RA3_ : 1, has(MD_FULL32) ? RF_ : 1));
+    // regions of the transforms, or the words of the inverse (2 M words), per mode
+    template <int M, int R, typename T>
+    static constexpr size_t mode_bytes() {
+        return mxs((size_t)R * greg_points<M / R>() * 2 * sizeof(T), (size_t)2 * M * sizeof(T));
+    }
+    static constexpr size_t B1 = has(MD_SYM) ? mode_bytes<MS_, RS_, double>() : 0;
+    static constexpr size_t B2 = has(MD_ASYM2) ? mode_bytes<MA2_, RA2_, double>() : 0;
+    static constexpr size_t B3 = has(MD_ASYM3) ? mode_bytes<MA3_, RA3_, double>() : 0;
+    static constexpr size_t B4 = has(MD_FULL32) ? mode_bytes<MF_, RF_, float>() : 0;
+    // the window with its sentinels (W_block <= 2 MF), 16 bytes in: win[-1] sits just before it
+    static constexpr size_t WIN = 16 + 4 * (2 * (size_t)MF_ + 1);
+    static constexpr size_t LDS = mxs(mxs(mxs(B1, B2), mxs(B3, B4)), WIN);
 };
 
-template <int RS, int RA2, int RA3, int RF, int MASK, bool FIELDS>
-__global__ void __launch_bounds__((64 * GroupShape<RS, RA2, RA3, RF, MASK>::NW)) k_fftg(RunArgs a) {
-    using G = GroupShape<RS, RA2, RA3, RF, MASK>;
+template <int MS_, int RS_, int MA2_, int RA2_, int MA3_, int RA3_, int MF_, int RF_, int MASK, bool FIELDS, bool MANY>
+__global__ void __launch_bounds__((64 * GroupShape<MS_, RS_, MA2_, RA2_, MA3_, RA3_, MF_, RF_, MASK>::NW), 5)
+    k_fftg(RunArgs a0) {
+    using G = GroupShape<MS_, RS_, MA2_, RA2_, MA3_, RA3_, MF_, RF_, MASK>;
     constexpr int NW = G::NW;
     constexpr int NTH = 64 * NW;
     __shared__ __attribute__((aligned(16))) char lds[G::LDS];
     __shared__ double red[3 * NW];
-    const int64_t item = blockIdx.x;
-    if (item >= a.P + 1) return;
+    // consecutive blocks share N + 1 samples: give consecutive blocks to workgroups of one XCD
+    // (workgroups go to the 8 XCDs in turn), so that the shared samples meet in one L2
+    const int64_t nblk = a0.nitems, q8 = nblk / 8, r8 = nblk % 8, x8 = blockIdx.x % 8;
+    int64_t item = x8 * q8 + (x8 < r8 ? x8 : r8) + blockIdx.x / 8;
+    if (blockIdx.x >= nblk) return;
+    const RunArgs& a = item_args<MANY>(a0, item);
     const WItem it = wave_make_item(a, item);
-    const WStats st = group_load_window<NTH>(a, it, reinterpret_cast<float*>(lds) + 1, red);
+    float* win = reinterpret_cast<float*>(lds + 16);
+    const WStats st = group_load_window<NTH>(a, it, win, red);
     const WChoice c = wave_choose(a, st);
     if (a.info && item < a.P && threadIdx.x == 0) {
         apx_block_info b;
@@ -1076,57 +1220,72 @@ __global__ void __launch_bounds__((64 * GroupShape<RS, RA2, RA3, RF, MASK>::NW))
         return;
     }
     if constexpr ((MASK >> MD_SYM) & 1)
-        if (c.mode == MD_SYM) group_item<MD_SYM, RS, NW, FIELDS>(a, it, c, lds);
+        if (c.mode == MD_SYM) group_item<MD_SYM, MS_, RS_, NW, FIELDS>(a, it, c, lds, win);
     if constexpr ((MASK >> MD_ASYM2) & 1)
-        if (c.mode == MD_ASYM2) group_item<MD_ASYM2, RA2, NW, FIELDS>(a, it, c, lds);
+        if (c.mode == MD_ASYM2) group_item<MD_ASYM2, MA2_, RA2_, NW, FIELDS>(a, it, c, lds, win);
     if constexpr ((MASK >> MD_ASYM3) & 1)
-        if (c.mode == MD_ASYM3) group_item<MD_ASYM3, RA3, NW, FIELDS>(a, it, c, lds);
+        if (c.mode == MD_ASYM3) group_item<MD_ASYM3, MA3_, RA3_, NW, FIELDS>(a, it, c, lds, win);
     if constexpr ((MASK >> MD_FULL32) & 1)
-        if (c.mode == MD_FULL32) group_item<MD_FULL32, RF, NW, FIELDS>(a, it, c, lds);
+        if (c.mode == MD_FULL32) group_item<MD_FULL32, MF_, RF_, NW, FIELDS>(a, it, c, lds, win);
 }
 
-// Compiled group sets: complex points per mode (sym, asym2, asym3, fp32), each a multiple of 512.
-#define APX_GROUP_SETS(X)         \
-    X(1024, 1536, 1024, 2048)     \
-    X(1024, 1536, 1536, 2048)     \
-    X(512, 1024, 512, 1024)       \
-    X(512, 1024, 1024, 1024)
+// Compiled group sets: complex points and waves per mode (sym, asym2, asym3, fp32).  FP64 modes
+// use 512-point wave transforms; FP32 transforms of 1024 points per wave keep the workgroup at
+// the waves of the widest FP64 mode.
+#define APX_GROUP_SETS(X)                      \
+    X(1024, 2, 1536, 3, 1024, 2, 2048, 2)      \
+    X(1024, 2, 1536, 3, 1536, 3, 2048, 2)      \
+    X(512, 1, 1024, 2, 512, 1, 1024, 2)        \
+    X(512, 1, 1024, 2, 1024, 2, 1024, 2)
 
 bool group_supported(int ms, int ma2, int ma3, int mf) {
-#define APX_CHECK(a_, b_, c_, d_) \
+#define APX_CHECK(a_, ra_, b_, rb_, c_, rc_, d_, rd_) \
     if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return true;
     APX_GROUP_SETS(APX_CHECK)
 #undef APX_CHECK
     return false;
 }
 
-template <int A, int B, int C, int D>
+// Points of one wave transform of `mode` (index MD_*) in the group set (ms, ma2, ma3, mf).
+int group_sub_points(int ms, int ma2, int ma3, int mf, int mode) {
+#define APX_SUB(a_, ra_, b_, rb_, c_, rc_, d_, rd_)                                         \
+    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_)                                     \
+        return mode == MD_SYM ? a_ / ra_ : mode == MD_ASYM2 ? b_ / rb_ : mode == MD_ASYM3 ? c_ / rc_ : d_ / rd_;
+    APX_GROUP_SETS(APX_SUB)
+#undef APX_SUB
+    return 0;
+}
+
+template <int A, int RA, int B, int RB, int C, int RC, int D, int RD>
 static hipError_t launch_gset(const RunArgs& a, unsigned grid, hipStream_t st) {
-    constexpr int RS = A / GM, RA2 = B / GM, RA3 = C / GM, RF = D / GM;
     constexpr int ALL = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_ASYM3) | (1 << MD_FULL32);
     constexpr int AUTO = (1 << MD_SYM) | (1 << MD_ASYM2) | (1 << MD_FULL32);
-#define APX_G(MASK_, FIELDS_)                                                                                 \
-    hipLaunchKernelGGL((k_fftg<RS, RA2, RA3, RF, MASK_, FIELDS_>), dim3(grid),                               \
-                       dim3(64 * GroupShape<RS, RA2, RA3, RF, MASK_>::NW), 0, st, a)
+#define APX_G(MASK_, FIELDS_, MANY_)                                                                       \
+    hipLaunchKernelGGL((k_fftg<A, RA, B, RB, C, RC, D, RD, MASK_, FIELDS_, MANY_>), dim3(grid),           \
+                       dim3(64 * GroupShape<A, RA, B, RB, C, RC, D, RD, MASK_>::NW), 0, st, a)
+#define APX_GM(MASK_)                 \
+    if (a.many) APX_G(MASK_, false, true); \
+    else APX_G(MASK_, false, false);
     if (a.fields) {
-        APX_G(ALL, true);
+        APX_G(ALL, true, false);
     } else {
         switch (a.mode) {
-            case MD_SYM: APX_G(1 << MD_SYM, false); break;
-            case MD_ASYM2: APX_G(1 << MD_ASYM2, false); break;
-            case MD_ASYM3: APX_G(1 << MD_ASYM3, false); break;
-            case MD_FULL32: APX_G(1 << MD_FULL32, false); break;
-            default: APX_G(AUTO, false); break;
+            case MD_SYM: APX_GM(1 << MD_SYM) break;
+            case MD_ASYM2: APX_GM(1 << MD_ASYM2) break;
+            case MD_ASYM3: APX_GM(1 << MD_ASYM3) break;
+            case MD_FULL32: APX_GM(1 << MD_FULL32) break;
+            default: APX_GM(AUTO) break;
         }
     }
+#undef APX_GM
 #undef APX_G
     return hipGetLastError();
 }
 
 hipError_t launch_fftg(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st) {
-    const unsigned grid = (unsigned)(a.P + 1);
-#define APX_LAUNCH(a_, b_, c_, d_) \
-    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return launch_gset<a_, b_, c_, d_>(a, grid, st);
+    const unsigned grid = (unsigned)a.nitems;
+#define APX_LAUNCH(a_, ra_, b_, rb_, c_, rc_, d_, rd_) \
+    if (ms == a_ && ma2 == b_ && ma3 == c_ && mf == d_) return launch_gset<a_, ra_, b_, rb_, c_, rc_, d_, rd_>(a, grid, st);
     APX_GROUP_SETS(APX_LAUNCH)
 #undef APX_LAUNCH
     return hipErrorInvalidValue;

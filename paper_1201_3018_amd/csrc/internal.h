@@ -66,8 +66,18 @@ struct RunArgs {
     const float2* wtwf;
     const double2* coef[4];
     const float2* coef32;
+    // multi-wave FFT core: per mode, the table of one wave transform (W_MS^t with its per-pass
+    // copies; float2 for index 0, the FP32 slot, double2 otherwise)
+    const void* gsub[4];
     double sigma_s;  // > 0: the signal's sigma in the SNR model for every block (else block rms)
     double sigma_k;  // > 0: the kernel's sigma in the SNR model (else the taps' root second moment)
+    int64_t nitems;            // work items of the launch: P (time-domain and integer cores) or
+                               // P + 1 (FFT cores: block 0's prefix item), or the sum over signals
+    // multi-signal launch: the arguments of every signal (built on the host, one RunArgs per
+    // signal), the signal of each launch item, and (in a signal's own RunArgs) its first item
+    const RunArgs* many;
+    const int32_t* many_sig;
+    int64_t item0;
 };
 
 // Host launchers (kernels.hip).
@@ -97,6 +107,7 @@ bool wave_supported(int ms, int ma2, int ma3, int mf);
 hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st);
 // group-of-waves FFT core (fftw.hip): sizes are multiples of 512 points
 bool group_supported(int ms, int ma2, int ma3, int mf);
+int group_sub_points(int ms, int ma2, int ma3, int mf, int mode);
 hipError_t launch_fftg(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st);
 hipError_t launch_coef(const double* h, int32_t nh, int32_t M, const double2* twF, double2* coef, hipStream_t st);
 hipError_t launch_coef32(const double* h, int32_t nh, int32_t M, const double2* twF, float2* coef, hipStream_t st);

@@ -17,6 +17,7 @@
 
 #include "fft.h"
 #include "internal.h"
+#include "items.h"
 
 namespace apx {
 
@@ -532,9 +533,12 @@ __device__ void td_item(const RunArgs& a, const Item& it, const Choice& c, char*
     }
 }
 
-__global__ void __launch_bounds__(NT) k_td(RunArgs a) {
+template <bool MANY>
+__global__ void __launch_bounds__(NT) k_td(RunArgs a0) {
     extern __shared__ char lds_td[];
-    const Item it = make_item(a, blockIdx.x, false);
+    int64_t item = blockIdx.x;
+    const RunArgs& a = item_args<MANY>(a0, item);
+    const Item it = make_item(a, item, false);
     const BlockStats st = block_stats(a.s, it.start, it.nwin);
     const Choice c = choose(a, st);
     write_info(a, it, c, st, true);
@@ -557,10 +561,13 @@ __global__ void __launch_bounds__(NT) k_td(RunArgs a) {
 
 hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st) {
     if (lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_td, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
+        for (const void* f : {(const void*)k_td<false>, (const void*)k_td<true>}) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            if (e != hipSuccess) return e;
+        }
     }
-    hipLaunchKernelGGL(k_td, dim3((unsigned)a.P), dim3(NT), lds_bytes, st, a);
+    if (a.many) hipLaunchKernelGGL(k_td<true>, dim3((unsigned)a.nitems), dim3(NT), lds_bytes, st, a);
+    else hipLaunchKernelGGL(k_td<false>, dim3((unsigned)a.nitems), dim3(NT), lds_bytes, st, a);
     return hipGetLastError();
 }
 
@@ -775,16 +782,18 @@ __device__ void fft_item_tail(const RunArgs& a, const Item& it, const Choice& c,
     }
 }
 
-template <int LOGF>
-__global__ void __launch_bounds__(NT) k_fft(RunArgs a) {
+template <int LOGF, bool MANY>
+__global__ void __launch_bounds__(NT) k_fft(RunArgs a0) {
     constexpr int F = 1 << LOGF;        // words for FP32 / asymmetric modes
     constexpr int MA = F / 2;           // complex points, FP32 / asymmetric
     constexpr int MS = F / 4;           // complex points, symmetric (F/2 words)
     extern __shared__ __attribute__((aligned(16))) char lds[];  // MA complex FP64 points
-    const Item it = make_item(a, blockIdx.x, true);
+    int64_t item = blockIdx.x;
+    const RunArgs& a = item_args<MANY>(a0, item);
+    const Item it = make_item(a, item, true);
     const BlockStats st = block_stats(a.s, it.start, it.nwin);
     const Choice c = choose(a, st);
-    write_info(a, it, c, st, blockIdx.x < a.P);
+    write_info(a, it, c, st, item < a.P);
     if (c.flags & APX_FLAG_NONFINITE) {
         fill_block(a, it, NAN);
         return;
@@ -807,13 +816,15 @@ __global__ void __launch_bounds__(NT) k_fft(RunArgs a) {
 // One fixed packed mode at a transform of its own length, 2 MW words (MW = 2^LOGMW complex
 // points): the asymmetric modes pack T + N - 1 words and the symmetric mode W_block / 2, so
 // they need shorter transforms than the W_block words of the FP32 slot that k_fft is sized by.
-template <int MODE, int LOGMW>
-__global__ void __launch_bounds__(NT) k_fft1(RunArgs a) {
+template <int MODE, int LOGMW, bool MANY>
+__global__ void __launch_bounds__(NT) k_fft1(RunArgs a0) {
     extern __shared__ __attribute__((aligned(16))) char lds[];  // MW complex FP64 points
-    const Item it = make_item(a, blockIdx.x, true);
+    int64_t item = blockIdx.x;
+    const RunArgs& a = item_args<MANY>(a0, item);
+    const Item it = make_item(a, item, true);
     const BlockStats st = block_stats(a.s, it.start, it.nwin);
     const Choice c = choose(a, st);  // a fixed mode: c.mode == MODE
-    write_info(a, it, c, st, blockIdx.x < a.P);
+    write_info(a, it, c, st, item < a.P);
     if (c.flags & APX_FLAG_NONFINITE) {
         fill_block(a, it, NAN);
         return;
@@ -831,9 +842,10 @@ int fft_max_logF() { return 14; }
 
 #define APX_FFT1_SIZES(X, MODE) X(MODE, 7) X(MODE, 8) X(MODE, 9) X(MODE, 10) X(MODE, 11) X(MODE, 12) X(MODE, 13)
 
+template <bool MANY>
 static const void* fft1_fn(int mode, int logmw) {
 #define APX_FN(M_, L_) \
-    if (mode == M_ && logmw == L_) return (const void*)k_fft1<M_, L_>;
+    if (mode == M_ && logmw == L_) return (const void*)k_fft1<M_, L_, MANY>;
     APX_FFT1_SIZES(APX_FN, MD_SYM)
     APX_FFT1_SIZES(APX_FN, MD_ASYM2)
     APX_FFT1_SIZES(APX_FN, MD_ASYM3)
@@ -841,21 +853,26 @@ static const void* fft1_fn(int mode, int logmw) {
     return nullptr;
 }
 
-bool fft1_supported(int mode, int logmw) { return fft1_fn(mode, logmw) != nullptr; }
+bool fft1_supported(int mode, int logmw) { return fft1_fn<false>(mode, logmw) != nullptr; }
 
 hipError_t fft1_set_lds(int mode, int logmw) {
-    const void* f = fft1_fn(mode, logmw);
-    if (!f) return hipErrorInvalidValue;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds_bytes(true, 1 << logmw));
+    for (const void* f : {fft1_fn<false>(mode, logmw), fft1_fn<true>(mode, logmw)}) {
+        if (!f) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)fft_lds_bytes(true, 1 << logmw));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_fft1(const RunArgs& a, int mode, int logmw, hipStream_t st) {
-    dim3 g((unsigned)(a.P + 1));
+    dim3 g((unsigned)a.nitems);
     const size_t lds = fft_lds_bytes(true, 1 << logmw);
-#define APX_GO(M_, L_)                                                          \
-    if (mode == M_ && logmw == L_) {                                            \
-        hipLaunchKernelGGL((k_fft1<M_, L_>), g, dim3(NT), lds, st, a);           \
-        return hipGetLastError();                                               \
+#define APX_GO(M_, L_)                                                                  \
+    if (mode == M_ && logmw == L_) {                                                    \
+        if (a.many) hipLaunchKernelGGL((k_fft1<M_, L_, true>), g, dim3(NT), lds, st, a);  \
+        else hipLaunchKernelGGL((k_fft1<M_, L_, false>), g, dim3(NT), lds, st, a);        \
+        return hipGetLastError();                                                       \
     }
     APX_FFT1_SIZES(APX_GO, MD_SYM)
     APX_FFT1_SIZES(APX_GO, MD_ASYM2)
@@ -872,30 +889,44 @@ static size_t fft_lds(int logF) {
 
 // Raises the LDS limit of the kernel for logF (once, at kernel preparation: launches may be
 // captured into a graph).
-hipError_t fft_set_lds(int logF) {
-    const void* f = nullptr;
+template <bool MANY>
+static const void* fft_fn(int logF) {
     switch (logF) {
-        case 9: f = (const void*)k_fft<9>; break;
-        case 10: f = (const void*)k_fft<10>; break;
-        case 11: f = (const void*)k_fft<11>; break;
-        case 12: f = (const void*)k_fft<12>; break;
-        case 13: f = (const void*)k_fft<13>; break;
-        case 14: f = (const void*)k_fft<14>; break;
-        default: return hipErrorInvalidValue;
+        case 9: return (const void*)k_fft<9, MANY>;
+        case 10: return (const void*)k_fft<10, MANY>;
+        case 11: return (const void*)k_fft<11, MANY>;
+        case 12: return (const void*)k_fft<12, MANY>;
+        case 13: return (const void*)k_fft<13, MANY>;
+        case 14: return (const void*)k_fft<14, MANY>;
+        default: return nullptr;
     }
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds(logF));
+}
+
+hipError_t fft_set_lds(int logF) {
+    for (const void* f : {fft_fn<false>(logF), fft_fn<true>(logF)}) {
+        if (!f) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fft_lds(logF));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st) {
-    dim3 g((unsigned)(a.P + 1));
+    dim3 g((unsigned)a.nitems);
     const size_t lds = fft_lds(logF);
+#define APX_GO(L_)                                                           \
+    case L_:                                                                 \
+        if (a.many) hipLaunchKernelGGL((k_fft<L_, true>), g, dim3(NT), lds, st, a);  \
+        else hipLaunchKernelGGL((k_fft<L_, false>), g, dim3(NT), lds, st, a);        \
+        break;
     switch (logF) {
-        case 9: hipLaunchKernelGGL(k_fft<9>, g, dim3(NT), lds, st, a); break;
-        case 10: hipLaunchKernelGGL(k_fft<10>, g, dim3(NT), lds, st, a); break;
-        case 11: hipLaunchKernelGGL(k_fft<11>, g, dim3(NT), lds, st, a); break;
-        case 12: hipLaunchKernelGGL(k_fft<12>, g, dim3(NT), lds, st, a); break;
-        case 13: hipLaunchKernelGGL(k_fft<13>, g, dim3(NT), lds, st, a); break;
-        case 14: hipLaunchKernelGGL(k_fft<14>, g, dim3(NT), lds, st, a); break;
+        APX_GO(9)
+        APX_GO(10)
+        APX_GO(11)
+        APX_GO(12)
+        APX_GO(13)
+        APX_GO(14)
+#undef APX_GO
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1606,13 +1637,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // SS, SK: the samples' / the taps' companding range exceeds 127 (two digit planes)
-template <bool SS, bool SK>
-__global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a, const i8x16* __restrict__ frag, int ksteps,
+template <bool SS, bool SK, bool MANY>
+__global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* __restrict__ frag, int ksteps,
                                                        int plane_len, int region) {
     extern __shared__ __attribute__((aligned(16))) char lds_all[];
     const int lane = threadIdx.x & 63;
-    const int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (blk >= a.P) return;
+    int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (blk >= a0.nitems) return;
+    const RunArgs& a = item_args<MANY>(a0, blk);
     char* lds_i8 = lds_all + (size_t)(threadIdx.x >> 6) * region;
     const Item it = make_item(a, blk, false);
     float* win = reinterpret_cast<float*>(lds_i8 + 2 * plane_len);
@@ -1803,8 +1835,10 @@ hipError_t launch_i8_frag(const float* kf, const KState* ks, int mode, int N_odd
 }
 
 hipError_t i8_set_lds(int bytes) {
-    const void* fs[4] = {(const void*)k_i8<false, false>, (const void*)k_i8<false, true>,
-                         (const void*)k_i8<true, false>, (const void*)k_i8<true, true>};
+    const void* fs[8] = {(const void*)k_i8<false, false, false>, (const void*)k_i8<false, true, false>,
+                         (const void*)k_i8<true, false, false>,  (const void*)k_i8<true, true, false>,
+                         (const void*)k_i8<false, false, true>,  (const void*)k_i8<false, true, true>,
+                         (const void*)k_i8<true, false, true>,   (const void*)k_i8<true, true, true>};
     for (const void* f : fs) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -1827,14 +1861,23 @@ size_t i8_lds_bytes(int plane_len, int W_block) {
 hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, hipStream_t st) {
     const int rg = (int)i8_region(plane_len, a.W_block);
     const int wpb = i8_wpb((size_t)rg);
-    const dim3 g((unsigned)((a.P + wpb - 1) / wpb)), b(64 * wpb);
+    const dim3 g((unsigned)((a.nitems + wpb - 1) / wpb)), b(64 * wpb);
     const size_t lds = (size_t)wpb * rg;
     const i8x16* fr = reinterpret_cast<const i8x16*>(frag);
     const int ks = i8_ksteps(a.N);
-    if (split_s && split_k) hipLaunchKernelGGL((k_i8<true, true>), g, b, lds, st, a, fr, ks, plane_len, rg);
-    else if (split_s) hipLaunchKernelGGL((k_i8<true, false>), g, b, lds, st, a, fr, ks, plane_len, rg);
-    else if (split_k) hipLaunchKernelGGL((k_i8<false, true>), g, b, lds, st, a, fr, ks, plane_len, rg);
-    else hipLaunchKernelGGL((k_i8<false, false>), g, b, lds, st, a, fr, ks, plane_len, rg);
+#define APX_GO(SS_, SK_)                                                                              \
+    if (a.many) hipLaunchKernelGGL((k_i8<SS_, SK_, true>), g, b, lds, st, a, fr, ks, plane_len, rg);     \
+    else hipLaunchKernelGGL((k_i8<SS_, SK_, false>), g, b, lds, st, a, fr, ks, plane_len, rg);
+    if (split_s && split_k) {
+        APX_GO(true, true)
+    } else if (split_s) {
+        APX_GO(true, false)
+    } else if (split_k) {
+        APX_GO(false, true)
+    } else {
+        APX_GO(false, false)
+    }
+#undef APX_GO
     return hipGetLastError();
 }
 

@@ -173,3 +173,29 @@ def test_server_budget(ctx):
     assert e.value.status == apx.APX_E_INVALID
     assert srv.stats()["rejected"] == 1
     srv.close()
+
+
+def test_server_batches_requests_of_one_kernel(ctx):
+    """Requests that share a prepared kernel and are admitted together run as one launch: a burst
+    of 40 requests over 2 kernels behind a long first request comes back in fewer launches than
+    requests, every output equal to the request run alone and to the oracle."""
+    N = 300
+    ks = [synth.hann_lowpass(N, 0.07), synth.hann_lowpass(N, 0.21)]
+    reqs = [dict(key=7, k=ks[0], s=synth.ar1(1 << 21, 40), N=N, L=1 << 21, op=apx.APX_CONV, snr=40.0)]
+    rng = np.random.default_rng(41)
+    for i in range(40):
+        L = int(rng.integers(N, 60000))
+        j = i % 2
+        reqs.append(dict(key=7 + j, k=ks[j], s=synth.ar1(L, 4100 + i), N=N, L=L,
+                         op=apx.APX_XCORR if j else apx.APX_CONV, snr=[30.0, 40.0, 50.0][i % 3]))
+    outs, comps, st = _serve(ctx, reqs, hbm_budget=4 << 30, n_streams=4, max_inflight=64)
+    _say(f"  stats {st}")
+    assert st["launches"] < st["completed"] == len(reqs)
+    for i in (0, 1, 2, 17, 40):
+        r, c = reqs[i], comps[i]
+        alone, info = _alone(ctx, r, c["W_block"], with_info=True)
+        assert np.array_equal(outs[i].view(np.int32), alone.view(np.int32)), i
+        _check_auto_oracle(r["s"], r["k"], r["op"], c["W_block"], r["snr"], outs[i], info)
+    for i in range(len(reqs)):
+        if i not in (0, 1, 2, 17, 40):
+            assert np.array_equal(outs[i].view(np.int32), _alone(ctx, reqs[i], comps[i]["W_block"]).view(np.int32)), i
