@@ -170,6 +170,17 @@ apx_status apx_run_auto(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t
                         apx_block_info* info, double snr_min_db, int32_t calib_block, void* workspace,
                         void* stream);
 
+/* apx_run_auto for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the calibration workspace is the
+ * library's own device array of 2048 bytes per device (apx_workspace_bytes() must fit it, else
+ * APX_E_UNSUPPORTED), so the call allocates nothing and never synchronizes.  Every call on one
+ * device shares that array: calls that overlap on one device race and must not be issued
+ * (serialize them on one stream, or use apx_run_auto with distinct workspaces).  Nothing in the
+ * array needs clearing between calls: each call writes every entry it reads.  Same arguments,
+ * results and errors as apx_run_auto otherwise. */
+apx_status apx_run_auto_noalloc(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t L, float* r_out,
+                                apx_block_info* info, double snr_min_db, int32_t calib_block, void* stream);
+
 /* Host only.  A short description of how a prepared kernel runs (core, FFT kernel and transform
  * sizes, companding ranges per mode) written into buf (host, size bytes, NUL-terminated). */
 apx_status apx_kernel_describe(apx_kernel kern, char* buf, int32_t size);

@@ -35,7 +35,7 @@ EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "ap
            "apx_fbank_create", "apx_fbank_run", "apx_fbank_describe", "apx_fbank_destroy", "apx_workspace_bytes",
            "apx_run_auto", "apx_server_create", "apx_server_submit", "apx_server_poll", "apx_server_drain",
            "apx_server_stats", "apx_server_destroy", "apx_server_now", "apx_fit_marginal", "apx_status_str",
-           "apx_last_error", "apx_many_create", "apx_many_run", "apx_many_describe", "apx_many_destroy")
+           "apx_last_error", "apx_many_create", "apx_many_run", "apx_many_describe", "apx_many_destroy", "apx_run_auto_noalloc")
 
 
 class apx_params(ctypes.Structure):
@@ -119,6 +119,7 @@ def lib() -> ctypes.CDLL:
         L.apx_workspace_bytes.argtypes = []
         L.apx_workspace_bytes.restype = ctypes.c_size_t
         L.apx_run_auto.argtypes = [vp, vp, vp, i64, vp, vp, dp, i32, vp, vp]
+        L.apx_run_auto_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, dp, i32, vp]
         L.apx_server_create.argtypes = [vp, ctypes.POINTER(apx_server_config), pvp]
         L.apx_server_submit.argtypes = [vp, ctypes.POINTER(apx_request), ctypes.POINTER(ctypes.c_uint64)]
         L.apx_server_poll.argtypes = [vp, ctypes.POINTER(apx_completion), i32, pi32, i32]
@@ -232,6 +233,12 @@ def apx_run_auto(ctx, kern, s, out, snr_min_db: float, calib_block: int, workspa
     _check(lib().apx_run_auto(ctx, kern, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(out, "float32"),
                               None if info is None else _dev_ptr(info, "uint8"), float(snr_min_db), int(calib_block),
                               _dev_ptr(workspace, "uint8"), _stream(stream)))
+
+
+def apx_run_auto_noalloc(ctx, kern, s, out, snr_min_db: float, calib_block: int, info=None, stream=None):
+    _check(lib().apx_run_auto_noalloc(ctx, kern, _dev_ptr(s, "float32"), s.numel(), _dev_ptr(out, "float32"),
+                                      None if info is None else _dev_ptr(info, "uint8"), float(snr_min_db),
+                                      int(calib_block), _stream(stream)))
 
 
 def apx_kernel_describe(kern) -> str:

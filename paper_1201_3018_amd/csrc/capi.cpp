@@ -329,6 +329,11 @@ apx_status apx_create(int device, apx_ctx* out) {
         c->max_lds = lds;
     apx_status r = build_twiddles(c);
     if (r == APX_OK) {
+        // the device address of this device's scratch copy, taken once with the device current
+        hipError_t e = noalloc_scratch(&c->scratch, &c->scratch_bytes);
+        if (e != hipSuccess) r = fail(APX_E_DEVICE, "scratch address: %s", hipGetErrorString(e));
+    }
+    if (r == APX_OK) {
         double2 w32[32], w24[24];
         fill_twiddles(32, w32);
         fill_twiddles(24, w24);
@@ -822,6 +827,16 @@ apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, fl
     a.calib_dev = off;
     a.snr_min_db = snr_min_db;
     return launch_block_kernel(k, a, st);
+}
+
+apx_status apx_run_auto_noalloc(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info,
+                                double snr_min_db, int32_t calib_block, void* stream) {
+    if (!ctx) return fail(APX_E_INVALID, "null context");
+    if (!ctx->scratch) return fail(APX_E_DEVICE, "no scratch address for device %d", ctx->device);
+    if (apx_workspace_bytes() > ctx->scratch_bytes)
+        return fail(APX_E_UNSUPPORTED, "the calibration needs %zu bytes, the scratch holds %zu", apx_workspace_bytes(),
+                    ctx->scratch_bytes);
+    return apx_run_auto(ctx, k, s, L, out, info, snr_min_db, calib_block, ctx->scratch, stream);
 }
 
 apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {

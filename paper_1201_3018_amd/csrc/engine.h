@@ -41,6 +41,9 @@ struct apx_ctx_s {
     // W_F^t tables (t < F) of any length F, built on first use, and their device bytes
     std::map<int, std::pair<double2*, float2*>> tables;
     size_t table_bytes = 0;
+    // device address of this device's copy of the library's calibration scratch
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
 };
 
 struct apx_kernel_s {

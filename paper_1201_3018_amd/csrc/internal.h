@@ -93,6 +93,8 @@ hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st);
 hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st);
 hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts,
                         hipStream_t st);
+// device address and size of the library's calibration scratch on the current device
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
 // marginal fit (model 0 Laplacian, 1 Weibull) of n samples; out: 4 doubles on the device
 hipError_t launch_fit_marginal(const float* x, int64_t n, int32_t model, double* out, hipStream_t st);
 // offset = measured - model SNR from launch_calib's partials, written to *out (device)

@@ -1392,6 +1392,19 @@ __global__ void __launch_bounds__(NT) k_calib(RunArgs a, int64_t block, int32_t 
     }
 }
 
+// Calibration workspace of apx_run_auto_noalloc, in the library's own device memory for callers
+// that cannot allocate.  Each device holds one copy for the life of the process, shared by every
+// call on that device.  Host code must not pass `scratch` itself to a kernel (in host code the
+// name stands for a host-side placeholder): noalloc_scratch gives its device address.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 2048;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of this device's scratch (call with the device current).
+hipError_t noalloc_scratch(void** ptr, size_t* bytes) {
+    *bytes = NOALLOC_SCRATCH_BYTES;
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts, hipStream_t st) {
     hipLaunchKernelGGL(k_calib, dim3(nparts), dim3(NT), 0, st, a, block, Q, partial);
     return hipGetLastError();
