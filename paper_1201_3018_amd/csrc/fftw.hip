@@ -761,6 +761,21 @@ hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipSt
 // wave per block gives, which hides memory and LDS latency behind other waves' arithmetic.
 // ------------------------------------------------------------------------------------------
 
+// A value every lane of the wave holds equally, moved to scalar registers (frees vector registers
+// for the transforms).
+__device__ __forceinline__ double uni_d(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni_l(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Ordering point for an LDS exchange among the lanes of one wave: the wave's own LDS
 // operations have completed, and the fences keep the compiler from moving LDS accesses across
 // it.  No s_barrier: the other waves of the workgroup are not waited for.
@@ -872,6 +887,8 @@ template <typename T, int M, int R, int RP, int NTH>
 __device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename tw_of<T>::type* twM,
                                                      const typename tw_of<T>::type* coef) {
     constexpr int MS = M / R;
+    using TW = typename tw_of<T>::type;
+    constexpr uint32_t ES = sizeof(TW);
     for (int u = threadIdx.x; u < MS / 2; u += NTH) {
         const int ca = u, cb = (u == 0) ? MS / 2 : MS - u;
         cx<T> A[R], B[R];
@@ -880,46 +897,42 @@ __device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename 
             A[w] = reg[w * RP + ca];
             B[w] = reg[w * RP + cb];
         }
+        // tables through a uniform base and a 32-bit lane offset (one address register per load)
 #pragma unroll
         for (int w = 1; w < R; ++w) {
-            const auto ta = twM[w * ca], tb = twM[w * cb];
+            const TW ta = ld_row(twM, (uint32_t)(w * ca) * ES), tb = ld_row(twM, (uint32_t)(w * cb) * ES);
             A[w] = cmul(A[w], cx<T>{ta.x, ta.y});
             B[w] = cmul(B[w], cx<T>{tb.x, tb.y});
         }
         dftr<T, R, false>(A);  // A[j] = Z[ca + MS j]
         dftr<T, R, false>(B);  // B[j] = Z[cb + MS j]
         __builtin_amdgcn_sched_barrier(0);
-        cx<T> VA[R], VB[R];
+        // partners: (M - ca - MS j) mod M and (M - cb - MS j) mod M; column 0 pairs with itself
+        // at row (R - j) mod R, column MS/2 with itself at row R - 1 - j.  One column at a time
+        // (spectral step, split, store), so that only one column's results and one row's
+        // coefficients are live beside A and B.
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            // partners: (M - ca - MS j) mod M and (M - cb - MS j) mod M
-            cx<T> pa, pb;
-            if (u == 0) {
-                pa = A[(R - j) % R];    // column 0 pairs with itself, row (R - j) mod R
-                pb = B[R - 1 - j];      // column MS/2 pairs with itself, row R - 1 - j
-            } else {
-                pa = B[R - 1 - j];
-                pb = A[R - 1 - j];
+        for (int side = 0; side < 2; ++side) {
+            const int cc = side ? cb : ca;
+            cx<T> V[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const cx<T> z = side ? B[j] : A[j];
+                const cx<T> p = (u == 0) ? (side ? B[R - 1 - j] : A[(R - j) % R]) : (side ? A[R - 1 - j] : B[R - 1 - j]);
+                const uint32_t ko = (uint32_t)(2 * (cc + MS * j)) * ES;
+                const TW al = ld_row(coef, ko), be = ld_row(coef, ko + ES);
+                V[j] = cmul(z, cx<T>{al.x, al.y}) + cmul(conj(p), cx<T>{be.x, be.y});
+                __builtin_amdgcn_sched_barrier(0);  // one row's coefficients in flight at a time
             }
-            const int ka = ca + MS * j, kb = cb + MS * j;
-            const auto aa = coef[2 * ka], ba = coef[2 * ka + 1];
-            const auto ab = coef[2 * kb], bb = coef[2 * kb + 1];
-            VA[j] = cmul(A[j], cx<T>{aa.x, aa.y}) + cmul(conj(pa), cx<T>{ba.x, ba.y});
-            VB[j] = cmul(B[j], cx<T>{ab.x, ab.y}) + cmul(conj(pb), cx<T>{bb.x, bb.y});
-            __builtin_amdgcn_sched_barrier(0);  // one row's coefficients in flight at a time
-        }
-        dftr<T, R, true>(VA);  // VA[w] = sum_j W_R^(-w j) V[ca + MS j]
-        dftr<T, R, true>(VB);
+            dftr<T, R, true>(V);  // V[w] = sum_j W_R^(-w j) V[cc + MS j]
 #pragma unroll
-        for (int w = 1; w < R; ++w) {
-            const auto ta = twM[w * ca], tb = twM[w * cb];
-            VA[w] = cmul(VA[w], cx<T>{ta.x, -ta.y});
-            VB[w] = cmul(VB[w], cx<T>{tb.x, -tb.y});
-        }
+            for (int w = 1; w < R; ++w) {
+                const TW tw = ld_row(twM, (uint32_t)(w * cc) * ES);
+                V[w] = cmul(V[w], cx<T>{tw.x, -tw.y});
+            }
 #pragma unroll
-        for (int w = 0; w < R; ++w) {
-            reg[w * RP + ca] = VA[w];
-            reg[w * RP + cb] = VB[w];
+            for (int w = 0; w < R; ++w) reg[w * RP + cc] = V[w];
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -1195,8 +1208,19 @@ __global__ void __launch_bounds__((64 * GroupShape<MS_, RS_, MA2_, RA2_, MA3_, R
     const RunArgs& a = item_args<MANY>(a0, item);
     const WItem it = wave_make_item(a, item);
     float* win = reinterpret_cast<float*>(lds + 16);
-    const WStats st = group_load_window<NTH>(a, it, win, red);
-    const WChoice c = wave_choose(a, st);
+    WStats st = group_load_window<NTH>(a, it, win, red);
+    st.smax = uni_d(st.smax);
+    st.sumsq = uni_d(st.sumsq);
+    st.nonfinite = uni_i(st.nonfinite);
+    WChoice c = wave_choose(a, st);
+    c.mode = uni_i(c.mode);
+    c.S = uni_i(c.S);
+    c.K = uni_i(c.K);
+    c.flags = uni_i(c.flags);
+    c.R = uni_l(c.R);
+    c.cs = uni_d(c.cs);
+    c.inv = uni_d(c.inv);
+    c.snr_db = uni_d(c.snr_db);
     if (a.info && item < a.P && threadIdx.x == 0) {
         apx_block_info b;
         b.mode = c.mode;
