@@ -110,6 +110,11 @@ apx_status apx_destroy(apx_ctx ctx);
 apx_status apx_geometry(int64_t L, int32_t N, int32_t W_block, int32_t* N_odd, int32_t* W, int64_t* P);
 
 /* Prepare a kernel k (device, N FP32 taps) for one operation and block size (Section IV,
+ * "Initialization").  W_block = 0 takes the block size apx_tune chose for this shape, else the
+ * default rule (the smallest power of two with W >= 2 N, at least 1024 up to 129 taps); with
+ * params->core = APX_CORE_AUTO and fft_variant = 0 the core and FFT implementation are the
+ * tuned ones when the context's table has this shape.  The rest of the preparation
+ * (Section IV,
  * "Initialization"): ||k||_inf, companding of k (eq. 2) for every mode the parameters can use,
  * symmetric packing of k (eq. 5, with eps^-1 = 2 R_max multiplying the even taps), and, for the
  * FFT core, the kernel spectra, all kept on the device.  APX_XCORR stores the time-reversed
@@ -180,6 +185,32 @@ apx_status apx_run_auto(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t
  * results and errors as apx_run_auto otherwise. */
 apx_status apx_run_auto_noalloc(apx_ctx ctx, apx_kernel kern, const float* s_in, int64_t L, float* r_out,
                                 apx_block_info* info, double snr_min_db, int32_t calib_block, void* stream);
+
+/* ---- Autotuning ---------------------------------------------------------------------------
+ * apx_tune: for taps k (device, N FP32), the operation and params->mode (and its companding and
+ * SNR settings), prepares the kernel on every core that can run the shape (time-domain, integer
+ * matrix cores for fixed packed modes, FFT core with LDS passes / one wavefront per block / a
+ * group of wavefronts per block, each with its own radix plan) at W_block, or, for W_block = 0,
+ * at the three smallest power-of-two block sizes with W >= 2 N; times each on a synthetic signal
+ * of 64 blocks (at least 2^16 samples) on `stream`; records the fastest in the context's table
+ * (used by apx_kernel_create for this shape from then on) and in the table file
+ * (APX_TUNE_FILE, else $HOME/.cache/apx_tune.txt; entries of other architectures are kept),
+ * from which apx_create loads this device's entries.  Allocates a test signal and output,
+ * synchronizes `stream`.  out (host): the choice and its time per output.  The packed modes
+ * give the same outputs on every core wherever their unpacking is exact; the choice of block
+ * size changes the per-block companding, so W_block = 0 is for callers that leave it free.
+ * APX_E_UNSUPPORTED: no core runs the shape.
+ * apx_tune_describe (host only): the device's table and the last tuning's timings as text. */
+typedef struct {
+    int32_t core;         /* apx_core */
+    int32_t fft_variant;  /* as apx_params.fft_variant (FFT core) */
+    int32_t W_block;
+    int32_t pad;
+    double ps_per_output; /* measured time per output sample, picoseconds */
+} apx_tuned;
+apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t W_block, const apx_params* params,
+                    void* stream, apx_tuned* out);
+apx_status apx_tune_describe(apx_ctx ctx, char* buf, int32_t size);
 
 /* Host only.  A short description of how a prepared kernel runs (core, FFT kernel and transform
  * sizes, companding ranges per mode) written into buf (host, size bytes, NUL-terminated). */

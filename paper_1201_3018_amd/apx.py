@@ -35,7 +35,8 @@ EXPORTS = ("apx_create", "apx_destroy", "apx_geometry", "apx_kernel_create", "ap
            "apx_fbank_create", "apx_fbank_run", "apx_fbank_describe", "apx_fbank_destroy", "apx_workspace_bytes",
            "apx_run_auto", "apx_server_create", "apx_server_submit", "apx_server_poll", "apx_server_drain",
            "apx_server_stats", "apx_server_destroy", "apx_server_now", "apx_fit_marginal", "apx_status_str",
-           "apx_last_error", "apx_many_create", "apx_many_run", "apx_many_describe", "apx_many_destroy", "apx_run_auto_noalloc")
+           "apx_last_error", "apx_many_create", "apx_many_run", "apx_many_describe", "apx_many_destroy", "apx_run_auto_noalloc",
+           "apx_tune", "apx_tune_describe")
 
 
 class apx_params(ctypes.Structure):
@@ -53,6 +54,11 @@ class apx_block_info(ctypes.Structure):
 BLOCK_INFO_DTYPE = np.dtype([("mode", "<i4"), ("flags", "<i4"), ("Sq", "<i4"), ("Kq", "<i4"), ("rmax", "<i8"),
                              ("cs", "<f8"), ("smax", "<f8"), ("rms", "<f8"), ("snr_pred_db", "<f8")])
 assert BLOCK_INFO_DTYPE.itemsize == ctypes.sizeof(apx_block_info)
+
+
+class apx_tuned(ctypes.Structure):
+    _fields_ = [("core", ctypes.c_int32), ("fft_variant", ctypes.c_int32), ("W_block", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("ps_per_output", ctypes.c_double)]
 
 
 class apx_server_config(ctypes.Structure):
@@ -129,6 +135,8 @@ def lib() -> ctypes.CDLL:
         L.apx_server_now.argtypes = []
         L.apx_server_now.restype = dp
         L.apx_fit_marginal.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
+        L.apx_tune.argtypes = [vp, vp, i32, i32, i32, ctypes.POINTER(apx_params), vp, ctypes.POINTER(apx_tuned)]
+        L.apx_tune_describe.argtypes = [vp, ctypes.c_char_p, i32]
         L.apx_many_create.argtypes = [vp, vp, i32, pvp, pi64, pvp, pvp, vp, pvp]
         L.apx_many_run.argtypes = [vp, vp, vp]
         L.apx_many_describe.argtypes = [vp, ctypes.c_char_p, i32]
@@ -311,6 +319,21 @@ def apx_xcorr_argmax_batch(ctx, refs, tmpls, prm: apx_params, lag_out, val_out, 
                                         _dev_ptr(val_out, "float32"), _stream(stream)))
 
 
+def apx_tune(ctx, k, W_block: int, prm: apx_params, op: int = APX_CONV, stream=None) -> dict:
+    """Time every core / FFT implementation (and block size when W_block = 0) for taps k (device
+    tensor) and record the fastest in the context's table (apx_tune)."""
+    t = apx_tuned()
+    _check(lib().apx_tune(ctx, _dev_ptr(k, "float32"), k.numel(), int(op), int(W_block), ctypes.byref(prm),
+                          _stream(stream), ctypes.byref(t)))
+    return {"core": t.core, "fft_variant": t.fft_variant, "W_block": t.W_block, "ps_per_output": t.ps_per_output}
+
+
+def apx_tune_describe(ctx) -> str:
+    buf = ctypes.create_string_buffer(16384)
+    _check(lib().apx_tune_describe(ctx, buf, 16384))
+    return buf.value.decode()
+
+
 def apx_many_create(ctx, kern, signals, outs, infos=None, stream=None):
     """signals / outs / infos: lists of device tensors (infos entries may be None)."""
     n = len(signals)
@@ -398,6 +421,9 @@ class Kernel:
         self.op = op
         self.prm = params(mode, core, Sq, Kq, snr_min_db, calib_db, allow_unsafe, fft_variant, sigma_s, sigma_k)
         self.h = apx_kernel_create(ctx.h, k, W_block, self.prm, op, stream)
+        if W_block == 0:  # the block size the library chose (tuned, or its default rule)
+            import re
+            self.W_block = int(re.search(r"W_block=(\d+)", self.describe()).group(1))
 
     def geometry(self, L: int):
         return apx_geometry(L, self.N, self.W_block)

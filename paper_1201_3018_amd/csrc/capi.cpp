@@ -231,6 +231,13 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
     const double calib = isnan(k->params.calib_db) ? k->calib_db : k->params.calib_db;
     a.calib_db = calib;
     a.thr_lin = pow(10.0, (k->params.snr_min_db - calib) / 10.0);
+    const double r12 = sqrt(12.0);
+    for (int m = 1; m < 4; ++m) {
+        a.qs_inv[m] = k->S[m] > 0 ? 1.0 / ((double)k->S[m] * r12) : 0.0;
+        a.qk_inv[m] = k->K[m] > 0 ? 1.0 / ((double)k->K[m] * r12) : 0.0;
+        a.eps[m] = k->R[m] > 0 ? 1.0 / (2.0 * (double)k->R[m]) : 0.0;
+    }
+    a.inv_wb = 1.0 / (double)k->W_block;
     a.ks = k->ks;
     a.kf = k->kf;
     a.kd = k->kd;
@@ -333,6 +340,7 @@ apx_status apx_create(int device, apx_ctx* out) {
         hipError_t e = noalloc_scratch(&c->scratch, &c->scratch_bytes);
         if (e != hipSuccess) r = fail(APX_E_DEVICE, "scratch address: %s", hipGetErrorString(e));
     }
+    if (r == APX_OK) apx::tune_load(c);  // this device's autotuning table from earlier processes
     if (r == APX_OK) {
         double2 w32[32], w24[24];
         fill_twiddles(32, w32);
@@ -635,9 +643,13 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
                              const apx_params* params, void* stream, apx_kernel* out) {
     if (!out) return fail(APX_E_INVALID, "null output handle");
     *out = nullptr;
+    if (!ctx || !params) return fail(APX_E_INVALID, "null argument");
+    if (W_block < 0) return fail(APX_E_INVALID, "W_block = %d", W_block);
+    apx_params p = *params;
+    apx::resolve_tuned(ctx, N, op, &W_block, &p);  // W_block 0 and automatic cores take the tuned choice
     apx_kernel k = new (std::nothrow) apx_kernel_s;
     if (!k) return fail(APX_E_NOMEM, "host allocation failed");
-    apx_status r = init_kernel(k, ctx, k_in, N, op, W_block, params, stream, 0);
+    apx_status r = init_kernel(k, ctx, k_in, N, op, W_block, &p, stream, 0);
     if (r != APX_OK) {
         delete k;
         return r;
@@ -768,12 +780,13 @@ apx_status run_args(apx_kernel k, const float* s, int64_t L, float* out, apx_blo
 apx_status calib_on_device(apx_kernel k, const RunArgs& a, int32_t block, void* workspace, const double** off,
                            hipStream_t st) {
     constexpr int nparts = 64, Q = 8;
-    static_assert((2 * nparts + 3) * sizeof(double) <= 2048, "calibration workspace");
     if (block < 0 || block >= a.P) return fail(APX_E_INVALID, "calibration block %d outside [0, %lld)", block, (long long)a.P);
+    static_assert((2 * nparts + 4) * sizeof(double) <= 2048, "calibration workspace");
     double* part = (double*)workspace;
-    double* o = part + 2 * nparts + 2;
+    double* o = part + 2 * nparts + 2;  // offset, then the threshold ratio for a.snr_min_db
     HIPCHK(launch_calib(a, block, Q, part, nparts, st));
-    HIPCHK(launch_calib_finish(part, nparts, k->ks, Q, o, k->params.sigma_k > 0.0 ? k->params.sigma_k : 0.0, st));
+    HIPCHK(launch_calib_finish(part, nparts, k->ks, Q, o, k->params.sigma_k > 0.0 ? k->params.sigma_k : 0.0,
+                               a.snr_min_db, st));
     *off = o;
     return APX_OK;
 }
@@ -794,7 +807,9 @@ apx_status kernel_plan_bytes(apx_ctx ctx, int32_t N, int32_t op, int32_t W_block
     apx_kernel_s tmp;
     tmp.plan_only = true;
     static const float dummy = 0.0f;  // never read: a plan reads no taps
-    apx_status r = init_kernel(&tmp, ctx, &dummy, N, op, W_block, p, nullptr, 0);
+    apx_params pp = *p;
+    resolve_tuned(ctx, N, op, &W_block, &pp);
+    apx_status r = init_kernel(&tmp, ctx, &dummy, N, op, W_block, &pp, nullptr, 0);
     if (r != APX_OK) return r;
     size_t tb = 0;
     for (int F : tmp.plan_tables) tb += (size_t)(F + pass_table_len(F)) * (sizeof(double2) + sizeof(float2));
@@ -821,11 +836,11 @@ apx_status apx_run_auto(apx_ctx ctx, apx_kernel k, const float* s, int64_t L, fl
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(ctx->device));
     RunArgs a = make_args(k, s, L, out, nullptr, info, P);
+    a.snr_min_db = snr_min_db;
     const double* off = nullptr;
     r = calib_on_device(k, a, calib_block, workspace, &off, st);
     if (r != APX_OK) return r;
     a.calib_dev = off;
-    a.snr_min_db = snr_min_db;
     return launch_block_kernel(k, a, st);
 }
 

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -33,6 +34,23 @@ hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_
 
 using apx::KState;
 
+namespace apx {
+// Autotuning table entries: the shape asked for, and the fastest way measured to run it.
+struct TuneKey {
+    int32_t N_odd, op, mode, W_block;  // W_block 0: the tuner chose the block size too
+    bool operator<(const TuneKey& o) const {
+        if (N_odd != o.N_odd) return N_odd < o.N_odd;
+        if (op != o.op) return op < o.op;
+        if (mode != o.mode) return mode < o.mode;
+        return W_block < o.W_block;
+    }
+};
+struct TuneVal {
+    int32_t core, variant, W_block;
+    double ps_per_output;
+};
+}  // namespace apx
+
 struct apx_ctx_s {
     int device = 0;
     double2* twd = nullptr;
@@ -44,6 +62,10 @@ struct apx_ctx_s {
     // device address of this device's copy of the library's calibration scratch
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // autotuning table of this device's architecture (tune.cpp)
+    std::string arch;
+    std::map<apx::TuneKey, apx::TuneVal> tuned;
+    std::string last_tune;
 };
 
 struct apx_kernel_s {
@@ -97,8 +119,9 @@ namespace apx {
 // Internal entry points used by the serving engine (capi.cpp).
 // Arguments of one run of k on s (device, L samples), with the checks of apx_run.
 apx_status run_args(apx_kernel k, const float* s, int64_t L, float* out, apx_block_info* info, RunArgs* a);
-// The per-call calibration of apx_run_auto on block `block` of a's signal, enqueued on st;
-// workspace: apx_workspace_bytes() device bytes; *off: device address of the offset.
+// The per-call calibration of apx_run_auto on block `block` of a's signal for the target
+// a.snr_min_db, enqueued on st; workspace: apx_workspace_bytes() device bytes; *off: device
+// address of the offset (followed by the threshold ratio the block kernels compare against).
 apx_status calib_on_device(apx_kernel k, const RunArgs& a, int32_t block, void* workspace, const double** off,
                            hipStream_t st);
 // One launch of k's block core over every item of the signals whose arguments (item0 set) sit at
@@ -111,5 +134,12 @@ apx_status kernel_plan_bytes(apx_ctx ctx, int32_t N, int32_t op, int32_t W_block
                              size_t* bytes);
 // Record a failure message for apx_last_error and return st.
 apx_status set_error(apx_status st, const char* fmt, ...);
+// Autotuning table (tune.cpp): load this device's entries; look one up; the default block size.
+void tune_load(apx_ctx ctx);
+bool tune_lookup(apx_ctx ctx, int32_t N_odd, int32_t op, int32_t mode, int32_t W_block, TuneVal* out);
+int32_t default_block(int32_t N);
+// The block size and core a kernel request resolves to: W_block 0 takes the tuned block size (or
+// the default rule), and an automatic core and FFT implementation take the tuned ones.
+void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_params* p);
 }  // namespace apx
 

@@ -335,6 +335,8 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
     KState ks = *a.ks;
     // eq. (18)'s sigmas: the block's and the taps' root second moments, or source-level values
     const double rms = a.sigma_s > 0.0 ? a.sigma_s : sqrt(st.sumsq / (double)a.W_block);
+    // the block's mean square (rms^2) for the division-free comparison below
+    const double ms = a.sigma_s > 0.0 ? a.sigma_s * a.sigma_s : st.sumsq * a.inv_wb;
     const bool kzero = ks.krms == 0.0;
     if (a.sigma_k > 0.0) ks.krms = a.sigma_k;
     c.flags = 0;
@@ -342,11 +344,14 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
     c.mode = a.mode;
     if (a.mode == MD_AUTO) {
         double thr = a.thr_lin, calib = a.calib_db;
-        if (a.calib_dev) {
-            calib = *a.calib_dev;
-            thr = pow(10.0, (a.snr_min_db - calib) / 10.0);
+        if (a.calib_dev) {  // this call's calibration: offset and threshold ratio
+            calib = a.calib_dev[0];
+            thr = a.calib_dev[1];
         }
         c.mode = MD_FULL32;
+        // model SNR ratio of eqs. (18)-(19), p^2 / D with p^2 = ms krms^2 and
+        // D = ms svk^2 + krms^2 svs^2 + svk^2 svs^2, compared as p^2 >= thr D (no division)
+        const double k2 = ks.krms * ks.krms;
 #pragma unroll
         for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
             if (!((a.cand_mask >> m) & 1) || a.S[m] < 1) continue;
@@ -354,10 +359,11 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
                 c.mode = m;
                 break;
             }
-            double ratio = wsnr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
-            if (ratio >= thr) {
+            const double svs = st.smax * a.qs_inv[m], svk = ks.kmax * a.qk_inv[m];
+            const double D = ms * (svk * svk) + k2 * (svs * svs) + (svk * svs) * (svk * svs);
+            if (ms * k2 >= thr * D) {
                 c.mode = m;
-                if (a.info) c.snr_db = 10.0 * log10(ratio) + calib;  // reported only
+                if (a.info) c.snr_db = 10.0 * log10(ms * k2 / D) + calib;  // reported only
                 break;
             }
         }
@@ -511,7 +517,7 @@ __device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, con
     cx<T> v[E];
     {
         const int l = lane_id_fresh();
-        const double eps = (MODE == MD_FULL32) ? 0.0 : 1.0 / (2.0 * (double)c.R);
+        const double eps = (MODE == MD_FULL32) ? 0.0 : a.eps[MODE];  // eq. (6), formed on the host
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int n = l + 64 * r;
@@ -578,7 +584,8 @@ __device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, con
             const double up = __shfl_up(De1, 1);
             const double Dep = (n == 0) ? 0.0 : ((l == 0) ? de_last : up);
             de_last = __shfl(De1, 63);
-            const double f0 = Dm0 + Dep, f1 = B0, f2 = Dm1 + De0, f3 = B1;  // r~[4n .. 4n+3]
+            // r~[4n .. 4n+3]; a zero digit is +0, as the integer it stands for
+            const double f0 = Dm0 + Dep + 0.0, f1 = B0 + 0.0, f2 = Dm1 + De0 + 0.0, f3 = B1 + 0.0;
             if (FIELDS) {
                 const double fv[4] = {f0, f1, f2, f3};
 #pragma unroll
@@ -607,7 +614,7 @@ __device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, con
                 const bool ok = (m >= N - 1) && (m < lw);
 #pragma unroll
                 for (int q = 0; q < MM; ++q) {
-                    const double d = rint(x);
+                    const double d = rint(x) + 0.0;  // a zero digit is +0
                     x = (x - d) * two_r;
                     if (ok) {
                         st[q * Tit + m] = (float)(c.inv * d);
@@ -1060,7 +1067,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
     cx<T> v[E];
     if (active) {
         const int l = lane_id_fresh();
-        const double eps = (MODE == MD_FULL32) ? 0.0 : 1.0 / (2.0 * (double)c.R);
+        const double eps = (MODE == MD_FULL32) ? 0.0 : a.eps[MODE];  // eq. (6), formed on the host
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int p = R * (l + 64 * r) + wv;  // complex point = words 2p, 2p + 1
@@ -1140,6 +1147,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
                 if (m >= 1) wsym_split((double)wd[m - 1], two_r, inv_two_r, R_, Dm1, B1, De1);
                 f = Dm + De1;
             }
+            f += 0.0;  // a zero digit is +0
             out[s] = (float)(c.inv * f);
             if (FIELDS) a.fields[it.o0 + s] = f;
         }
@@ -1164,6 +1172,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
                 x = (x - dq) * two_r;
                 if (qq == q) d = dq;
             }
+            d += 0.0;  // a zero digit is +0
             out[s] = (float)(c.inv * d);
             if (FIELDS) a.fields[it.o0 + s] = d;
         }

@@ -46,6 +46,10 @@ struct RunArgs {
     int32_t T[4];        // asymmetric part stride per mode (W / M rounded up)
     int32_t Fw[4];       // FFT length in words per mode (index 0 = FP32 full precision)
     double thr_lin;      // MD_AUTO: SNR ratio that a candidate's model must reach
+    double qs_inv[4];    // per packed mode 1 / (S_q sqrt 12) and 1 / (K_q sqrt 12): sigma_v of eq. (18)
+    double qk_inv[4];    //   is ||x||_inf times these
+    double eps[4];       // per packed mode eps = 1 / (2 R_max) of eq. (6)
+    double inv_wb;       // 1 / W_block
     double calib_db;     // MD_AUTO: offset reported in the block info
     const double* calib_dev;  // MD_AUTO: offset measured on the device for this call (nullable);
     double snr_min_db;        //   then the threshold is formed per block from snr_min_db
@@ -97,10 +101,11 @@ hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* part
 hipError_t noalloc_scratch(void** ptr, size_t* bytes);
 // marginal fit (model 0 Laplacian, 1 Weibull) of n samples; out: 4 doubles on the device
 hipError_t launch_fit_marginal(const float* x, int64_t n, int32_t model, double* out, hipStream_t st);
-// offset = measured - model SNR from launch_calib's partials, written to *out (device)
-// (krms_override > 0 replaces the taps' root second moment, as RunArgs::sigma_k)
+// offset = measured - model SNR from launch_calib's partials, written to out[0] (device), and the
+// SNR ratio a candidate's model must reach for snr_min_db, 10^((snr_min_db - offset) / 10), to
+// out[1] (krms_override > 0 replaces the taps' root second moment, as RunArgs::sigma_k)
 hipError_t launch_calib_finish(const double* partial, int32_t nparts, const KState* ks, int32_t Q, double* out,
-                               double krms_override, hipStream_t st);
+                               double krms_override, double snr_min_db, hipStream_t st);
 hipError_t fft_set_lds(int logF);
 size_t td_lds_bytes(int mode, int N_odd, int W_block, int T2, int T3);
 // wave-per-block FFT core (fftw.hip)

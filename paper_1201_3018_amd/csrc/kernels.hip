@@ -171,6 +171,8 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
     KState ks = *a.ks;
     // eq. (18)'s sigmas: each block's and the taps' root second moments, or source-level values
     const double rms = a.sigma_s > 0.0 ? a.sigma_s : sqrt(st.sumsq / (double)a.W_block);
+    // the block's mean square (rms^2) for the division-free comparison below
+    const double ms = a.sigma_s > 0.0 ? a.sigma_s * a.sigma_s : st.sumsq * a.inv_wb;
     const bool kzero = ks.krms == 0.0;
     if (a.sigma_k > 0.0) ks.krms = a.sigma_k;
     c.flags = 0;
@@ -178,11 +180,14 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
     c.mode = a.mode;
     if (a.mode == MD_AUTO) {
         double thr = a.thr_lin, calib = a.calib_db;
-        if (a.calib_dev) {
-            calib = *a.calib_dev;
-            thr = pow(10.0, (a.snr_min_db - calib) / 10.0);
+        if (a.calib_dev) {  // this call's calibration: offset and threshold ratio
+            calib = a.calib_dev[0];
+            thr = a.calib_dev[1];
         }
         c.mode = MD_FULL32;
+        // model SNR ratio of eqs. (18)-(19), p^2 / D with p^2 = ms krms^2 and
+        // D = ms svk^2 + krms^2 svs^2 + svk^2 svs^2, compared as p^2 >= thr D (no division)
+        const double k2 = ks.krms * ks.krms;
 #pragma unroll
         for (int m = MD_SYM; m <= MD_ASYM2; ++m) {
             if (!((a.cand_mask >> m) & 1) || a.S[m] < 1) continue;
@@ -190,10 +195,11 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
                 c.mode = m;
                 break;
             }
-            double ratio = snr_ratio(rms, st.smax, ks.krms, ks.kmax, a.S[m], a.K[m]);
-            if (ratio >= thr) {
+            const double svs = st.smax * a.qs_inv[m], svk = ks.kmax * a.qk_inv[m];
+            const double D = ms * (svk * svk) + k2 * (svs * svs) + (svk * svs) * (svk * svs);
+            if (ms * k2 >= thr * D) {
                 c.mode = m;
-                if (a.info) c.snr_db = 10.0 * log10(ratio) + calib;  // reported only
+                if (a.info) c.snr_db = 10.0 * log10(ms * k2 / D) + calib;  // reported only
                 break;
             }
         }
@@ -247,6 +253,7 @@ __device__ __forceinline__ void fill_block(const RunArgs& a, const Item& it, flo
 
 __device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double inv) {
     const int64_t o = it.o0 + (j - it.j_lo);
+    rt += 0.0;  // a zero digit is +0, as the integer it stands for
     if (a.fields) a.fields[o] = rt;
     a.out[o] = (float)(inv * rt);  // eq. (16)
 }
@@ -284,7 +291,7 @@ struct ArgmaxSink {
     }
     __device__ __forceinline__ unsigned long long key() const { return bo < 0 ? 0ull : argmax_key(bv, bo); }
     __device__ __forceinline__ void put(const RunArgs& a, const Item& it, int j, double rt, double inv) {
-        consider(it.o0 + (j - it.j_lo), (float)(inv * rt));  // eq. (16), as stored by StoreSink
+        consider(it.o0 + (j - it.j_lo), (float)(inv * (rt + 0.0)));  // eq. (16), as stored by StoreSink
     }
     __device__ __forceinline__ void put32(const RunArgs& a, const Item& it, int j, float v) {
         consider(it.o0 + (j - it.j_lo), v);
@@ -1413,7 +1420,7 @@ hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* part
 // Same arithmetic as the host side of apx_calibrate, in the same order.  A block without
 // quantization error or without signal gives offset 0 (the model alone).
 __global__ void k_calib_finish(const double* __restrict__ partial, int32_t nparts, const KState* __restrict__ ks,
-                               int32_t Q, double* out, double krms_override) {
+                               int32_t Q, double* out, double krms_override, double snr_min_db) {
     if (threadIdx.x != 0) return;
     double pr = 0.0, pe = 0.0;
     for (int i = 0; i < nparts; ++i) {
@@ -1431,12 +1438,13 @@ __global__ void k_calib_finish(const double* __restrict__ partial, int32_t npart
         const double model = 10.0 * log10((rms * krms) * (rms * krms) / D);
         off = measured - model;
     }
-    *out = off;
+    out[0] = off;
+    out[1] = pow(10.0, (snr_min_db - off) / 10.0);  // the ratio a candidate's model must reach
 }
 
 hipError_t launch_calib_finish(const double* partial, int32_t nparts, const KState* ks, int32_t Q, double* out,
-                               double krms_override, hipStream_t st) {
-    hipLaunchKernelGGL(k_calib_finish, dim3(1), dim3(64), 0, st, partial, nparts, ks, Q, out, krms_override);
+                               double krms_override, double snr_min_db, hipStream_t st) {
+    hipLaunchKernelGGL(k_calib_finish, dim3(1), dim3(64), 0, st, partial, nparts, ks, Q, out, krms_override, snr_min_db);
     return hipGetLastError();
 }
 

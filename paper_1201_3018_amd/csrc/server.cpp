@@ -374,10 +374,10 @@ struct apx_server_s {
             if (rc != APX_OK) return rc;
             if (r.mode == APX_AUTO_SNR) {
                 const double* off = nullptr;
+                a.snr_min_db = r.snr_min_db;
                 rc = apx::calib_on_device(k, a, 0, q->ws, &off, s);
                 if (rc != APX_OK) return rc;
                 a.calib_dev = off;
-                a.snr_min_db = r.snr_min_db;
             }
             a.item0 = items;
             items += a.nitems;

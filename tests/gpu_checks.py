@@ -54,7 +54,7 @@ def check_mixed_blocks(s, k, Wb, ps, modes, got, core="fft", ref64=None):
         j_lo, j_hi, o = part.keep(w)
         sl = slice(o, o + j_hi - j_lo)
         if modes[w] != 0:
-            bad = np.nonzero(got[sl] != ref[sl])[0]
+            bad = np.nonzero(got[sl].view(np.int32) != ref[sl].view(np.int32))[0]  # bit for bit
             assert bad.size == 0, f"block {w} (mode {modes[w]}): {bad.size} outputs differ, first at {o + bad[:4]}"
         else:
             err = np.abs(got[sl].astype(np.float64) - ref64[sl])

@@ -65,7 +65,8 @@ def _check_packed(s, k, Wb, mode, S, got, fields, info, kernel_for_oracle=None):
     ref, ref_f, _ = O.conv_blocked(s, kk, Wb, ps, return_fields=True)
     bad = np.nonzero(fields != ref_f)[0]
     assert bad.size == 0, f"{bad.size} integer fields differ, first at {bad[:8]}"
-    badr = np.nonzero(got != ref)[0]
+    # bit for bit: a zero digit gives +0 on both sides
+    badr = np.nonzero(got.view(np.int32) != ref.view(np.int32))[0]
     assert badr.size == 0, f"{badr.size} outputs differ, first at {badr[:8]}: {got[badr[:4]]} vs {ref[badr[:4]]}"
     # block report
     part = O.partition(len(s), len(k), Wb)

@@ -1,0 +1,81 @@
+"""Autotuner (apx_tune): every core / FFT implementation that can run a shape is timed, the
+fastest is recorded in the context's table and the table file, kernels created afterwards with
+automatic choices use it (W_block = 0 takes the tuned block size), a second process loads the
+table, and the tuned kernel's outputs equal the oracle's."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1201_3018_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1201_3018_amd import apx  # noqa: E402
+
+DEV = torch.device("cuda:0")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def test_tune_choose_block_and_core(tmp_path, monkeypatch):
+    path = str(tmp_path / "tune.txt")
+    monkeypatch.setenv("APX_TUNE_FILE", path)
+    ctx = apx.Context(0)
+    N = 64
+    k = synth.uniform(N, 1002)
+    tk = _dev(k)
+    res = apx.apx_tune(ctx.h, tk, 0, apx.params(apx.APX_ASYM2))
+    print("tuned:", res, flush=True)
+    print(apx.apx_tune_describe(ctx.h), flush=True)
+    assert res["W_block"] in (256, 512, 1024) and res["core"] in (apx.APX_CORE_TIME, apx.APX_CORE_INT8, apx.APX_CORE_FFT)
+    assert os.path.exists(path)
+    kern = apx.Kernel(ctx, tk, 0, mode=apx.APX_ASYM2)
+    assert kern.W_block == res["W_block"]
+    core_name = {apx.APX_CORE_TIME: "core=time", apx.APX_CORE_INT8: "core=int8", apx.APX_CORE_FFT: "core=fft"}
+    assert kern.describe().startswith(core_name[res["core"]]), kern.describe()
+    s = synth.gaussian(50000, 1001)
+    out = torch.full((s.size + N - 1,), float("nan"), dtype=torch.float32, device=DEV)
+    kern.run(_dev(s), out=out)
+    got = out.cpu().numpy()
+    S = O.max_q(O.ASYM2, N + 1)
+    ref = O.conv_blocked(s, k, kern.W_block, O.fixed_params(s, k, kern.W_block, O.ASYM2, S, S))
+    assert np.array_equal(got.view(np.int32), ref.view(np.int32))
+    kern.close()
+    # the FFT-block shape: the tuner picks among the FFT core's implementations
+    k2 = _dev(synth.hann_lowpass(1024))
+    res2 = apx.apx_tune(ctx.h, k2, 4096, apx.params(apx.APX_AUTO_SNR, snr_min_db=40.0))
+    print("tuned C2 shape:", res2, flush=True)
+    assert res2["core"] == apx.APX_CORE_FFT and res2["W_block"] == 4096
+    kern2 = apx.Kernel(ctx, k2, 4096, mode=apx.APX_AUTO_SNR, snr_min_db=40.0)
+    want = {1: ("k_fft<", "k_fft1<"), 2: ("k_fftw<",), 3: ("k_fftg<",)}[res2["fft_variant"]]
+    assert any(w in kern2.describe() for w in want), kern2.describe()
+    kern2.close()
+    ctx.close()
+    # a second process starts with the table
+    code = ("import sys; sys.path.insert(0, %r); from paper_1201_3018_amd import apx; c = apx.Context(0); "
+            "print(apx.apx_tune_describe(c.h)); c.close()" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                         env=dict(os.environ, APX_TUNE_FILE=path))
+    print(out.stdout, flush=True)
+    assert out.returncode == 0, out.stderr
+    assert f"N=65 op=0 mode={apx.APX_ASYM2} W_block=0" in out.stdout
+    assert "N=1025 op=0 mode=4 W_block=4096" in out.stdout
+
+
+def test_tune_errors():
+    ctx = apx.Context(0)
+    with pytest.raises(apx.ApxError) as e:
+        apx.apx_tune(ctx.h, _dev(synth.uniform(64, 3)), 1025, apx.params(apx.APX_SYM))  # W odd
+    assert e.value.status == apx.APX_E_INVALID
+    ctx.close()
