@@ -192,7 +192,9 @@ apx_status apx_run_auto_noalloc(apx_ctx ctx, apx_kernel kern, const float* s_in,
  * matrix cores for fixed packed modes, FFT core with LDS passes / one wavefront per block / a
  * group of wavefronts per block, each with its own radix plan) at W_block, or, for W_block = 0,
  * at the three smallest power-of-two block sizes with W >= 2 N; times each on a synthetic signal
- * of 64 blocks (at least 2^16 samples) on `stream`; records the fastest in the context's table
+ * of L_hint samples (0: 64 blocks, at least 2^16 samples; the number of blocks a call has decides
+ * how much parallelism each core finds, so tune for the length you run) on `stream`; records the
+ * fastest in the context's table
  * (used by apx_kernel_create for this shape from then on) and in the table file
  * (APX_TUNE_FILE, else $HOME/.cache/apx_tune.txt; entries of other architectures are kept),
  * from which apx_create loads this device's entries.  Allocates a test signal and output,
@@ -209,7 +211,7 @@ typedef struct {
     double ps_per_output; /* measured time per output sample, picoseconds */
 } apx_tuned;
 apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t W_block, const apx_params* params,
-                    void* stream, apx_tuned* out);
+                    int64_t L_hint, void* stream, apx_tuned* out);
 apx_status apx_tune_describe(apx_ctx ctx, char* buf, int32_t size);
 
 /* Host only.  A short description of how a prepared kernel runs (core, FFT kernel and transform

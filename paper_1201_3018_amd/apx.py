@@ -135,7 +135,7 @@ def lib() -> ctypes.CDLL:
         L.apx_server_now.argtypes = []
         L.apx_server_now.restype = dp
         L.apx_fit_marginal.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]
-        L.apx_tune.argtypes = [vp, vp, i32, i32, i32, ctypes.POINTER(apx_params), vp, ctypes.POINTER(apx_tuned)]
+        L.apx_tune.argtypes = [vp, vp, i32, i32, i32, ctypes.POINTER(apx_params), i64, vp, ctypes.POINTER(apx_tuned)]
         L.apx_tune_describe.argtypes = [vp, ctypes.c_char_p, i32]
         L.apx_many_create.argtypes = [vp, vp, i32, pvp, pi64, pvp, pvp, vp, pvp]
         L.apx_many_run.argtypes = [vp, vp, vp]
@@ -319,12 +319,12 @@ def apx_xcorr_argmax_batch(ctx, refs, tmpls, prm: apx_params, lag_out, val_out, 
                                         _dev_ptr(val_out, "float32"), _stream(stream)))
 
 
-def apx_tune(ctx, k, W_block: int, prm: apx_params, op: int = APX_CONV, stream=None) -> dict:
+def apx_tune(ctx, k, W_block: int, prm: apx_params, op: int = APX_CONV, L_hint: int = 0, stream=None) -> dict:
     """Time every core / FFT implementation (and block size when W_block = 0) for taps k (device
-    tensor) and record the fastest in the context's table (apx_tune)."""
+    tensor) on a signal of L_hint samples and record the fastest in the context's table."""
     t = apx_tuned()
     _check(lib().apx_tune(ctx, _dev_ptr(k, "float32"), k.numel(), int(op), int(W_block), ctypes.byref(prm),
-                          _stream(stream), ctypes.byref(t)))
+                          int(L_hint), _stream(stream), ctypes.byref(t)))
     return {"core": t.core, "fft_variant": t.fft_variant, "W_block": t.W_block, "ps_per_output": t.ps_per_output}
 
 

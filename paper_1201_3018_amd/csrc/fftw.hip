@@ -330,9 +330,27 @@ __device__ __forceinline__ double wsnr_ratio(double rms, double smax, double krm
     return (p * p) / D;
 }
 
-__device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& st) {
+// Inputs of the choice that live in device memory (the taps' statistics, this call's
+// calibration), requested at the start of a block so that their latency overlaps the window load.
+struct WChoiceIn {
+    KState ks;
+    double calib, thr;
+};
+__device__ __forceinline__ WChoiceIn wave_choice_inputs(const RunArgs& a) {
+    WChoiceIn in;
+    in.ks = *a.ks;
+    in.calib = a.calib_db;
+    in.thr = a.thr_lin;
+    if (a.mode == MD_AUTO && a.calib_dev) {  // this call's calibration: offset and threshold ratio
+        in.calib = a.calib_dev[0];
+        in.thr = a.calib_dev[1];
+    }
+    return in;
+}
+
+__device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& st, const WChoiceIn& in) {
     WChoice c;
-    KState ks = *a.ks;
+    KState ks = in.ks;
     // eq. (18)'s sigmas: the block's and the taps' root second moments, or source-level values
     const double rms = a.sigma_s > 0.0 ? a.sigma_s : sqrt(st.sumsq / (double)a.W_block);
     // the block's mean square (rms^2) for the division-free comparison below
@@ -343,11 +361,7 @@ __device__ __forceinline__ WChoice wave_choose(const RunArgs& a, const WStats& s
     c.snr_db = INFINITY;
     c.mode = a.mode;
     if (a.mode == MD_AUTO) {
-        double thr = a.thr_lin, calib = a.calib_db;
-        if (a.calib_dev) {  // this call's calibration: offset and threshold ratio
-            calib = a.calib_dev[0];
-            thr = a.calib_dev[1];
-        }
+        const double thr = in.thr, calib = in.calib;
         c.mode = MD_FULL32;
         // model SNR ratio of eqs. (18)-(19), p^2 / D with p^2 = ms krms^2 and
         // D = ms svk^2 + krms^2 svs^2 + svk^2 svs^2, compared as p^2 >= thr D (no division)
@@ -666,9 +680,10 @@ __global__ void __launch_bounds__(64) k_fftw(RunArgs a0) {
     if (blockIdx.x >= nblk) return;
     const RunArgs& a = item_args<MANY>(a0, item);
     {
+        const WChoiceIn cin = wave_choice_inputs(a);
         const WItem it = wave_make_item(a, item);
         const WStats st = wave_load_window(a, it, reinterpret_cast<float*>(lds) + 1);
-        const WChoice c = wave_choose(a, st);
+        const WChoice c = wave_choose(a, st, cin);
         if (a.info && item < a.P && threadIdx.x == 0) {
             apx_block_info b;
             b.mode = c.mode;
@@ -814,18 +829,24 @@ constexpr int greg_points() {
 template <typename T, int MS, bool INV>
 __device__ __forceinline__ void gsub_fft(cx<T>* v, cx<T>* reg, const typename tw_of<T>::type* tw) {
     constexpr int E = MS / 64;
-    static_assert(E % 8 == 0, "points per lane must be a multiple of 8");
+    static_assert(E % 8 == 0 && (E & (E - 1)) == 0, "points per lane: a power of two, multiple of 8");
     constexpr int NB = E / 8;
+    constexpr int S8 = E / 8;  // distinct row offsets (mod E) among the rows q + 8 r
     using TW = typename tw_of<T>::type;
     auto twB = [&](int r, int k) { return ld_row(tw + MS + (r - 1) * E, (uint32_t)k * (uint32_t)sizeof(TW)); };
     auto twC = [&](int r, int j) {
         return ld_row(tw + MS + 7 * E + (r - 1) * (MS / 8), (uint32_t)j * (uint32_t)sizeof(TW));
     };
-    dftn<T, E, INV>(v);  // pass A: output i = l E + r
+    // Positions follow gpos<E>, written out so that each access is a per-lane base plus a
+    // constant: point j + 8 E r (row q + 8 r, column k, q = j / E, k = j % E) sits at
+    // (q + 8 r) E + (k ^ ((q + 8 r) mod E)), and (q + 8 r) mod E takes E / 8 values as r runs.
+    dftn<T, E, INV>(v);  // pass A: output i = l E + r, at l E + (r ^ (l mod E))
     {
         const int l = lane_id_fresh();
+        cx<T>* row = reg + l * E;
+        const int c = l & (E - 1);
 #pragma unroll
-        for (int r = 0; r < E; ++r) reg[gpos<E>(l * E + r)] = v[r];
+        for (int r = 0; r < E; ++r) row[r ^ c] = v[r];
     }
     region_sync();
     // pass B: radix 8 over sub-transforms of size E; input i = j + 8E r, output 8E q + k + E r
@@ -840,8 +861,11 @@ __device__ __forceinline__ void gsub_fft(cx<T>* v, cx<T>* reg, const typename tw
             const int k = j - q * E;
             q_[b] = q;
             k_[b] = k;
+            const cx<T>* base[S8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) u[b][r] = reg[gpos<E>(j + 8 * E * r)];
+            for (int s = 0; s < S8; ++s) base[s] = reg + q * E + (k ^ ((q + 8 * s) & (E - 1)));
+#pragma unroll
+            for (int r = 0; r < 8; ++r) u[b][r] = base[r % S8][8 * E * r];
 #pragma unroll
             for (int r = 1; r < 8; ++r) {
                 const auto w = twB(r, k);  // W_{8E}^{rk} = W_MS^{8rk}
@@ -850,10 +874,14 @@ __device__ __forceinline__ void gsub_fft(cx<T>* v, cx<T>* reg, const typename tw
             dft8<T, INV>(u[b]);
         }
         region_sync();
+        // point 8 E q + k + E r: row 8 q + r, whose value mod E is 8 (q mod (E / 8)) + r
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b) {
+            cx<T>* row0 = reg + 8 * E * q_[b];
+            const int kx = k_[b] ^ (8 * (q_[b] & (S8 - 1)));
 #pragma unroll
-            for (int r = 0; r < 8; ++r) reg[gpos<E>(8 * E * q_[b] + k_[b] + E * r)] = u[b][r];
+            for (int r = 0; r < 8; ++r) row0[E * r + (kx ^ r)] = u[b][r];
+        }
     }
     region_sync();
     // pass C: radix 8 over sub-transforms of size MS/8; results stay in registers
@@ -862,9 +890,14 @@ __device__ __forceinline__ void gsub_fft(cx<T>* v, cx<T>* reg, const typename tw
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int j = l + 64 * b;
+            const int q = j / E;
+            const int k = j - q * E;
+            const cx<T>* base[S8];
+#pragma unroll
+            for (int s = 0; s < S8; ++s) base[s] = reg + q * E + (k ^ ((q + 8 * s) & (E - 1)));
             cx<T> x[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) x[r] = reg[gpos<E>(j + 8 * E * r)];
+            for (int r = 0; r < 8; ++r) x[r] = base[r % S8][8 * E * r];
 #pragma unroll
             for (int r = 1; r < 8; ++r) {
                 const auto w = twC(r, j);
@@ -946,13 +979,12 @@ __device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename 
 
 // Window of the item into LDS (FP32, zero past nvalid, zero sentinels at -1 and W_block) with
 // its statistics from the same loads; per-wave partials are combined through `red` in the same
-// order by every thread.
-template <int NTH>
+// order by every thread.  CH float2 loads per thread and step.
+template <int NTH, int CH>
 __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WItem& it, float* win, double* red) {
     double m = 0.0, q = 0.0;
     int nf = 0;
     const float* p = a.s + it.start;  // start is even and s_in 8-byte aligned (checked on the host)
-    constexpr int CH = 4;             // float2 loads in flight per thread
     auto take = [&](float x0, float x1) {
         const bool f0 = isfinite(x0), f1 = isfinite(x1);
         if (!(f0 && f1)) nf = 1;
@@ -960,18 +992,24 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
         m = fmax(m, fmax(fabs(d0), fabs(d1)));
         q += d0 * d0 + d1 * d1;
     };
+    // uniform: the window lies inside the signal and is valid throughout (every block but the
+    // last), so that a sample needs no bound but the window's own
+    const bool interior = it.nwin >= a.W_block && it.nvalid >= a.W_block;
     for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
         float2 f[CH];
-        const int end = base + 2 * NTH * CH;
-        if (end <= it.nwin && end <= it.nvalid && end <= a.W_block) {  // uniform: no per-sample bounds
+        if (interior) {
 #pragma unroll
-            for (int c = 0; c < CH; ++c)
-                f[c] = *reinterpret_cast<const float2*>(p + base + 2 * ((int)threadIdx.x + NTH * c));
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + 2 * ((int)threadIdx.x + NTH * c);  // even, as W_block is
+                if (i < a.W_block) f[c] = *reinterpret_cast<const float2*>(p + i);
+            }
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int i = base + 2 * ((int)threadIdx.x + NTH * c);
-                take(f[c].x, f[c].y);
-                *reinterpret_cast<float2*>(win + i) = f[c];
+                if (i < a.W_block) {
+                    take(f[c].x, f[c].y);
+                    *reinterpret_cast<float2*>(win + i) = f[c];
+                }
             }
             continue;
         }
@@ -1059,8 +1097,11 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
         lw = Tit + N - 1;
     }
     const int wb = a.W_block;
+    // window sample, clamped onto the zero sentinels outside [0, W_block), and companded (eq. 2);
+    // the unclamped forms serve the steps whose every index lies in [0, W_block]
     auto rd = [&](int i) -> float { return win[min(max(i, -1), wb)]; };
     auto sqd = [&](int i) -> double { return rint(c.cs * (double)rd(i)); };
+    auto sqd_in = [&](int i) -> double { return rint(c.cs * (double)win[i]); };
     const int wv = threadIdx.x >> 6;
     const bool active = wv < R;
     // ---- pack: wave w holds the decimated points z[R n + w], n = l + 64 r (eq. 4 / eq. 7)
@@ -1071,27 +1112,60 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int p = R * (l + 64 * r) + wv;  // complex point = words 2p, 2p + 1
+            // the step's first and last points (uniform over the wave)
+            const int pmin = R * 64 * r + wv, pmax = R * (64 * r + 63) + wv;
             if constexpr (MODE == MD_FULL32) {
-                v[r].x = rd(2 * p);
-                v[r].y = rd(2 * p + 1);
-            } else if constexpr (MODE == MD_SYM) {
-                v[r].x = sqd(4 * p) + eps * sqd(4 * p + 1);
-                v[r].y = sqd(4 * p + 2) + eps * sqd(4 * p + 3);
-            } else {
-                double w2[2];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int wd = 2 * p + h;
-                    double acc = 0.0, e = 1.0;
-#pragma unroll
-                    for (int q = 0; q < MM; ++q) {
-                        acc += e * sqd(base_off + q * Tit + wd);
-                        e *= eps;
-                    }
-                    w2[h] = (wd < lw) ? acc : 0.0;
+                if (2 * pmax + 1 <= wb) {
+                    v[r].x = win[2 * p];
+                    v[r].y = win[2 * p + 1];
+                } else {
+                    v[r].x = rd(2 * p);
+                    v[r].y = rd(2 * p + 1);
                 }
-                v[r].x = w2[0];
-                v[r].y = w2[1];
+            } else if constexpr (MODE == MD_SYM) {
+                if (4 * pmax + 3 <= wb) {
+                    v[r].x = sqd_in(4 * p) + eps * sqd_in(4 * p + 1);
+                    v[r].y = sqd_in(4 * p + 2) + eps * sqd_in(4 * p + 3);
+                } else {
+                    v[r].x = sqd(4 * p) + eps * sqd(4 * p + 1);
+                    v[r].y = sqd(4 * p + 2) + eps * sqd(4 * p + 3);
+                }
+            } else {
+                if (!prefix && 2 * pmax + 1 < lw && base_off + (MM - 1) * Tit + 2 * pmax + 1 <= wb) {
+                    // every word of the step is kept and reads inside the window (base_off >= 0)
+                    double w2[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int wd = base_off + 2 * p + h;
+                        double acc = sqd_in(wd), e = eps;
+#pragma unroll
+                        for (int q = 1; q < MM; ++q) {
+                            acc += e * sqd_in(wd + q * Tit);
+                            e *= eps;
+                        }
+                        w2[h] = acc;
+                    }
+                    v[r].x = w2[0];
+                    v[r].y = w2[1];
+                } else if (2 * pmin >= lw) {  // every word of the step is padding
+                    v[r].x = 0.0;
+                    v[r].y = 0.0;
+                } else {
+                    double w2[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int wd = 2 * p + h;
+                        double acc = 0.0, e = 1.0;
+#pragma unroll
+                        for (int q = 0; q < MM; ++q) {
+                            acc += e * sqd(base_off + q * Tit + wd);
+                            e *= eps;
+                        }
+                        w2[h] = (wd < lw) ? acc : 0.0;
+                    }
+                    v[r].x = w2[0];
+                    v[r].y = w2[1];
+                }
             }
             if (r & 1) __builtin_amdgcn_sched_barrier(0);  // bound the window reads in flight
         }
@@ -1152,29 +1226,22 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
             if (FIELDS) a.fields[it.o0 + s] = f;
         }
     } else {
-        // local output j = base_off + q Tit + word, word in [N - 1, lw)
+        // word N - 1 + u (u < Tit) holds digit q of local output base_off + q Tit + N - 1 + u, i.e.
+        // of output s = q Tit + u of the item: one word per thread, its MM digits in turn
         const double two_r = (double)(2 * c.R);
-        for (int s = threadIdx.x; s < nout; s += NTH) {
-            const int jj = it.j_lo + s - base_off;  // = q Tit + word
-            int q = 0;
-            int wdx = jj;
+        for (int u = threadIdx.x; u < Tit; u += NTH) {
+            double x = (double)wd[N - 1 + u];
 #pragma unroll
-            for (int qq = 1; qq < MM; ++qq)
-                if (jj - qq * Tit >= N - 1) {
-                    q = qq;
-                    wdx = jj - qq * Tit;
-                }
-            double x = (double)wd[wdx];
-            double d = 0.0;
-#pragma unroll
-            for (int qq = 0; qq < MM; ++qq) {
+            for (int q = 0; q < MM; ++q) {
                 const double dq = rint(x);
                 x = (x - dq) * two_r;
-                if (qq == q) d = dq;
+                const int s = q * Tit + u;
+                if (s < nout) {
+                    const double d = dq + 0.0;  // a zero digit is +0
+                    out[s] = (float)(c.inv * d);
+                    if (FIELDS) a.fields[it.o0 + s] = d;
+                }
             }
-            d += 0.0;  // a zero digit is +0
-            out[s] = (float)(c.inv * d);
-            if (FIELDS) a.fields[it.o0 + s] = d;
         }
     }
 }
@@ -1215,13 +1282,14 @@ __global__ void __launch_bounds__((64 * GroupShape<MS_, RS_, MA2_, RA2_, MA3_, R
     int64_t item = x8 * q8 + (x8 < r8 ? x8 : r8) + blockIdx.x / 8;
     if (blockIdx.x >= nblk) return;
     const RunArgs& a = item_args<MANY>(a0, item);
+    const WChoiceIn cin = wave_choice_inputs(a);
     const WItem it = wave_make_item(a, item);
     float* win = reinterpret_cast<float*>(lds + 16);
-    WStats st = group_load_window<NTH>(a, it, win, red);
+    WStats st = group_load_window<NTH, 4>(a, it, win, red);
     st.smax = uni_d(st.smax);
     st.sumsq = uni_d(st.sumsq);
     st.nonfinite = uni_i(st.nonfinite);
-    WChoice c = wave_choose(a, st);
+    WChoice c = wave_choose(a, st, cin);
     c.mode = uni_i(c.mode);
     c.S = uni_i(c.S);
     c.K = uni_i(c.K);

@@ -158,11 +158,12 @@ void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_par
 extern "C" {
 
 apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t W_block, const apx_params* params,
-                    void* stream, apx_tuned* out) {
+                    int64_t L_hint, void* stream, apx_tuned* out) {
     if (!ctx || !k || !params || !out) return apx::set_error(APX_E_INVALID, "null argument");
     if (N < 1) return apx::set_error(APX_E_INVALID, "N = %d", N);
     if (op != APX_CONV && op != APX_XCORR) return apx::set_error(APX_E_INVALID, "unknown op %d", op);
     if (W_block < 0) return apx::set_error(APX_E_INVALID, "W_block = %d", W_block);
+    if (L_hint < 0 || (L_hint > 0 && L_hint < N)) return apx::set_error(APX_E_INVALID, "L_hint = %lld", (long long)L_hint);
     const int32_t N_odd = odd_of(N);
     std::vector<int32_t> blocks;
     if (W_block > 0) {
@@ -174,9 +175,10 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
     }
     hipStream_t st = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return apx::set_error(APX_E_DEVICE, "hipSetDevice failed");
-    // a signal of 64 of the largest blocks' outputs (at least 2^16 samples)
+    // the caller's signal length, else 64 of the largest blocks' outputs (at least 2^16 samples):
+    // how many blocks a call has decides how much parallelism each core finds
     const int32_t wb_max = blocks.back();
-    const int64_t L = std::max<int64_t>((int64_t)64 * (wb_max - N_odd - 1), 1 << 16);
+    const int64_t L = L_hint > 0 ? L_hint : std::max<int64_t>((int64_t)64 * (wb_max - N_odd - 1), 1 << 16);
     const std::vector<float> hs = test_signal(L);
     float *s = nullptr, *o = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;

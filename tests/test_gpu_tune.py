@@ -54,7 +54,7 @@ def test_tune_choose_block_and_core(tmp_path, monkeypatch):
     kern.close()
     # the FFT-block shape: the tuner picks among the FFT core's implementations
     k2 = _dev(synth.hann_lowpass(1024))
-    res2 = apx.apx_tune(ctx.h, k2, 4096, apx.params(apx.APX_AUTO_SNR, snr_min_db=40.0))
+    res2 = apx.apx_tune(ctx.h, k2, 4096, apx.params(apx.APX_AUTO_SNR, snr_min_db=40.0), L_hint=1 << 22)
     print("tuned C2 shape:", res2, flush=True)
     assert res2["core"] == apx.APX_CORE_FFT and res2["W_block"] == 4096
     kern2 = apx.Kernel(ctx, k2, 4096, mode=apx.APX_AUTO_SNR, snr_min_db=40.0)
