@@ -118,13 +118,25 @@ def main():
     N_odd, W, P = apx.apx_geometry(L, N, Wb)
     core = apx.APX_CORE_FFT if wl["core"] == "fft" else apx.APX_CORE_TIME
 
+    tuned = None
     if args.workload == "c2":
-        kern = apx.Kernel(ctx, tk, Wb, mode=apx.APX_AUTO_SNR, core=core, snr_min_db=wl["snr"])
-        calib = kern.calibrate(ts[0])
+        # calibrate the SNR model once on this signal, then let the autotuner pick the core and
+        # FFT implementation of the packed path and of the FP32 comparator at this shape
+        k0 = apx.Kernel(ctx, tk, Wb, mode=apx.APX_AUTO_SNR, core=core, snr_min_db=wl["snr"])
+        calib = k0.calibrate(ts[0])
+        k0.close()
+        tuned = {
+            "packed": apx.apx_tune(ctx.h, tk, Wb, apx.params(apx.APX_AUTO_SNR, apx.APX_CORE_AUTO,
+                                                              snr_min_db=wl["snr"], calib_db=calib), L_hint=L),
+            "full_fp32": apx.apx_tune(ctx.h, tk, Wb, apx.params(apx.APX_FULL_FP32, apx.APX_CORE_AUTO), L_hint=L),
+        }
+        kern = apx.Kernel(ctx, tk, Wb, mode=apx.APX_AUTO_SNR, core=apx.APX_CORE_AUTO, snr_min_db=wl["snr"],
+                          calib_db=calib)
+        full = apx.Kernel(ctx, tk, Wb, mode=apx.APX_FULL_FP32, core=apx.APX_CORE_AUTO)
     else:
         kern = apx.Kernel(ctx, tk, Wb, mode=apx.APX_ASYM2, core=core, Sq=127, Kq=127)
         calib = None
-    full = apx.Kernel(ctx, tk, Wb, mode=apx.APX_FULL_FP32, core=core)
+        full = apx.Kernel(ctx, tk, Wb, mode=apx.APX_FULL_FP32, core=core)
     try:
         ref64 = apx.Kernel(ctx, tk, Wb, mode=apx.APX_FULL_FP64, core=apx.APX_CORE_TIME)
     except apx.ApxError as e:  # FP64 reference path needs more LDS than this device offers
@@ -156,7 +168,7 @@ def main():
     snr_sweep = []
     if args.workload == "c2":
         for target in (20.0, 30.0, 50.0):
-            kt = apx.Kernel(ctx, tk, Wb, mode=apx.APX_AUTO_SNR, core=core, snr_min_db=target, calib_db=calib)
+            kt = apx.Kernel(ctx, tk, Wb, mode=apx.APX_AUTO_SNR, core=apx.APX_CORE_AUTO, snr_min_db=target, calib_db=calib)
             ms_t = timed(kt, max(1, args.steps // 4), 2)
             _, inf_t = kt.run(ts[0], info=True)
             torch.cuda.synchronize()
@@ -216,8 +228,11 @@ def main():
     value = outputs / (ms_packed * 1e-3)
     modes = np.bincount(info["mode"], minlength=4)
 
-    # roofline of the dominant kernel (the fused FFT / TD block kernel, one launch per step)
-    bytes_alg = P * Wb * 4 + outputs * 4          # each window read once + each output written once
+    # roofline of the dominant kernel (the fused FFT / TD block kernel, one launch per step):
+    # compulsory bytes, every input sample read once and every output written once; the window
+    # bytes (overlapping windows each read whole) are reported beside them
+    bytes_alg = L * 4 + outputs * 4
+    bytes_win = P * Wb * 4 + outputs * 4
     achieved_gbs = bytes_alg / (ms_packed * 1e-3) / 1e9
     if args.workload == "c2":
         F = 1 << max(9, int(math.ceil(math.log2(Wb))))
@@ -242,8 +257,10 @@ def main():
     roof["traffic"] = measured_traffic(args.workload)  # scaled FETCH_SIZE + WRITE_SIZE, bytes/launch
     roof["alt"] = {"hbm_GBs": round(achieved_gbs, 1), "hbm_frac": round(hbm_frac, 4),
                    "fp64_TFLOPs": round(achieved_tf, 2), "fp64_frac": round(alu_frac, 4)}
+    roof["alt"]["window_bytes_GBs"] = round(bytes_win / (ms_packed * 1e-3) / 1e9, 1)
     roof["kernel"] = kern.describe()
     roof["bytes_per_launch"] = bytes_alg
+    roof["window_bytes_per_launch"] = bytes_win
     roof["flops_per_launch"] = fl
 
     res = {
@@ -265,10 +282,13 @@ def main():
         "full_fp32": {"value": outputs / (ms_full * 1e-3), "ms_per_step": ms_full,
                       "snr_db_min": float(np.min(snr_f))},
         "packed_over_fp32": ms_full / ms_packed,
+        "full_fp32_kernel": full.describe(),
         "modes": {"full_fp32": int(modes[0]), "sym": int(modes[1]), "asym2": int(modes[2])},
         "snr_db": {"min": float(np.min(snr_p)), "mean": float(np.mean(snr_p[np.isfinite(snr_p)]))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
     }
+    if tuned:
+        res["tuned"] = tuned
     if snr_sweep:
         res["snr_sweep"] = snr_sweep
     if int8_core:
@@ -380,6 +400,7 @@ def bench_c1(args, wl):
         "full_fp32": {"ms_per_step": ms_full, "value": outputs / (ms_full * 1e-3),
                       "snr_db_min": float(np.min(snrs_f))},
         "packed_over_fp32": ms_full / ms_packed,
+        "full_fp32_kernel": full.describe(),
         "snr_db": {"min": float(np.min(snrs)), "sampled_signals": 4},
     }
     if not args.no_cpu:

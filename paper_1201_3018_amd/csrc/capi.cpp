@@ -521,11 +521,20 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         if (wm[0] == 0) ok = false;  // the FP32 size also sizes the window in LDS
         if (ok && p.fft_variant != 1) {
             // modes that are not used may take any size, except the FP32 slot (W_block <= 2 M):
-            // look for a compiled set that matches (the launch needs a complete set); the
-            // one-wave core first (faster on every measured shape), the group core if asked for
+            // look for a compiled set that matches (the launch needs a complete set).  Automatic
+            // choice: the group core first when a packed mode can occur (C2, asymmetric M=2:
+            // 28 vs 30 us; per-block choice at 40 dB: 29 vs 32 us), the one-wave core first for
+            // FP32 alone (24 vs 25 us)
             const int cand[4] = {512, 1024, 1536, 2048};
-            for (int pass = (p.fft_variant == 3 ? 0 : 1); pass >= 0 && !k->wave; --pass) {
-                if (pass == 0 && p.fft_variant != 3) continue;
+            const bool packed = k->use[MD_SYM] || k->use[MD_ASYM2] || k->use[MD_ASYM3];
+            int order[2] = {packed ? 0 : 1, packed ? 1 : 0};  // 0 = group, 1 = one wave
+            int npass = 2;
+            if (p.fft_variant == 2 || p.fft_variant == 3) {
+                order[0] = p.fft_variant == 3 ? 0 : 1;
+                npass = 1;
+            }
+            for (int oi = 0; oi < npass && !k->wave; ++oi) {
+                const int pass = order[oi];
                 for (int c = 0; c < 256 && !k->wave; ++c) {
                     const int t4[4] = {cand[c & 3], cand[(c >> 2) & 3], cand[(c >> 4) & 3], cand[(c >> 6) & 3]};
                     bool match = t4[0] == wm[0];

@@ -130,6 +130,17 @@ __device__ __forceinline__ V ld_row(const V* row, uint32_t off) {
     return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(row) + off);
 }
 
+// An opaque copy of a wave-uniform table pointer: loads through it cannot be merged with loads
+// through the original, so table entries read in one phase are not kept in registers for a
+// later phase that reads them again (the inverse transform reuses the forward one's twiddles).
+template <typename V>
+__device__ __forceinline__ const V* table_fresh(const V* p) {
+    const uint64_t b = (uint64_t)(uintptr_t)p;
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return reinterpret_cast<const V*>((uintptr_t)(((uint64_t)hi << 32) | lo));
+}
+
 // An opaque copy of the lane id (0..63 in every wave of the workgroup): address arithmetic derived from it cannot be shared between
 // phases, so nothing computed for one phase stays live (in registers) through the next.
 __device__ __forceinline__ int lane_id_fresh() {
@@ -1181,11 +1192,14 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
     __syncthreads();
     gjoin_spectral_split<T, M, R, RP, NTH>(reg, twM, coef);
     __syncthreads();
+    // the inverse gets arrays of its own: were it to reuse v, the forward results would stay
+    // live (in registers) through the fused pass on the path of the waves that hold no region
+    cx<T> vi[E];
     if (active) {
         const int l = lane_id_fresh();
 #pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = mine[l + 64 * r];
-        gsub_fft<T, MS, true>(v, mine, tws);
+        for (int r = 0; r < E; ++r) vi[r] = mine[l + 64 * r];
+        gsub_fft<T, MS, true>(vi, mine, table_fresh(tws));
     }
     __syncthreads();  // every region is dead: the words of the cyclic convolution take their bytes
     T* wd = reinterpret_cast<T*>(lds_raw);
@@ -1194,8 +1208,8 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
 #pragma unroll
         for (int t = 0; t < E; ++t) {
             const int p = R * (l + 64 * t) + wv;
-            wd[2 * p] = v[t].x;
-            wd[2 * p + 1] = v[t].y;
+            wd[2 * p] = vi[t].x;
+            wd[2 * p + 1] = vi[t].y;
         }
     }
     __syncthreads();
@@ -1208,23 +1222,43 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
             if (FIELDS) a.fields[it.o0 + s] = 0.0;
         }
     } else if constexpr (MODE == MD_SYM) {
-        // word m -> r~[2m + 1] = B(m), r~[2m] = Dm(m) + De(m - 1)
+        // word m -> r~[2m + 1] = B(m), r~[2m] = Dm(m) + De(m - 1).  Each thread splits a run of cw
+        // consecutive words once each, and the word before its run; the outputs then go over the
+        // words' bytes (the pair 2m, 2m + 1 as two floats where word m was) and are copied out
+        // coalesced.  cw is odd, so that the lanes' runs start on different LDS banks.
         const double two_r = (double)(2 * c.R), R_ = (double)c.R, inv_two_r = 1.0 / two_r;
-        for (int s = threadIdx.x; s < nout; s += NTH) {
-            const int j = it.j_lo + s;
-            const int m = j >> 1;
-            double Dm, B, De;
-            wsym_split((double)wd[m], two_r, inv_two_r, R_, Dm, B, De);
-            double f = B;
-            if ((j & 1) == 0) {
-                double Dm1 = 0.0, B1 = 0.0, De1 = 0.0;
-                if (m >= 1) wsym_split((double)wd[m - 1], two_r, inv_two_r, R_, Dm1, B1, De1);
-                f = Dm + De1;
+        constexpr int CW = ((2 * M + NTH - 1) / NTH) | 1;  // words per thread at most
+        const int mA = it.j_lo >> 1, mB = (it.j_hi + 1) >> 1;  // the words whose outputs are kept
+        const int cw = ((mB - mA + NTH - 1) / NTH) | 1;         // uniform, <= CW
+        const int m0 = mA + (int)threadIdx.x * cw;
+        double w[CW + 1];  // w[0]: word m0 - 1
+        w[0] = (m0 >= 1 && m0 <= mB) ? (double)wd[m0 - 1] : 0.0;
+#pragma unroll
+        for (int i = 0; i < CW; ++i) w[i + 1] = (i < cw && m0 + i < mB) ? (double)wd[m0 + i] : 0.0;
+        __syncthreads();  // every word is read: the outputs take their bytes
+        float* stg = reinterpret_cast<float*>(lds_raw);
+        double Dm, B, De_prev = 0.0;
+        if (m0 >= 1 && m0 < mB) wsym_split(w[0], two_r, inv_two_r, R_, Dm, B, De_prev);
+#pragma unroll
+        for (int i = 0; i < CW; ++i) {
+            const int m = m0 + i;
+            if (i < cw && m < mB) {
+                double De;
+                wsym_split(w[i + 1], two_r, inv_two_r, R_, Dm, B, De);
+                const double fe = Dm + De_prev + 0.0, fo = B + 0.0;  // a zero digit is +0
+                De_prev = De;
+                if (2 * m >= it.j_lo && 2 * m < it.j_hi) {
+                    stg[2 * m] = (float)(c.inv * fe);
+                    if (FIELDS) a.fields[it.o0 + (2 * m - it.j_lo)] = fe;
+                }
+                if (2 * m + 1 >= it.j_lo && 2 * m + 1 < it.j_hi) {
+                    stg[2 * m + 1] = (float)(c.inv * fo);
+                    if (FIELDS) a.fields[it.o0 + (2 * m + 1 - it.j_lo)] = fo;
+                }
             }
-            f += 0.0;  // a zero digit is +0
-            out[s] = (float)(c.inv * f);
-            if (FIELDS) a.fields[it.o0 + s] = f;
         }
+        __syncthreads();
+        for (int s = threadIdx.x; s < nout; s += NTH) out[s] = stg[it.j_lo + s];
     } else {
         // word N - 1 + u (u < Tit) holds digit q of local output base_off + q Tit + N - 1 + u, i.e.
         // of output s = q Tit + u of the item: one word per thread, its MM digits in turn

@@ -475,7 +475,7 @@ def _tie_case(L=20000, N=65, Wb=1024, seed=77):
 
 
 @pytest.mark.parametrize("core,variant", [("td", apx.FFT_AUTO), ("fft", apx.FFT_BLOCK), ("fft", apx.FFT_WAVE),
-                                          ("int8", apx.FFT_AUTO)])
+                                          ("fft", apx.FFT_GROUP), ("int8", apx.FFT_AUTO)])
 def test_sym_base_digit_tie(ctx, core, variant):
     """Symmetric packing with a base digit at +-R_max.  The word 2R D + B + eps E holds the same
     value for (D, R) and (D + 1, -R), so the unpacking cannot tell which one the convolution
@@ -486,8 +486,8 @@ def test_sym_base_digit_tie(ctx, core, variant):
     S_q = K_q = 16: the coherent full-scale segments make their rounding error large, and at the
     largest in-bound S_q = K_q (38) it moves side digits of outputs near the segments (Table 1's
     bound is the one for the sequential time-domain sum); the ties are there at any S_q."""
-    N, Wb = 65, 1024
-    s, k, ends = _tie_case(N=N, Wb=Wb)
+    N, Wb = 65, (2048 if variant == apx.FFT_GROUP else 1024)  # the group core's smallest block
+    s, k, ends = _tie_case(L=20000 * Wb // 1024, N=N, Wb=Wb)
     S = 16 if core == "fft" else O.max_q(O.SYM, N)
     _say("case: symmetric base-digit tie", core, variant, "S=K=", S, "ends", ends)
     got, fields, info = _run_fixed(ctx, s, k, Wb, O.SYM, core, S, S, variant=variant)
