@@ -73,8 +73,7 @@ typedef struct {
     double calib_db;      /* APX_AUTO_SNR: offset added to the model SNR (apx_calibrate) */
     int32_t allow_unsafe; /* 1: accept R_max beyond the bound (unpacking may then be wrong) */
     int32_t fft_variant;  /* FFT core implementation: 0 = automatic (the autotuner's entry for
-                             the shape if there is one, else the group core when a packed mode
-                             can occur and the one-wave core for FP32 alone, where the sizes are
+                             the shape if there is one, else 3, else 2, where the sizes are
                              supported, else 1), 1 = one 256-thread workgroup per block with LDS
                              passes, 2 = one wavefront per block, 3 = a group of 512-point
                              wavefront transforms per block (2 and 3: supported sizes only) */
@@ -196,7 +195,9 @@ apx_status apx_run_auto_noalloc(apx_ctx ctx, apx_kernel kern, const float* s_in,
  * at the three smallest power-of-two block sizes with W >= 2 N; times each on a synthetic signal
  * of L_hint samples (0: 64 blocks, at least 2^16 samples; the number of blocks a call has decides
  * how much parallelism each core finds, so tune for the length you run) on `stream`, in three
- * rounds that visit every candidate in turn, each candidate keeping its fastest round; records the
+ * rounds that visit every candidate in turn, each candidate keeping its fastest round (the runs
+ * rotate over up to 16 copies of the signal, at most 512 MiB, so that inputs come from HBM rather
+ * than the last-level cache); records the
  * fastest in the context's table
  * (used by apx_kernel_create for this shape from then on) and in the table file
  * (APX_TUNE_FILE, else $HOME/.cache/apx_tune.txt; entries of other architectures are kept),

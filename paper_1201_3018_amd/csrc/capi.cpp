@@ -522,12 +522,10 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         if (ok && p.fft_variant != 1) {
             // modes that are not used may take any size, except the FP32 slot (W_block <= 2 M):
             // look for a compiled set that matches (the launch needs a complete set).  Automatic
-            // choice: the group core first when a packed mode can occur (C2, asymmetric M=2:
-            // 28 vs 30 us; per-block choice at 40 dB: 29 vs 32 us), the one-wave core first for
-            // FP32 alone (24 vs 25 us)
+            // choice: the group core first (C2: asymmetric M=2 25 vs 30 us, per-block choice at
+            // 40 dB 27 vs 32 us, FP32 23.4 vs 24.3 us), then the one-wave core
             const int cand[4] = {512, 1024, 1536, 2048};
-            const bool packed = k->use[MD_SYM] || k->use[MD_ASYM2] || k->use[MD_ASYM3];
-            int order[2] = {packed ? 0 : 1, packed ? 1 : 0};  // 0 = group, 1 = one wave
+            int order[2] = {0, 1};  // 0 = group, 1 = one wave
             int npass = 2;
             if (p.fft_variant == 2 || p.fft_variant == 3) {
                 order[0] = p.fft_variant == 3 ? 0 : 1;

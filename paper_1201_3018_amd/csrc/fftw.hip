@@ -791,7 +791,8 @@ hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipSt
 // run as one pass over column pairs.  The window goes to LDS with its statistics, every wave
 // packs its own decimated points, and the words of the inverse go to LDS, from which
 // consecutive threads unpack consecutive outputs.  Blocks are spread over more waves than one
-// wave per block gives, which hides memory and LDS latency behind other waves' arithmetic.
+// wave per block gives, which hides memory and LDS latency behind other waves' arithmetic; the
+// first wave makes the block's mode choice and hands it to the others through LDS.
 // ------------------------------------------------------------------------------------------
 
 // A value every lane of the wave holds equally, moved to scalar registers (frees vector registers
@@ -1286,8 +1287,13 @@ struct GroupShape {
     static constexpr bool has(int m) { return (MASK >> m) & 1; }
     static constexpr int mx(int x, int y) { return x > y ? x : y; }
     static constexpr size_t mxs(size_t x, size_t y) { return x > y ? x : y; }
-    static constexpr int NW = mx(mx(has(MD_SYM) ? RS_ : 1, has(MD_ASYM2) ? RA2_ : 1),
-                                 mx(has(MD_ASYM3) ? RA3_ : 1, has(MD_FULL32) ? RF_ : 1));
+    // waves: four, whatever the modes' R (at most 4): the waves without a region of their own
+    // still share the window load, the fused pass over column pairs (one pair per thread when
+    // MS / 2 = 256) and the unpacking, and the wider group balances those passes
+    static constexpr int RMAX = mx(mx(has(MD_SYM) ? RS_ : 1, has(MD_ASYM2) ? RA2_ : 1),
+                                   mx(has(MD_ASYM3) ? RA3_ : 1, has(MD_FULL32) ? RF_ : 1));
+    static_assert(RMAX <= 4, "at most four wave transforms per block");
+    static constexpr int NW = 4;
     // regions of the transforms, or the words of the inverse (2 M words), per mode
     template <int M, int R, typename T>
     static constexpr size_t mode_bytes() {
@@ -1323,7 +1329,15 @@ __global__ void __launch_bounds__((64 * GroupShape<MS_, RS_, MA2_, RA2_, MA3_, R
     st.smax = uni_d(st.smax);
     st.sumsq = uni_d(st.sumsq);
     st.nonfinite = uni_i(st.nonfinite);
-    WChoice c = wave_choose(a, st, cin);
+    // the first wave makes the block's choice and hands it to the others through LDS (the same
+    // arithmetic in every wave would cost each SIMD the VALU time of all of them)
+    __shared__ WChoice chosen;
+    if (threadIdx.x < 64) {
+        const WChoice c0 = wave_choose(a, st, cin);
+        if (threadIdx.x == 0) chosen = c0;
+    }
+    __syncthreads();
+    WChoice c = chosen;
     c.mode = uni_i(c.mode);
     c.S = uni_i(c.S);
     c.K = uni_i(c.K);

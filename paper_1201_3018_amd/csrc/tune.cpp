@@ -180,11 +180,19 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
     const int32_t wb_max = blocks.back();
     const int64_t L = L_hint > 0 ? L_hint : std::max<int64_t>((int64_t)64 * (wb_max - N_odd - 1), 1 << 16);
     const std::vector<float> hs = test_signal(L);
+    // the timed runs rotate over copies of the signal and outputs that together exceed the
+    // device's last-level cache (256 MiB on MI355X), so that inputs come from HBM as they do
+    // in a real stream of calls
+    const int64_t one = (int64_t)(2 * L + N - 1) * 4;
+    const int nbuf = (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)512 << 20) / one));
     float *s = nullptr, *o = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipMalloc((void**)&s, (size_t)L * 4);
-    if (e == hipSuccess) e = hipMalloc((void**)&o, (size_t)(L + N - 1) * 4);
-    if (e == hipSuccess) e = hipMemcpy(s, hs.data(), (size_t)L * 4, hipMemcpyHostToDevice);
+    hipError_t e = hipMalloc((void**)&s, (size_t)L * 4 * nbuf);
+    if (e == hipSuccess) e = hipMalloc((void**)&o, (size_t)(L + N - 1) * 4 * nbuf);
+    for (int b = 0; b < nbuf && e == hipSuccess; ++b)
+        e = hipMemcpy(s + (size_t)L * b, hs.data(), (size_t)L * 4, hipMemcpyHostToDevice);
+    auto sig = [&](int i) { return s + (size_t)L * (i % nbuf); };
+    auto res = [&](int i) { return o + (size_t)(L + N - 1) * (i % nbuf); };
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     apx_tuned best{};
@@ -215,7 +223,7 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
             apx_kernel kern = nullptr;
             if (apx_kernel_create(ctx, k, N, op, wb, &p, stream, &kern) != APX_OK) continue;  // cannot run it
             bool ok = true;
-            for (int i = 0; i < 2 && ok; ++i) ok = apx_run(ctx, kern, s, L, o, nullptr, stream) == APX_OK;
+            for (int i = 0; i < 2 && ok; ++i) ok = apx_run(ctx, kern, sig(i), L, res(i), nullptr, stream) == APX_OK;
             if (!ok) {
                 apx_kernel_destroy(kern);
                 continue;
@@ -224,12 +232,16 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
         }
     }
     constexpr int ROUNDS = 3, REPS = 5;
+    int turn = 0;
     for (int round = 0; round < ROUNDS; ++round) {
         for (Cand& c : cands) {
             if (!c.kern) continue;
             float ms = 0.0f;
             bool ok = hipEventRecord(e0, st) == hipSuccess;
-            for (int i = 0; i < REPS && ok; ++i) ok = apx_run(ctx, c.kern, s, L, o, nullptr, stream) == APX_OK;
+            for (int i = 0; i < REPS && ok; ++i) {
+                ok = apx_run(ctx, c.kern, sig(turn), L, res(turn), nullptr, stream) == APX_OK;
+                ++turn;
+            }
             ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                  hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
             if (!ok) {  // drop the candidate
