@@ -334,7 +334,8 @@ def bench_c1(args, wl):
     tk = torch.from_numpy(k).to(dev)
     N_odd, W, P = apx.apx_geometry(L, N, Wb)
     outputs = n * (L + N - 1)
-    bytes_alg = n * (P * Wb * 4 + (L + N - 1) * 4)
+    bytes_alg = n * (L * 4 + (L + N - 1) * 4)        # compulsory: every sample read once, every output written once
+    bytes_win = n * (P * Wb * 4 + (L + N - 1) * 4)   # every window read whole
 
     def timed(kh, steps, warmup):
         manys = [apx.Many(kh, [ins[j][i] for i in range(n)]) for j in range(sets)]
@@ -394,7 +395,8 @@ def bench_c1(args, wl):
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic("c1"),
                      "bytes_per_launch": bytes_alg, "bytes_per_output": round(bytes_alg / outputs, 3),
-                     "kernel": desc},
+                     "window_bytes_per_launch": bytes_win,
+                     "window_bytes_GBs": round(bytes_win / (ms_packed * 1e-3) / 1e9, 1), "kernel": desc},
         "packed_fp64_time_domain": {"ms_per_step": ms_td, "value": outputs / (ms_td * 1e-3),
                                     "outputs_equal_default_core": same_td},
         "full_fp32": {"ms_per_step": ms_full, "value": outputs / (ms_full * 1e-3),
@@ -403,6 +405,8 @@ def bench_c1(args, wl):
         "full_fp32_kernel": full.describe(),
         "snr_db": {"min": float(np.min(snrs)), "sampled_signals": 4},
     }
+    if args.copy_probe:
+        res["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu:
         import oracle as O
         t0 = time.perf_counter()
@@ -1129,7 +1133,8 @@ def bench_calib(args, wl):
 
 # rocprofv3 counter summary per workload and the kernel sources its figures hold for
 TRAFFIC_SUMMARIES = {"c2": ("fft_c2_hbm_counters.md", ("fftw.hip", "fft.h", "internal.h")),
-                     "c3": ("batch_c3_hbm_counters.md", ("kernels.hip", "fft.h", "internal.h"))}
+                     "c3": ("batch_c3_hbm_counters.md", ("kernels.hip", "fft.h", "internal.h")),
+                     "c1": ("int8_c1_hbm_counters.md", ("kernels.hip", "items.h", "internal.h"))}
 
 
 def measured_traffic(workload: str):
