@@ -156,7 +156,7 @@ def _check(st: int):
         raise ApxError(st, lib().apx_last_error().decode(errors="replace"))
 
 
-FFT_AUTO, FFT_BLOCK, FFT_WAVE, FFT_GROUP = 0, 1, 2, 3
+FFT_AUTO, FFT_BLOCK, FFT_WAVE, FFT_GROUP, FFT_MULTIPASS = 0, 1, 2, 3, 4
 
 
 def params(mode=APX_FULL_FP32, core=APX_CORE_AUTO, Sq=0, Kq=0, snr_min_db=0.0, calib_db=float("nan"),

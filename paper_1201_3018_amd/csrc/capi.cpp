@@ -89,6 +89,9 @@ apx_status dalloc(apx_kernel k, T** p, size_t n) {
 void free_kernel(apx_kernel k) {
     for (void* p : k->allocs) (void)hipFree(p);
     k->allocs.clear();
+    if (k->big_scr) (void)hipFree(k->big_scr);
+    k->big_scr = nullptr;
+    k->big_scr_bytes = 0;
 }
 
 apx_status build_twiddles(apx_ctx c) {
@@ -266,7 +269,41 @@ RunArgs make_args(apx_kernel k, const float* s, int64_t L, float* out, double* f
     return a;
 }
 
+// The multi-pass FFT core: its per-item scratch (grown here to the signal's items; the
+// allocation waits for the device), then its passes.
+apx_status launch_big_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
+    if (a.many) return fail(APX_E_UNSUPPORTED, "the multi-pass FFT core runs one signal per launch");
+    if (a.nitems > 65535) return fail(APX_E_UNSUPPORTED, "the multi-pass FFT core runs at most 65535 blocks");
+    const int MW = 1 << k->big_logmw, F1 = 1 << (k->big_logmw / 2);
+    const bool fp32 = k->params.mode == APX_FULL_FP32;
+    const size_t pts = (size_t)a.nitems * MW * (fp32 ? sizeof(float2) : sizeof(double2));
+    const size_t need = pts + (size_t)a.nitems * big_item_bytes();
+    if (need > k->big_scr_bytes) {
+        if (k->big_scr) HIPCHK(hipFree(k->big_scr));
+        k->big_scr = nullptr;
+        k->big_scr_bytes = 0;
+        HIPCHK(hipMalloc(&k->big_scr, need));
+        k->big_scr_bytes = need;
+    }
+    double2 *d1 = nullptr, *d2 = nullptr, *dm = nullptr, *dF = nullptr;
+    float2 *f1 = nullptr, *f2 = nullptr, *fm = nullptr, *fF = nullptr;
+    apx_status r = get_table(k->ctx, F1, &d1, &f1);
+    if (r == APX_OK) r = get_table(k->ctx, MW / F1, &d2, &f2);
+    if (r == APX_OK) r = get_table(k->ctx, MW, &dm, &fm);
+    if (r == APX_OK) r = get_table(k->ctx, 2 * MW, &dF, &fF);
+    if (r != APX_OK) return r;
+    const int m = k->params.mode;
+    const void* H = fp32 ? (const void*)k->spec32 : (const void*)k->spec[m];
+    char* items = (char*)k->big_scr + pts;
+    if (fp32)
+        HIPCHK(launch_big(a, MD_FULL32, k->big_logmw, items, k->big_scr, f1, f2, fm, fF, H, st));
+    else
+        HIPCHK(launch_big(a, m, k->big_logmw, items, k->big_scr, d1, d2, dm, dF, H, st));
+    return APX_OK;
+}
+
 apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
+    if (k->core == APX_CORE_FFT && k->big_logmw) return launch_big_kernel(k, a, st);
     if (k->core == APX_CORE_INT8) {
         HIPCHK(launch_i8(a, k->i8frag, k->S[k->params.mode] > 127, k->i8_splitk, k->i8_plane, st));
     } else if (k->core == APX_CORE_FFT && k->group) {
@@ -490,7 +527,20 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         // T + N - 1 (asymmetric), at the shortest power of two that holds them
         const bool fixed_packed = p.mode >= APX_SYM && p.mode <= APX_ASYM3;
         int own_logw = 0;
-        if (fixed_packed) {
+        // the multi-pass core: asked for (fft_variant 4), or a fixed mode / FP32 whose words
+        // exceed the one-workgroup transforms
+        const int big_words = fixed_packed ? ((p.mode == MD_SYM) ? W_block / 2 : k->T[p.mode] + N_odd - 1)
+                                           : (p.mode == APX_FULL_FP32 ? W_block : 0);
+        if (big_words > 0 && (p.fft_variant == 4 || ceil_log2(big_words) > fft_max_logF())) {
+            const int logmw = std::max(ceil_log2(big_words), 1) - 1;
+            if (!big_supported(logmw))
+                return fail(APX_E_UNSUPPORTED, "FFT core: %d words per block (multi-pass transforms of %d to %d words)",
+                            big_words, 2 << BIG_LOGMW_MIN, 2 << BIG_LOGMW_MAX);
+            k->big_logmw = logmw;
+            for (int m = 0; m < 4; ++m) k->Fw[m] = 2 << logmw;
+        } else if (p.fft_variant == 4) {
+            return fail(APX_E_UNSUPPORTED, "the multi-pass FFT core runs a fixed packed mode or FP32");
+        } else if (fixed_packed) {
             const int words = (p.mode == MD_SYM) ? W_block / 2 : k->T[p.mode] + N_odd - 1;
             own_logw = std::max(ceil_log2(words), fft_min_logF() - 1);
             if (own_logw > fft_max_logF() || !fft1_supported(p.mode, own_logw - 1))
@@ -499,14 +549,14 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         } else if (k->logF > fft_max_logF()) {
             return fail(APX_E_UNSUPPORTED, "FFT core supports W_block <= %d", 1 << fft_max_logF());
         }
-        if (k->logF <= fft_max_logF()) {
+        if (k->logF <= fft_max_logF() && !k->big_logmw) {
             const int F = 1 << k->logF;
             k->Fw[0] = F;
             k->Fw[MD_SYM] = F / 2;
             k->Fw[MD_ASYM2] = F;
             k->Fw[MD_ASYM3] = F;
         }
-        if (fixed_packed) {
+        if (fixed_packed && !k->big_logmw) {
             k->fft1_logmw = own_logw - 1;
             k->Fw[p.mode] = 1 << own_logw;
         }
@@ -519,6 +569,7 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             if (k->use[m] && wm[m] == 0) ok = false;
         }
         if (wm[0] == 0) ok = false;  // the FP32 size also sizes the window in LDS
+        if (k->big_logmw) ok = false;
         if (ok && p.fft_variant != 1) {
             // modes that are not used may take any size, except the FP32 slot (W_block <= 2 M):
             // look for a compiled set that matches (the launch needs a complete set).  Automatic
@@ -601,6 +652,17 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             if (r == APX_OK && k->group) r = table(group_sub_points(k->wM[1], k->wM[2], k->wM[3], k->wM[0], m));
         }
     }
+    if (r == APX_OK && core == APX_CORE_FFT && k->big_logmw) {
+        // twiddles of the two transform lengths, of the inter-pass step and of the real split
+        const int MW = 1 << k->big_logmw, F1 = 1 << (k->big_logmw / 2);
+        for (int F : {F1, MW / F1, MW, 2 * MW}) {
+            if (r != APX_OK) break;
+            if (!k->plan_only) r = get_table(ctx, F, nullptr, nullptr);
+            else if (!ctx->tables.count(F) &&
+                     std::find(k->plan_tables.begin(), k->plan_tables.end(), F) == k->plan_tables.end())
+                k->plan_tables.push_back(F);
+        }
+    }
     if (r == APX_OK && core == APX_CORE_INT8) r = dalloc(k, &k->i8frag, (size_t)2 * i8_kpad(N_odd) * 64 * 4);
     if (r != APX_OK) {
         free_kernel(k);
@@ -610,7 +672,14 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
     hipError_t e = launch_prepare_kernel(k_in, N, N_odd, op == APX_XCORR, k->ks, k->kf, k->kd, k->kf_pad + 8,
                                          k->kq[MD_SYM], k->kq[MD_ASYM2], k->kq[MD_ASYM3], k->K, k->R,
                                          k->kq_pad[MD_SYM] + 8, k->kq_pad[MD_ASYM2] + 8, st);
-    if (e == hipSuccess && core == APX_CORE_FFT && !k->wave) {
+    if (e == hipSuccess && core == APX_CORE_FFT && k->big_logmw) {
+        // the multi-pass core's spectrum of its one mode, by a direct DFT in FP64
+        double2* tF = nullptr;
+        get_table(ctx, k->Fw[0], &tF, nullptr);
+        for (int m = MD_SYM; m <= MD_ASYM3 && e == hipSuccess; ++m)
+            if (k->use[m]) e = launch_big_spectrum(k->kq[m], k->kq_len[m], k->Fw[m], tF, k->spec[m], false, st);
+        if (e == hipSuccess && k->use[0]) e = launch_big_spectrum(k->kd, N_odd, k->Fw[0], tF, k->spec32, true, st);
+    } else if (e == hipSuccess && core == APX_CORE_FFT && !k->wave) {
         for (int m = MD_SYM; m <= MD_ASYM3 && e == hipSuccess; ++m)
             if (k->use[m]) e = launch_spectrum(k->kq[m], k->kq_len[m], k->Fw[m], ctx->twd, k->spec[m], st);
         if (e == hipSuccess && k->use[0]) e = launch_spectrum32(k->kf, N_odd, k->Fw[0], ctx->twf, k->spec32, st);
@@ -633,7 +702,7 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
         const size_t lds = i8_lds_bytes(k->i8_plane, W_block);
         if (e == hipSuccess && lds > 65536) e = i8_set_lds((int)lds);
     }
-    if (e == hipSuccess && core == APX_CORE_FFT && !k->wave && fft_words == 0)
+    if (e == hipSuccess && core == APX_CORE_FFT && !k->wave && !k->big_logmw && fft_words == 0)
         e = k->fft1_logmw > 0 ? fft1_set_lds(p.mode, k->fft1_logmw) : fft_set_lds(k->logF);
     if (e != hipSuccess) {
         free_kernel(k);
@@ -874,6 +943,9 @@ apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {
         n = snprintf(tmp, sizeof tmp, "core=fft kernel=%s<%d,%d,%d,%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d",
                      k->group ? "k_fftg" : "k_fftw", k->wM[1], k->wM[2], k->wM[3], k->wM[0], 2 * k->wM[0],
                      2 * k->wM[1], 2 * k->wM[2], 2 * k->wM[3]);
+    } else if (k->big_logmw > 0) {
+        n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_big<mode %d, %d x %d points> words=%d", k->params.mode,
+                     1 << (k->big_logmw / 2), 1 << (k->big_logmw - k->big_logmw / 2), 2 << k->big_logmw);
     } else if (k->fft1_logmw > 0) {
         n = snprintf(tmp, sizeof tmp, "core=fft kernel=k_fft1<mode %d, %d points> words=%d", k->params.mode,
                      1 << k->fft1_logmw, k->Fw[k->params.mode]);
@@ -946,6 +1018,7 @@ apx_status apx_many_create(apx_ctx ctx, apx_kernel k, int32_t n, const float* co
     if (!ctx || !k || !s || !L || !r_out) return fail(APX_E_INVALID, "null argument");
     if (n < 1) return fail(APX_E_INVALID, "n = %d signals", n);
     if (k->ctx != ctx) return fail(APX_E_INVALID, "the kernel belongs to another context");
+    if (k->big_logmw) return fail(APX_E_UNSUPPORTED, "the multi-pass FFT core runs one signal per launch");
     std::vector<RunArgs> ha((size_t)n);
     int64_t total = 0;
     for (int32_t i = 0; i < n; ++i) {

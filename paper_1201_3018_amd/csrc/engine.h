@@ -104,6 +104,12 @@ struct apx_kernel_s {
     int32_t wM[4] = {0, 0, 0, 0};  // complex points per mode (0 = FP32)
     double2* coef[4] = {nullptr, nullptr, nullptr, nullptr};
     float2* coef32 = nullptr;
+    // multi-pass FFT core (transforms beyond one workgroup's LDS): 2^big_logmw complex points per
+    // block, its kernel spectrum, and a per-item scratch grown to the longest signal run so far
+    int big_logmw = 0;
+    void* big_spec = nullptr;
+    void* big_scr = nullptr;
+    size_t big_scr_bytes = 0;
     std::vector<void*> allocs;
     size_t dev_bytes = 0;  // device memory owned by (or carved for) this kernel
     // device buffers carved from a caller-owned pool instead of hipMalloc (batched pairs)

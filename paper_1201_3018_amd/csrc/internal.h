@@ -116,6 +116,15 @@ hipError_t launch_fftw(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipSt
 bool group_supported(int ms, int ma2, int ma3, int mf);
 int group_sub_points(int ms, int ma2, int ma3, int mf, int mode);
 hipError_t launch_fftg(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st);
+// multi-pass FFT core (kernels.hip): transforms of 2^logmw complex points per block,
+// BIG_LOGMW_MIN <= logmw <= BIG_LOGMW_MAX, through a device scratch of 2^logmw points per item
+constexpr int BIG_LOGMW_MIN = 10, BIG_LOGMW_MAX = 15;
+bool big_supported(int logmw);
+size_t big_item_bytes();
+hipError_t launch_big_spectrum(const double* h, int32_t nh, int32_t F, const double2* twF, void* spec, bool fp32,
+                               hipStream_t st);
+hipError_t launch_big(const RunArgs& a, int mode, int logmw, void* items, void* scratch, const void* twF1,
+                      const void* twF2, const void* twMW, const void* twF, const void* H, hipStream_t st);
 hipError_t launch_coef(const double* h, int32_t nh, int32_t M, const double2* twF, double2* coef, hipStream_t st);
 hipError_t launch_coef32(const double* h, int32_t nh, int32_t M, const double2* twF, float2* coef, hipStream_t st);
 int fft_max_logF();

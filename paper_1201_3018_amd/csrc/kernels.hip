@@ -940,6 +940,397 @@ hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st) {
 }
 
 
+// ------------------------------------------------------------------------------------------
+// Multi-pass FFT core: blocks whose transform exceeds one workgroup's LDS (fixed packed modes
+// and FP32).  The MW = F1 F2 complex points of an item are transformed in four steps through a
+// device scratch of MW points per item, with index n = n1 F2 + n2 and k = k1 + F1 k2:
+//   columns: pack z[n], DFT over n1 (length F1), twiddle W_MW^(n2 k1)      -> scratch (k1, n2)
+//   rows:    DFT over n2 (length F2): X[k1 + F1 k2]; the spectral step pairs row k1 with row
+//            (F1 - k1) mod F1 (reversed), so one workgroup takes both; inverse DFT over k2,
+//            twiddle W_MW^-(n2 k1)                                          -> scratch (k1, n2)
+//   columns: inverse DFT over k1: the words of the cyclic convolution at n; unpack (the
+//            symmetric mode writes the words and a last pass unpacks them).
+// The transforms are radix-2 passes in LDS over several independent sequences at a time.
+// ------------------------------------------------------------------------------------------
+constexpr int BIG_TC = 16;  // columns per workgroup of the column passes
+
+// buf[i C + c], c < C: C sequences of Fn points.  DIT takes bit-reversed input and leaves natural
+// order; DIF takes natural order and leaves bit-reversed order.  tw: W_Fn^t, t < Fn.
+template <typename T, int Fn, int C, bool INV>
+__device__ __forceinline__ void big_fft_dit(cx<T>* buf, const typename tw_of<T>::type* tw) {
+    for (int h = 1; h < Fn; h *= 2) {
+        for (int e = threadIdx.x; e < (Fn / 2) * C; e += NT) {
+            const int c = e % C, b = e / C;
+            const int j = b & (h - 1), base = 2 * (b - j);
+            const auto w = tw[j * (Fn / (2 * h))];
+            const cx<T> wc = {w.x, INV ? -w.y : w.y};
+            const cx<T> u = buf[(base + j) * C + c], v = cmul(buf[(base + j + h) * C + c], wc);
+            buf[(base + j) * C + c] = u + v;
+            buf[(base + j + h) * C + c] = u - v;
+        }
+        __syncthreads();
+    }
+}
+template <typename T, int Fn, int C, bool INV>
+__device__ __forceinline__ void big_fft_dif(cx<T>* buf, const typename tw_of<T>::type* tw) {
+    for (int h = Fn / 2; h >= 1; h /= 2) {
+        for (int e = threadIdx.x; e < (Fn / 2) * C; e += NT) {
+            const int c = e % C, b = e / C;
+            const int j = b & (h - 1), base = 2 * (b - j);
+            const auto w = tw[j * (Fn / (2 * h))];
+            const cx<T> wc = {w.x, INV ? -w.y : w.y};
+            const cx<T> u = buf[(base + j) * C + c], v = buf[(base + j + h) * C + c];
+            buf[(base + j) * C + c] = u + v;
+            buf[(base + j + h) * C + c] = cmul(u - v, wc);
+        }
+        __syncthreads();
+    }
+}
+template <int BITS>
+__device__ __forceinline__ int big_brev(int i) {
+    return (int)(__builtin_bitreverse32((uint32_t)i) >> (32 - BITS));
+}
+
+struct BigItem {
+    Choice c;
+    int32_t run;  // 1: the item needs the transforms; 0: its outputs are written already
+    int32_t pad;
+};
+
+struct BigArgs {
+    RunArgs a;
+    BigItem* bi;       // one per item
+    void* scr;         // MW complex points per item (double2, or float2 for FP32)
+    const void* twF1;  // W_F1^t, W_F2^t, W_MW^t, W_2MW^t tables (double2, or float2 for FP32)
+    const void* twF2;
+    const void* twMW;
+    const void* twF;
+    const void* H;     // kernel spectrum H'[k] = H[k] / (4 MW), k <= MW
+};
+
+// Statistics, choice and the outputs of the items that need no arithmetic.
+__global__ void __launch_bounds__(NT) k_big_stats(RunArgs a, BigItem* bi) {
+    const int64_t item = blockIdx.x;
+    const Item it = make_item(a, item, true);
+    const BlockStats st = block_stats(a.s, it.start, it.nwin);
+    const Choice c = choose(a, st);
+    write_info(a, it, c, st, item < a.P);
+    int run = 1;
+    if (c.flags & APX_FLAG_NONFINITE) {
+        fill_block(a, it, NAN);
+        run = 0;
+    } else if ((c.flags & APX_FLAG_ZERO) && c.mode != MD_FULL32) {
+        fill_block(a, it, 0.0f);
+        run = 0;
+    } else if (it.j_hi <= it.j_lo) {
+        run = 0;
+    }
+    if (threadIdx.x == 0) {
+        bi[item].c = c;
+        bi[item].run = run;
+    }
+}
+
+// Complex point n of the item's packed sequence (as fft_item packs it).
+template <int MODE>
+__device__ __forceinline__ cx<typename std::conditional<MODE == MD_FULL32, float, double>::type> big_point(
+    const RunArgs& a, const Item& it, const Choice& c, int n) {
+    if constexpr (MODE == MD_FULL32) {
+        const int i0 = 2 * n;
+        return {(i0 < it.nvalid) ? a.s[it.start + i0] : 0.0f, (i0 + 1 < it.nvalid) ? a.s[it.start + i0 + 1] : 0.0f};
+    } else if constexpr (MODE == MD_SYM) {
+        const double eps = 1.0 / (2.0 * (double)c.R);
+        const int i0 = 4 * n;
+        return {sq_at(a, it, c.cs, i0) + eps * sq_at(a, it, c.cs, i0 + 1),
+                sq_at(a, it, c.cs, i0 + 2) + eps * sq_at(a, it, c.cs, i0 + 3)};
+    } else {
+        constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
+        const double eps = 1.0 / (2.0 * (double)c.R);
+        const bool prefix = it.j_lo == 0;
+        const int N = a.N;
+        const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+        const int base_off = it.j_lo - (N - 1);
+        const int lw = Tit + N - 1;
+        double v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int m = 2 * n + h;
+            double acc = 0.0;
+            if (m < lw) {
+                double e = 1.0;
+#pragma unroll
+                for (int q = 0; q < MM; ++q) {
+                    acc += e * sq_at(a, it, c.cs, base_off + q * Tit + m);
+                    e *= eps;
+                }
+            }
+            v[h] = acc;
+        }
+        return {v[0], v[1]};
+    }
+}
+
+// Column passes.  INV = false: pack, DFT over n1, twiddle, store (k1, n2).  INV = true: inverse
+// DFT over k1 of (k1, n2), then the words at n = n1 F2 + n2: unpacked (FP32, asymmetric modes)
+// or stored back at n (symmetric mode).
+template <int MODE, int LOGMW, bool INV>
+__global__ void __launch_bounds__(NT) k_big_cols(BigArgs g) {
+    using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+    using T2 = typename tw_of<T>::type;
+    constexpr int MW = 1 << LOGMW, L1 = LOGMW / 2, F1 = 1 << L1, F2 = MW / F1, C = BIG_TC;
+    static_assert(F2 % C == 0, "whole column tiles");
+    const RunArgs& a = g.a;
+    const int64_t item = blockIdx.y;
+    const BigItem* b = g.bi + item;
+    if (!b->run) return;
+    const Choice c = b->c;
+    const Item it = make_item(a, item, true);
+    __shared__ cx<T> buf[F1 * C];
+    cx<T>* scr = reinterpret_cast<cx<T>*>(g.scr) + (size_t)item * MW;
+    const T2* tw1 = reinterpret_cast<const T2*>(g.twF1);
+    const T2* twm = reinterpret_cast<const T2*>(g.twMW);
+    const int n2_0 = blockIdx.x * C;
+    if constexpr (!INV) {
+        for (int e = threadIdx.x; e < F1 * C; e += NT) {
+            const int n1 = e / C, cc = e % C;
+            buf[big_brev<L1>(n1) * C + cc] = big_point<MODE>(a, it, c, n1 * F2 + n2_0 + cc);
+        }
+        __syncthreads();
+        big_fft_dit<T, F1, C, false>(buf, tw1);
+        for (int e = threadIdx.x; e < F1 * C; e += NT) {
+            const int k1 = e / C, cc = e % C, n2 = n2_0 + cc;
+            const T2 w = twm[k1 * n2];  // W_MW^(k1 n2), k1 n2 < MW
+            scr[k1 * F2 + n2] = cmul(buf[k1 * C + cc], cx<T>{w.x, w.y});
+        }
+    } else {
+        for (int e = threadIdx.x; e < F1 * C; e += NT) {
+            const int k1 = e / C, cc = e % C;
+            buf[k1 * C + cc] = scr[k1 * F2 + n2_0 + cc];
+        }
+        __syncthreads();
+        big_fft_dif<T, F1, C, true>(buf, tw1);
+        // position p holds n1 = brev(p)
+        if constexpr (MODE == MD_SYM) {
+            for (int e = threadIdx.x; e < F1 * C; e += NT) {
+                const int p = e / C, cc = e % C;
+                scr[big_brev<L1>(p) * F2 + n2_0 + cc] = buf[p * C + cc];
+            }
+        } else if constexpr (MODE == MD_FULL32) {
+            StoreSink sk;
+            for (int e = threadIdx.x; e < F1 * C; e += NT) {
+                const int p = e / C, cc = e % C;
+                const int n = big_brev<L1>(p) * F2 + n2_0 + cc;
+                const cx<T> v = buf[p * C + cc];
+                if (2 * n >= it.j_lo && 2 * n < it.j_hi) sk.put32(a, it, 2 * n, (float)v.x);
+                if (2 * n + 1 >= it.j_lo && 2 * n + 1 < it.j_hi) sk.put32(a, it, 2 * n + 1, (float)v.y);
+            }
+        } else {
+            constexpr int MM = (MODE == MD_ASYM2) ? 2 : 3;
+            const int N = a.N;
+            const bool prefix = it.j_lo == 0;
+            const int Tit = prefix ? (N + 1 + MM - 1) / MM : a.T[MODE];
+            const int base_off = it.j_lo - (N - 1);
+            const int lw = Tit + N - 1;
+            const double two_r = (double)(2 * c.R);
+            for (int e = threadIdx.x; e < 2 * F1 * C; e += NT) {
+                const int p = e / (2 * C), r = e % (2 * C), cc = r >> 1, h = r & 1;
+                const int m = 2 * (big_brev<L1>(p) * F2 + n2_0 + cc) + h;  // word
+                if (m < N - 1 || m >= lw) continue;
+                const cx<T> v = buf[p * C + cc];
+                double x = h ? (double)v.y : (double)v.x;
+#pragma unroll
+                for (int q = 0; q < MM; ++q) {
+                    const double d = rint(x);
+                    x = (x - d) * two_r;
+                    const int j = base_off + q * Tit + m;
+                    if (j >= it.j_lo && j < it.j_hi) put(a, it, j, d, c.inv);
+                }
+            }
+        }
+    }
+}
+
+// Row pairs: workgroup p takes rows p and F1 - p (p = 1 .. F1/2 - 1), workgroup 0 the rows 0 and
+// F1/2, each of which pairs with itself.
+template <int MODE, int LOGMW>
+__global__ void __launch_bounds__(NT) k_big_rows(BigArgs g) {
+    using T = typename std::conditional<MODE == MD_FULL32, float, double>::type;
+    using T2 = typename tw_of<T>::type;
+    constexpr int MW = 1 << LOGMW, L1 = LOGMW / 2, F1 = 1 << L1, L2 = LOGMW - L1, F2 = 1 << L2;
+    const int64_t item = blockIdx.y;
+    if (!g.bi[item].run) return;
+    const int pr = blockIdx.x;
+    const int row[2] = {pr, pr == 0 ? F1 / 2 : F1 - pr};
+    __shared__ cx<T> buf[2 * F2];
+    cx<T>* scr = reinterpret_cast<cx<T>*>(g.scr) + (size_t)item * MW;
+    const T2* tw2 = reinterpret_cast<const T2*>(g.twF2);
+    const T2* twm = reinterpret_cast<const T2*>(g.twMW);
+    const T2* twF = reinterpret_cast<const T2*>(g.twF);
+    const T2* H = reinterpret_cast<const T2*>(g.H);
+    for (int e = threadIdx.x; e < 2 * F2; e += NT) {
+        const int cc = e / F2, n2 = e % F2;
+        buf[big_brev<L2>(n2) * 2 + cc] = scr[row[cc] * F2 + n2];
+    }
+    __syncthreads();
+    big_fft_dit<T, F2, 2, false>(buf, tw2);
+    // spectral step (as spectral_step) on the pair (k, MW - k), k the smaller index; element
+    // (k2, cc) holds X[row[cc] + F1 k2]
+    auto step = [&](int ka, int pa, int kb, int pb) {  // X[ka] at buf[pa], X[kb] at buf[pb], kb = (MW - ka) mod MW
+        if (ka > kb) {
+            const int t0 = ka, t1 = pa;
+            ka = kb;
+            pa = pb;
+            kb = t0;
+            pb = t1;
+        }
+        const cx<T> za = buf[pa], zb = buf[pb];
+        const T2 wt = twF[ka];
+        const cx<T> w = {wt.x, wt.y};
+        const cx<T> A = za + conj(zb);
+        const cx<T> Bd = za - conj(zb);
+        const cx<T> wB = cmul(w, Bd);
+        const cx<T> x_k = A - mul_i(wB);
+        const cx<T> x_mk = conj(A + mul_i(wB));
+        const T2 h0 = H[ka], h1 = H[MW - ka];
+        const cx<T> yk = cmul(x_k, cx<T>{h0.x, h0.y});
+        const cx<T> ymk = cmul(x_mk, cx<T>{h1.x, h1.y});
+        const cx<T> P = yk + conj(ymk);
+        const cx<T> Q = yk - conj(ymk);
+        const cx<T> cQ = mul_i(cmul(conj(w), Q));
+        buf[pa] = P + cQ;
+        if (ka != 0 && kb != ka) buf[pb] = conj(P - cQ);
+    };
+    if (pr != 0) {
+        // (row A, k2) pairs with (row B, F2 - 1 - k2)
+        for (int k2 = threadIdx.x; k2 < F2; k2 += NT)
+            step(row[0] + F1 * k2, k2 * 2 + 0, row[1] + F1 * (F2 - 1 - k2), (F2 - 1 - k2) * 2 + 1);
+    } else {
+        // row 0: (0, k2) with (0, (F2 - k2) mod F2); row F1/2: (F1/2, k2) with (F1/2, F2 - 1 - k2)
+        for (int k2 = threadIdx.x; k2 <= F2 / 2; k2 += NT) {
+            const int kb2 = (F2 - k2) & (F2 - 1);
+            step(F1 * k2, k2 * 2, F1 * kb2, kb2 * 2);
+        }
+        for (int k2 = threadIdx.x; k2 < F2 / 2; k2 += NT)
+            step(F1 / 2 + F1 * k2, k2 * 2 + 1, F1 / 2 + F1 * (F2 - 1 - k2), (F2 - 1 - k2) * 2 + 1);
+    }
+    __syncthreads();
+    big_fft_dif<T, F2, 2, true>(buf, tw2);
+    for (int e = threadIdx.x; e < 2 * F2; e += NT) {
+        const int cc = e / F2, pp = e % F2;
+        const int n2 = big_brev<L2>(pp);
+        const int k1 = row[cc];
+        const T2 w = twm[k1 * n2];
+        scr[k1 * F2 + n2] = cmul(buf[pp * 2 + cc], cx<T>{w.x, -w.y});
+    }
+}
+
+// Symmetric words at n (re: word 2n, im: word 2n + 1) -> outputs (as sym_unpack_store).
+template <int LOGMW>
+__global__ void __launch_bounds__(NT) k_big_sym_unpack(BigArgs g) {
+    constexpr int MW = 1 << LOGMW;
+    const RunArgs& a = g.a;
+    const int64_t item = blockIdx.y;
+    const BigItem* b = g.bi + item;
+    if (!b->run) return;
+    const Choice c = b->c;
+    const Item it = make_item(a, item, true);
+    const cx<double>* scr = reinterpret_cast<const cx<double>*>(g.scr) + (size_t)item * MW;
+    auto rbar = [&](int m) -> double {
+        if (m < 0) return 0.0;
+        const cx<double> v = scr[m >> 1];
+        return (m & 1) ? v.y : v.x;
+    };
+    const double two_r = (double)(2 * c.R), R = (double)c.R, inv_two_r = 1.0 / two_r;
+    const int m_lo = it.j_lo >> 1, m_hi = (it.j_hi + 1) >> 1;
+    for (int m = m_lo + (int)(blockIdx.x * NT + threadIdx.x); m < m_hi; m += (int)(NT * gridDim.x)) {
+        const SymDigits cur = sym_split(rbar(m), two_r, inv_two_r, R);
+        const int j0 = 2 * m, j1 = 2 * m + 1;
+        if (j0 >= it.j_lo && j0 < it.j_hi) {
+            const double de_prev = (m >= 1) ? sym_split(rbar(m - 1), two_r, inv_two_r, R).De : 0.0;
+            put(a, it, j0, cur.Dm + de_prev, c.inv);
+        }
+        if (j1 >= it.j_lo && j1 < it.j_hi) put(a, it, j1, cur.B, c.inv);
+    }
+}
+
+// H'[k] = (1 / (2F)) sum_n h[n] W_F^(n k), k <= F/2 (direct DFT in FP64, the table W_F^t).
+template <typename OUT2>
+__global__ void __launch_bounds__(NT) k_big_spectrum(const double* __restrict__ h, int32_t nh, int32_t F,
+                                                     const double2* __restrict__ twF, OUT2* spec) {
+    const int k = blockIdx.x * NT + threadIdx.x;
+    if (k > F / 2) return;
+    double re = 0.0, im = 0.0;
+    int idx = 0;
+    for (int n = 0; n < nh; ++n) {
+        const double2 w = twF[idx];
+        re = fma(h[n], w.x, re);
+        im = fma(h[n], w.y, im);
+        idx += k;
+        if (idx >= F) idx -= F;
+    }
+    const double sc = 1.0 / (2.0 * (double)F);
+    if constexpr (std::is_same<OUT2, double2>::value) spec[k] = make_double2(re * sc, im * sc);
+    else spec[k] = make_float2((float)(re * sc), (float)(im * sc));
+}
+
+hipError_t launch_big_spectrum(const double* h, int32_t nh, int32_t F, const double2* twF, void* spec, bool fp32,
+                               hipStream_t st) {
+    const unsigned grid = (unsigned)((F / 2 + 1 + NT - 1) / NT);
+    if (fp32) hipLaunchKernelGGL(k_big_spectrum<float2>, dim3(grid), dim3(NT), 0, st, h, nh, F, twF, (float2*)spec);
+    else hipLaunchKernelGGL(k_big_spectrum<double2>, dim3(grid), dim3(NT), 0, st, h, nh, F, twF, (double2*)spec);
+    return hipGetLastError();
+}
+
+bool big_supported(int logmw) { return logmw >= BIG_LOGMW_MIN && logmw <= BIG_LOGMW_MAX; }
+
+template <int MODE, int LOGMW>
+static hipError_t big_run(const BigArgs& g, hipStream_t st) {
+    constexpr int L1 = LOGMW / 2, F1 = 1 << L1, F2 = (1 << LOGMW) / F1;
+    const unsigned items = (unsigned)g.a.nitems;
+    hipLaunchKernelGGL(k_big_stats, dim3(items), dim3(NT), 0, st, g.a, g.bi);
+    hipLaunchKernelGGL((k_big_cols<MODE, LOGMW, false>), dim3(F2 / BIG_TC, items), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((k_big_rows<MODE, LOGMW>), dim3(F1 / 2, items), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((k_big_cols<MODE, LOGMW, true>), dim3(F2 / BIG_TC, items), dim3(NT), 0, st, g);
+    if constexpr (MODE == MD_SYM)
+        hipLaunchKernelGGL((k_big_sym_unpack<LOGMW>), dim3(16, items), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_big(const RunArgs& a, int mode, int logmw, void* bi, void* scr, const void* twF1,
+                      const void* twF2, const void* twMW, const void* twF, const void* H, hipStream_t st) {
+    if (a.nitems > 65535) return hipErrorInvalidValue;  // items run along grid y
+    BigArgs g;
+    g.a = a;
+    g.bi = reinterpret_cast<BigItem*>(bi);
+    g.scr = scr;
+    g.twF1 = twF1;
+    g.twF2 = twF2;
+    g.twMW = twMW;
+    g.twF = twF;
+    g.H = H;
+#define APX_BIG(L_)                                                  \
+    case L_:                                                         \
+        switch (mode) {                                              \
+            case MD_FULL32: return big_run<MD_FULL32, L_>(g, st);    \
+            case MD_SYM: return big_run<MD_SYM, L_>(g, st);          \
+            case MD_ASYM2: return big_run<MD_ASYM2, L_>(g, st);      \
+            case MD_ASYM3: return big_run<MD_ASYM3, L_>(g, st);      \
+            default: return hipErrorInvalidValue;                    \
+        }
+    switch (logmw) {
+        APX_BIG(10)
+        APX_BIG(11)
+        APX_BIG(12)
+        APX_BIG(13)
+        APX_BIG(14)
+        APX_BIG(15)
+        default: return hipErrorInvalidValue;
+    }
+#undef APX_BIG
+}
+
+size_t big_item_bytes() { return sizeof(BigItem); }
+
 // Fixed symmetric or FP32 items of the batched kernel read their window once: point n =
 // threadIdx.x + NT k holds samples SPP n .. SPP n + SPP - 1 of the window in registers (zero at
 // or past nwin); the block statistics are taken from them and the packed words are written from
