@@ -78,9 +78,9 @@ typedef struct {
                              passes, 2 = one wavefront per block, 3 = a group of 512-point
                              wavefront transforms per block (2 and 3: supported sizes only),
                              4 = multi-pass transforms through a device scratch (fixed packed
-                             modes and FP32, 2^11 to 2^16 words; taken by itself where a fixed
-                             mode's or FP32's words exceed 2^14, i.e. W_block up to 65536; one
-                             signal per launch, no apx_many) */
+                             modes, 2^11 to 2^16 words, and FP32, to 2^17 words; taken by
+                             itself where a fixed mode's or FP32's words exceed 2^14; one signal
+                             per launch, no apx_many) */
     double sigma_s;       /* > 0: the signal's sigma in eq. (18) for every block (a source-level
                              value, e.g. from apx_fit_marginal, Section IV.D); 0 = each block's
                              root second moment.  The block maximum still sets sigma_v. */

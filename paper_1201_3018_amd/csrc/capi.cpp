@@ -533,9 +533,10 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
                                            : (p.mode == APX_FULL_FP32 ? W_block : 0);
         if (big_words > 0 && (p.fft_variant == 4 || ceil_log2(big_words) > fft_max_logF())) {
             const int logmw = std::max(ceil_log2(big_words), 1) - 1;
-            if (!big_supported(logmw))
+            const bool fp32 = p.mode == APX_FULL_FP32;
+            if (!big_supported(logmw, fp32))
                 return fail(APX_E_UNSUPPORTED, "FFT core: %d words per block (multi-pass transforms of %d to %d words)",
-                            big_words, 2 << BIG_LOGMW_MIN, 2 << BIG_LOGMW_MAX);
+                            big_words, 2 << BIG_LOGMW_MIN, 2 << (fp32 ? BIG_LOGMW_MAX_FP32 : BIG_LOGMW_MAX));
             k->big_logmw = logmw;
             for (int m = 0; m < 4; ++m) k->Fw[m] = 2 << logmw;
         } else if (p.fft_variant == 4) {

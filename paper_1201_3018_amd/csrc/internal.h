@@ -117,9 +117,10 @@ bool group_supported(int ms, int ma2, int ma3, int mf);
 int group_sub_points(int ms, int ma2, int ma3, int mf, int mode);
 hipError_t launch_fftg(const RunArgs& a, int ms, int ma2, int ma3, int mf, hipStream_t st);
 // multi-pass FFT core (kernels.hip): transforms of 2^logmw complex points per block,
-// BIG_LOGMW_MIN <= logmw <= BIG_LOGMW_MAX, through a device scratch of 2^logmw points per item
-constexpr int BIG_LOGMW_MIN = 10, BIG_LOGMW_MAX = 15;
-bool big_supported(int logmw);
+// BIG_LOGMW_MIN <= logmw <= BIG_LOGMW_MAX (BIG_LOGMW_MAX_FP32 for FP32), through a device
+// scratch of 2^logmw points per item
+constexpr int BIG_LOGMW_MIN = 10, BIG_LOGMW_MAX = 15, BIG_LOGMW_MAX_FP32 = 16;
+bool big_supported(int logmw, bool fp32);
 size_t big_item_bytes();
 hipError_t launch_big_spectrum(const double* h, int32_t nh, int32_t F, const double2* twF, void* spec, bool fp32,
                                hipStream_t st);

@@ -1281,7 +1281,9 @@ hipError_t launch_big_spectrum(const double* h, int32_t nh, int32_t F, const dou
     return hipGetLastError();
 }
 
-bool big_supported(int logmw) { return logmw >= BIG_LOGMW_MIN && logmw <= BIG_LOGMW_MAX; }
+bool big_supported(int logmw, bool fp32) {
+    return logmw >= BIG_LOGMW_MIN && logmw <= (fp32 ? BIG_LOGMW_MAX_FP32 : BIG_LOGMW_MAX);
+}
 
 template <int MODE, int LOGMW>
 static hipError_t big_run(const BigArgs& g, hipStream_t st) {
@@ -1324,6 +1326,9 @@ hipError_t launch_big(const RunArgs& a, int mode, int logmw, void* bi, void* scr
         APX_BIG(13)
         APX_BIG(14)
         APX_BIG(15)
+        case 16:  // FP32 only: 256 x 256 points, 32 KB of LDS per column tile
+            if (mode == MD_FULL32) return big_run<MD_FULL32, 16>(g, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 #undef APX_BIG

@@ -110,7 +110,7 @@ def test_multipass_large_blocks_packed(ctx, mode, Wb):
     _check_packed(s, k, Wb, mode, S, got, fields, info)
 
 
-@pytest.mark.parametrize("Wb", [32768, 65536])
+@pytest.mark.parametrize("Wb", [32768, 65536, 66338])
 def test_multipass_large_blocks_fp32(ctx, Wb):
     L, N = 3 * Wb + 999, 801
     rng = np.random.default_rng(Wb)

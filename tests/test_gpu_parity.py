@@ -221,14 +221,14 @@ def test_fft_block_core_own_length(ctx, mode, N, Wb):
 
 def test_fft_block_core_limits(ctx):
     """Beyond one workgroup's transform (16384 words) the multi-pass core takes over (FP32 above
-    W_block = 16384, symmetric above 32768, asymmetric M=2 above 16384 words), up to 65536 words;
-    beyond that the FFT core refuses."""
+    W_block = 16384, symmetric above 32768, asymmetric M=2 above 16384 words), up to 65536 words
+    (131072 for FP32); beyond that the FFT core refuses."""
     k = _dev(synth.uniform(800, 9))
     for mode, Wb in ((apx.APX_FULL_FP32, 17186), (apx.APX_ASYM2, 33570), (apx.APX_SYM, 33570)):
         kern = apx.Kernel(ctx, k, Wb, mode=mode, core=apx.APX_CORE_FFT)
         assert "k_big" in kern.describe(), (mode, Wb, kern.describe())
         kern.close()
-    for mode, Wb in ((apx.APX_FULL_FP32, 65538), (apx.APX_ASYM2, 131072), (apx.APX_SYM, 131074)):
+    for mode, Wb in ((apx.APX_FULL_FP32, 131074), (apx.APX_ASYM2, 131072), (apx.APX_SYM, 131074)):
         with pytest.raises(apx.ApxError) as e:
             apx.Kernel(ctx, k, Wb, mode=mode, core=apx.APX_CORE_FFT)
         assert e.value.status == apx.APX_E_UNSUPPORTED, (mode, Wb)
