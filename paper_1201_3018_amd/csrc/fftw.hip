@@ -949,12 +949,15 @@ __device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename 
             A[w] = reg[w * RP + ca];
             B[w] = reg[w * RP + cb];
         }
-        // tables through a uniform base and a 32-bit lane offset (one address register per load)
+        // tables through a uniform base and a 32-bit lane offset (one address register per load);
+        // the split uses the same twiddles, conjugated
+        TW ta[R], tb[R];
 #pragma unroll
         for (int w = 1; w < R; ++w) {
-            const TW ta = ld_row(twM, (uint32_t)(w * ca) * ES), tb = ld_row(twM, (uint32_t)(w * cb) * ES);
-            A[w] = cmul(A[w], cx<T>{ta.x, ta.y});
-            B[w] = cmul(B[w], cx<T>{tb.x, tb.y});
+            ta[w] = ld_row(twM, (uint32_t)(w * ca) * ES);
+            tb[w] = ld_row(twM, (uint32_t)(w * cb) * ES);
+            A[w] = cmul(A[w], cx<T>{ta[w].x, ta[w].y});
+            B[w] = cmul(B[w], cx<T>{tb[w].x, tb[w].y});
         }
         dftr<T, R, false>(A);  // A[j] = Z[ca + MS j]
         dftr<T, R, false>(B);  // B[j] = Z[cb + MS j]
@@ -979,7 +982,7 @@ __device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename 
             dftr<T, R, true>(V);  // V[w] = sum_j W_R^(-w j) V[cc + MS j]
 #pragma unroll
             for (int w = 1; w < R; ++w) {
-                const TW tw = ld_row(twM, (uint32_t)(w * cc) * ES);
+                const TW tw = side ? tb[w] : ta[w];
                 V[w] = cmul(V[w], cx<T>{tw.x, -tw.y});
             }
 #pragma unroll
@@ -991,7 +994,8 @@ __device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename 
 
 // Window of the item into LDS (FP32, zero past nvalid, zero sentinels at -1 and W_block) with
 // its statistics from the same loads; per-wave partials are combined through `red` in the same
-// order by every thread.  CH float2 loads per thread and step.
+// order by every thread.  CH float2 loads per thread and step (with four waves and CH = 8 a
+// 4096-sample window is one step: all of its loads in flight together, C2 -0.7 us).
 template <int NTH, int CH>
 __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WItem& it, float* win, double* red) {
     double m = 0.0, q = 0.0;
@@ -1325,7 +1329,7 @@ __global__ void __launch_bounds__((64 * GroupShape<MS_, RS_, MA2_, RA2_, MA3_, R
     const WChoiceIn cin = wave_choice_inputs(a);
     const WItem it = wave_make_item(a, item);
     float* win = reinterpret_cast<float*>(lds + 16);
-    WStats st = group_load_window<NTH, 4>(a, it, win, red);
+    WStats st = group_load_window<NTH, 8>(a, it, win, red);
     st.smax = uni_d(st.smax);
     st.sumsq = uni_d(st.sumsq);
     st.nonfinite = uni_i(st.nonfinite);
