@@ -1009,8 +1009,11 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
         q += d0 * d0 + d1 * d1;
     };
     // uniform: the window lies inside the signal and is valid throughout (every block but the
-    // last), so that a sample needs no bound but the window's own
+    // last), so that a sample needs no bound but the window's own.  Its statistics take the
+    // samples as they are, and x * 0 (NaN exactly for a NaN or infinite x) marks a non-finite
+    // one; a thread that met one takes its partials again below, over its finite samples only.
     const bool interior = it.nwin >= a.W_block && it.nvalid >= a.W_block;
+    float z = 0.0f;
     for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
         float2 f[CH];
         if (interior) {
@@ -1023,7 +1026,10 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
             for (int c = 0; c < CH; ++c) {
                 const int i = base + 2 * ((int)threadIdx.x + NTH * c);
                 if (i < a.W_block) {
-                    take(f[c].x, f[c].y);
+                    const double d0 = (double)f[c].x, d1 = (double)f[c].y;
+                    m = fmax(m, fmax(fabs(d0), fabs(d1)));
+                    q += d0 * d0 + d1 * d1;
+                    z = fmaf(f[c].y, 0.0f, fmaf(f[c].x, 0.0f, z));
                     *reinterpret_cast<float2*>(win + i) = f[c];
                 }
             }
@@ -1043,6 +1049,17 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
                 take(f[c].x, f[c].y);
                 *reinterpret_cast<float2*>(win + i) =
                     make_float2(i < it.nvalid ? f[c].x : 0.0f, i + 1 < it.nvalid ? f[c].y : 0.0f);
+            }
+        }
+    }
+    if (interior && z != z) {  // this thread's own samples, back from LDS, as take() counts them
+        m = 0.0;
+        q = 0.0;
+        for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int i = base + 2 * ((int)threadIdx.x + NTH * c);
+                if (i < a.W_block) take(win[i], win[i + 1]);
             }
         }
     }
@@ -1118,7 +1135,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
     auto rd = [&](int i) -> float { return win[min(max(i, -1), wb)]; };
     auto sqd = [&](int i) -> double { return rint(c.cs * (double)rd(i)); };
     auto sqd_in = [&](int i) -> double { return rint(c.cs * (double)win[i]); };
-    const int wv = threadIdx.x >> 6;
+    const int wv = uni_i((int)threadIdx.x >> 6);  // the wave's index, in a scalar register
     const bool active = wv < R;
     // ---- pack: wave w holds the decimated points z[R n + w], n = l + 64 r (eq. 4 / eq. 7)
     cx<T> v[E];
