@@ -58,7 +58,7 @@ assert BLOCK_INFO_DTYPE.itemsize == ctypes.sizeof(apx_block_info)
 
 class apx_tuned(ctypes.Structure):
     _fields_ = [("core", ctypes.c_int32), ("fft_variant", ctypes.c_int32), ("W_block", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("ps_per_output", ctypes.c_double)]
+                ("tile", ctypes.c_int32), ("ps_per_output", ctypes.c_double)]
 
 
 class apx_server_config(ctypes.Structure):
@@ -325,7 +325,8 @@ def apx_tune(ctx, k, W_block: int, prm: apx_params, op: int = APX_CONV, L_hint: 
     t = apx_tuned()
     _check(lib().apx_tune(ctx, _dev_ptr(k, "float32"), k.numel(), int(op), int(W_block), ctypes.byref(prm),
                           int(L_hint), _stream(stream), ctypes.byref(t)))
-    return {"core": t.core, "fft_variant": t.fft_variant, "W_block": t.W_block, "ps_per_output": t.ps_per_output}
+    return {"core": t.core, "fft_variant": t.fft_variant, "W_block": t.W_block, "tile": t.tile,
+            "ps_per_output": t.ps_per_output}
 
 
 def apx_tune_describe(ctx) -> str:

@@ -305,7 +305,7 @@ apx_status launch_big_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
 apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
     if (k->core == APX_CORE_FFT && k->big_logmw) return launch_big_kernel(k, a, st);
     if (k->core == APX_CORE_INT8) {
-        HIPCHK(launch_i8(a, k->i8frag, k->S[k->params.mode] > 127, k->i8_splitk, k->i8_plane, st));
+        HIPCHK(launch_i8(a, k->i8frag, k->S[k->params.mode] > 127, k->i8_splitk, k->i8_plane, k->i8_tm, st));
     } else if (k->core == APX_CORE_FFT && k->group) {
         HIPCHK(launch_fftg(a, k->wM[1], k->wM[2], k->wM[3], k->wM[0], st));
     } else if (k->core == APX_CORE_FFT && k->wave) {
@@ -509,6 +509,7 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             return fail(APX_E_UNSUPPORTED, "the integer core takes S_q, K_q <= 16319 (two int8 digits)");
         if ((int64_t)N_odd + 31 >= (1 << 17)) return fail(APX_E_UNSUPPORTED, "N too large for int32 digit sums");
         k->i8_plane = i8_plane_len(N_odd, W);
+        k->i8_tm = std::min(3, std::max(1, i8_tiles(N_odd, W)));  // no pass computes a tile no block has
         k->i8_splitk = k->K[m] > 127;
         const size_t lds = i8_lds_bytes(k->i8_plane, W_block);
         if (lds > (size_t)ctx->max_lds)
@@ -723,7 +724,8 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
     if (!ctx || !params) return fail(APX_E_INVALID, "null argument");
     if (W_block < 0) return fail(APX_E_INVALID, "W_block = %d", W_block);
     apx_params p = *params;
-    apx::resolve_tuned(ctx, N, op, &W_block, &p);  // W_block 0 and automatic cores take the tuned choice
+    int32_t tile = 0;
+    apx::resolve_tuned(ctx, N, op, &W_block, &p, &tile);  // W_block 0 and automatic cores take the tuned choice
     apx_kernel k = new (std::nothrow) apx_kernel_s;
     if (!k) return fail(APX_E_NOMEM, "host allocation failed");
     apx_status r = init_kernel(k, ctx, k_in, N, op, W_block, &p, stream, 0);
@@ -731,6 +733,7 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
         delete k;
         return r;
     }
+    if (tile > 0 && k->core == APX_CORE_INT8) k->i8_tm = tile;
     *out = k;
     return APX_OK;
 }
@@ -938,8 +941,8 @@ apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {
     if (k->core == APX_CORE_TIME) {
         n = snprintf(tmp, sizeof tmp, "core=time kernel=k_td lds=%zu", k->td_lds);
     } else if (k->core == APX_CORE_INT8) {
-        n = snprintf(tmp, sizeof tmp, "core=int8 kernel=k_i8 ksteps=%d lds=%zu split_k=%d", i8_ksteps(k->N_odd),
-                     i8_lds_bytes(k->i8_plane, k->W_block), k->i8_splitk);
+        n = snprintf(tmp, sizeof tmp, "core=int8 kernel=k_i8 ksteps=%d lds=%zu split_k=%d tiles_per_pass=%d",
+                     i8_ksteps(k->N_odd), i8_lds_bytes(k->i8_plane, k->W_block), k->i8_splitk, k->i8_tm);
     } else if (k->wave) {
         n = snprintf(tmp, sizeof tmp, "core=fft kernel=%s<%d,%d,%d,%d> words(fp32,sym,asym2,asym3)=%d,%d,%d,%d",
                      k->group ? "k_fftg" : "k_fftw", k->wM[1], k->wM[2], k->wM[3], k->wM[0], 2 * k->wM[0],

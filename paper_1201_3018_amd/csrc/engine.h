@@ -29,7 +29,9 @@ size_t i8_lds_bytes(int plane_len, int W_block);
 hipError_t launch_i8_frag(const float* kf, const KState* ks, int mode, int N_odd, int split, void* frag,
                           hipStream_t st);
 hipError_t i8_set_lds(int bytes);
-hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, hipStream_t st);
+// tm: output tiles per pass over the taps, 1 to 3
+hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, int tm, hipStream_t st);
+int i8_tiles(int N_odd, int W);
 }  // namespace apx
 
 using apx::KState;
@@ -48,6 +50,7 @@ struct TuneKey {
 struct TuneVal {
     int32_t core, variant, W_block;
     double ps_per_output;
+    int32_t tile = 0;  // integer core: output tiles per pass (0: the shape's default)
 };
 }  // namespace apx
 
@@ -82,6 +85,7 @@ struct apx_kernel_s {
     int32_t* i8frag = nullptr;
     int i8_plane = 0;
     int i8_splitk = 0;
+    int i8_tm = 3;  // output tiles per pass (1 to 3)
     int32_t S[4] = {0, 0, 0, 0}, K[4] = {0, 0, 0, 0};
     int64_t R[4] = {0, 0, 0, 0};
     int32_t T[4] = {0, 0, 0, 0};
@@ -146,6 +150,6 @@ bool tune_lookup(apx_ctx ctx, int32_t N_odd, int32_t op, int32_t mode, int32_t W
 int32_t default_block(int32_t N);
 // The block size and core a kernel request resolves to: W_block 0 takes the tuned block size (or
 // the default rule), and an automatic core and FFT implementation take the tuned ones.
-void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_params* p);
+void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_params* p, int32_t* tile = nullptr);
 }  // namespace apx
 

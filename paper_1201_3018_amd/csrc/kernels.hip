@@ -1993,7 +1993,6 @@ typedef int i8x16 __attribute__((ext_vector_type(4)));   // 16 int8 per lane
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int I8_TILE = 1024;  // outputs per 32 x 32 tile
-constexpr int I8_TM = 3;       // tiles per pass over the taps
 
 __device__ __forceinline__ void i8_digits(int v, bool split, int& lo, int& hi) {
     if (split) {
@@ -2053,8 +2052,10 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// SS, SK: the samples' / the taps' companding range exceeds 127 (two digit planes)
-template <bool SS, bool SK, bool MANY>
+// SS, SK: the samples' / the taps' companding range exceeds 127 (two digit planes); TM: output
+// tiles per pass over the taps (more tiles reuse each fragment load, fewer keep fewer accumulators
+// and do no work for a block that has fewer tiles)
+template <bool SS, bool SK, bool MANY, int TM>
 __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* __restrict__ frag, int ksteps,
                                                        int plane_len, int region) {
     extern __shared__ __attribute__((aligned(16))) char lds_all[];
@@ -2140,7 +2141,7 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
     const int row = lane & 31, half = lane >> 5;
     const char* a0p = lds_i8 + 32 * row + 16 * half;
     const char* a1p = a0p + plane_len;
-    // every pass computes I8_TM tiles over kpad k-steps (the planes and the zero-padded fragment
+    // every pass computes TM tiles over kpad k-steps (the planes and the zero-padded fragment
     // rows cover them); a last pass with fewer tiles repeats the last tile, and outputs past j_hi
     // are not stored.  Blocks walk the k-steps from different starting chunks (the integer sums
     // do not depend on the order), so the waves of the GPU do not all read the same fragment
@@ -2151,18 +2152,18 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
     constexpr int NACC = SS && SK ? 3 : (SS || SK ? 2 : 1);
     // one-digit operands: two accumulator sets (even and odd k-steps) for independent MFMA chains
     constexpr int AS = NACC == 1 ? 2 : 1;
-    for (int t0 = 0; t0 < ntiles; t0 += I8_TM) {
-        i32x16 acc[NACC * AS][I8_TM];
+    for (int t0 = 0; t0 < ntiles; t0 += TM) {
+        i32x16 acc[NACC * AS][TM];
 #pragma unroll
         for (int g = 0; g < NACC * AS; ++g)
 #pragma unroll
-            for (int u = 0; u < I8_TM; ++u)
+            for (int u = 0; u < TM; ++u)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[g][u][r] = 0;
         i8x16 bc[I8_KC][SK ? 2 : 1], bn[I8_KC][SK ? 2 : 1];
-        int tofs[I8_TM];  // tile origin in the planes
+        int tofs[TM];  // tile origin in the planes
 #pragma unroll
-        for (int u = 0; u < I8_TM; ++u) tofs[u] = j0 + min(t0 + u, ntiles - 1) * I8_TILE;
+        for (int u = 0; u < TM; ++u) tofs[u] = j0 + min(t0 + u, ntiles - 1) * I8_TILE;
         {
             const int kc = c_first * I8_KC;
 #pragma unroll
@@ -2186,7 +2187,7 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
 #pragma unroll
             for (int kk = 0; kk < I8_KC; ++kk) {
 #pragma unroll
-                for (int u = 0; u < I8_TM; ++u) {
+                for (int u = 0; u < TM; ++u) {
                     const int ofs = tofs[u] + 32 * (k0 + kk);
                     const i8x16 x0 = *reinterpret_cast<const i8x16*>(a0p + ofs);
                     const int g0 = AS == 2 ? (kk & 1) : 0;  // static once the k-step loop is unrolled
@@ -2212,7 +2213,7 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
         }
         // D[r] of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
 #pragma unroll
-        for (int u = 0; u < I8_TM; ++u) {
+        for (int u = 0; u < TM; ++u) {
             if (t0 + u >= ntiles) continue;
             const int m0 = j0 + (t0 + u) * I8_TILE;
 #pragma unroll
@@ -2235,6 +2236,14 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
 int i8_ksteps(int N_odd) { return (N_odd + 31 + 31) / 32; }
 int i8_kpad(int N_odd) { return (i8_ksteps(N_odd) + I8_KC - 1) / I8_KC * I8_KC; }
 
+// output tiles of the block with the most (block 0 from output 0, later blocks from N + 1)
+int i8_tiles(int N_odd, int W) {
+    const int nt0 = (W + N_odd - 1 + I8_TILE - 1) / I8_TILE;
+    const int j0 = (N_odd + 1) & ~15;
+    const int nt1 = (N_odd + 1 + W - j0 + I8_TILE - 1) / I8_TILE;
+    return std::max(nt0, nt1);
+}
+
 int i8_plane_len(int N_odd, int W) {
     const int nt0 = (W + N_odd - 1 + I8_TILE - 1) / I8_TILE;     // block 0: outputs from 0
     const int j0 = (N_odd + 1) & ~15;                             // later blocks
@@ -2251,11 +2260,23 @@ hipError_t launch_i8_frag(const float* kf, const KState* ks, int mode, int N_odd
     return hipGetLastError();
 }
 
+template <int TM>
+static void i8_fns(const void** fs) {
+    fs[0] = (const void*)k_i8<false, false, false, TM>;
+    fs[1] = (const void*)k_i8<false, true, false, TM>;
+    fs[2] = (const void*)k_i8<true, false, false, TM>;
+    fs[3] = (const void*)k_i8<true, true, false, TM>;
+    fs[4] = (const void*)k_i8<false, false, true, TM>;
+    fs[5] = (const void*)k_i8<false, true, true, TM>;
+    fs[6] = (const void*)k_i8<true, false, true, TM>;
+    fs[7] = (const void*)k_i8<true, true, true, TM>;
+}
+
 hipError_t i8_set_lds(int bytes) {
-    const void* fs[8] = {(const void*)k_i8<false, false, false>, (const void*)k_i8<false, true, false>,
-                         (const void*)k_i8<true, false, false>,  (const void*)k_i8<true, true, false>,
-                         (const void*)k_i8<false, false, true>,  (const void*)k_i8<false, true, true>,
-                         (const void*)k_i8<true, false, true>,   (const void*)k_i8<true, true, true>};
+    const void* fs[24];
+    i8_fns<1>(fs);
+    i8_fns<2>(fs + 8);
+    i8_fns<3>(fs + 16);
     for (const void* f : fs) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -2275,16 +2296,24 @@ size_t i8_lds_bytes(int plane_len, int W_block) {
 }
 
 // split_s: the fixed mode's S_q > 127 (every block of the call uses it)
-hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, hipStream_t st) {
+hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, int tm, hipStream_t st) {
     const int rg = (int)i8_region(plane_len, a.W_block);
     const int wpb = i8_wpb((size_t)rg);
     const dim3 g((unsigned)((a.nitems + wpb - 1) / wpb)), b(64 * wpb);
     const size_t lds = (size_t)wpb * rg;
     const i8x16* fr = reinterpret_cast<const i8x16*>(frag);
     const int ks = i8_ksteps(a.N);
-#define APX_GO(SS_, SK_)                                                                              \
-    if (a.many) hipLaunchKernelGGL((k_i8<SS_, SK_, true>), g, b, lds, st, a, fr, ks, plane_len, rg);     \
-    else hipLaunchKernelGGL((k_i8<SS_, SK_, false>), g, b, lds, st, a, fr, ks, plane_len, rg);
+#define APX_GOT(SS_, SK_, TM_)                                                                          \
+    if (a.many) hipLaunchKernelGGL((k_i8<SS_, SK_, true, TM_>), g, b, lds, st, a, fr, ks, plane_len, rg);  \
+    else hipLaunchKernelGGL((k_i8<SS_, SK_, false, TM_>), g, b, lds, st, a, fr, ks, plane_len, rg);
+#define APX_GO(SS_, SK_)                  \
+    if (tm == 1) {                        \
+        APX_GOT(SS_, SK_, 1)              \
+    } else if (tm == 2) {                 \
+        APX_GOT(SS_, SK_, 2)              \
+    } else {                              \
+        APX_GOT(SS_, SK_, 3)              \
+    }
     if (split_s && split_k) {
         APX_GO(true, true)
     } else if (split_s) {
@@ -2295,6 +2324,7 @@ hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_
         APX_GO(false, false)
     }
 #undef APX_GO
+#undef APX_GOT
     return hipGetLastError();
 }
 

@@ -50,15 +50,18 @@ std::string arch_of(int device) {
 }
 
 // Table line: arch, N_odd, op, mode, W_block asked for (0: chosen too), then core, FFT
-// implementation, W_block and picoseconds per output measured.
+// implementation, W_block, picoseconds per output measured and the integer core's output tiles
+// per pass (a line without the last field reads as 0: the shape's default).
 bool parse(const char* line, std::string* arch, apx::TuneKey* k, apx::TuneVal* v) {
     char a[128];
     double us = 0.0;
-    if (sscanf(line, "%127s %d %d %d %d %d %d %d %lf", a, &k->N_odd, &k->op, &k->mode, &k->W_block, &v->core,
-               &v->variant, &v->W_block, &us) != 9)
-        return false;
+    int tile = 0;
+    const int got = sscanf(line, "%127s %d %d %d %d %d %d %d %lf %d", a, &k->N_odd, &k->op, &k->mode, &k->W_block,
+                           &v->core, &v->variant, &v->W_block, &us, &tile);
+    if (got < 9) return false;
     *arch = a;
     v->ps_per_output = us;
+    v->tile = (got == 10 && tile >= 1 && tile <= 3) ? tile : 0;
     return true;
 }
 
@@ -82,8 +85,9 @@ void save(apx_ctx ctx) {
     if (!f) return;  // the table stays in memory only
     for (const std::string& l : keep) fputs(l.c_str(), f);
     for (const auto& kv : ctx->tuned)
-        fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", ctx->arch.c_str(), kv.first.N_odd, kv.first.op, kv.first.mode,
-                kv.first.W_block, kv.second.core, kv.second.variant, kv.second.W_block, kv.second.ps_per_output);
+        fprintf(f, "%s %d %d %d %d %d %d %d %.3f %d\n", ctx->arch.c_str(), kv.first.N_odd, kv.first.op,
+                kv.first.mode, kv.first.W_block, kv.second.core, kv.second.variant, kv.second.W_block,
+                kv.second.ps_per_output, kv.second.tile);
     fclose(f);
     if (rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
 }
@@ -132,7 +136,7 @@ int32_t default_block(int32_t N) {
     return wb;
 }
 
-void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_params* p) {
+void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_params* p, int32_t* tile) {
     const int32_t no = odd_of(N);
     const bool auto_core = p->core == APX_CORE_AUTO && p->fft_variant == 0;
     TuneVal v;
@@ -142,6 +146,7 @@ void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_par
             if (auto_core) {
                 p->core = v.core;
                 p->fft_variant = v.variant;
+                if (tile) *tile = v.tile;
             }
             return;
         }
@@ -150,6 +155,7 @@ void resolve_tuned(apx_ctx ctx, int32_t N, int32_t op, int32_t* W_block, apx_par
     if (auto_core && tune_lookup(ctx, no, op, p->mode, *W_block, &v)) {
         p->core = v.core;
         p->fft_variant = v.variant;
+        if (tile) *tile = v.tile;
     }
 }
 
@@ -198,18 +204,19 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
     apx_tuned best{};
     best.ps_per_output = INFINITY;
     int tried = 0;
-    char table[2048];
+    char table[4096];
     int used = 0;
     table[0] = 0;
-    // candidates: time-domain core, integer core (fixed packed modes), FFT core in each of its
-    // implementations (LDS passes; one wave per block; a group of waves per block).  Every
+    // candidates: time-domain core, integer core (fixed packed modes) with each count of output
+    // tiles per pass up to the tiles a block has, FFT core in each of its implementations (LDS
+    // passes; one wave per block; a group of waves per block).  Every
     // candidate that runs the shape is prepared first; then rounds of timed runs visit them in
     // turn and each keeps its fastest round, so that a slow moment of the device (another
     // process, a profiler) does not decide the choice.
     const int cores[5][2] = {{APX_CORE_TIME, 0}, {APX_CORE_INT8, 0}, {APX_CORE_FFT, 1}, {APX_CORE_FFT, 2},
                              {APX_CORE_FFT, 3}};
     struct Cand {
-        int32_t wb, core, variant;
+        int32_t wb, core, variant, tile;
         apx_kernel kern;
         double ps;
     };
@@ -220,15 +227,21 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
             apx_params p = *params;
             p.core = cv[0];
             p.fft_variant = cv[1];
-            apx_kernel kern = nullptr;
-            if (apx_kernel_create(ctx, k, N, op, wb, &p, stream, &kern) != APX_OK) continue;  // cannot run it
-            bool ok = true;
-            for (int i = 0; i < 2 && ok; ++i) ok = apx_run(ctx, kern, sig(i), L, res(i), nullptr, stream) == APX_OK;
-            if (!ok) {
-                apx_kernel_destroy(kern);
-                continue;
+            const int ntile =
+                cv[0] == APX_CORE_INT8 ? std::min(3, std::max(1, apx::i8_tiles(N_odd, wb - N_odd - 1))) : 1;
+            for (int t = 1; t <= ntile; ++t) {
+                apx_kernel kern = nullptr;
+                if (apx_kernel_create(ctx, k, N, op, wb, &p, stream, &kern) != APX_OK) break;  // cannot run it
+                if (cv[0] == APX_CORE_INT8) kern->i8_tm = t;
+                bool ok = true;
+                for (int i = 0; i < 2 && ok; ++i)
+                    ok = apx_run(ctx, kern, sig(i), L, res(i), nullptr, stream) == APX_OK;
+                if (!ok) {
+                    apx_kernel_destroy(kern);
+                    break;
+                }
+                cands.push_back(Cand{wb, cv[0], cv[1], cv[0] == APX_CORE_INT8 ? t : 0, kern, INFINITY});
             }
-            cands.push_back(Cand{wb, cv[0], cv[1], kern, INFINITY});
         }
     }
     constexpr int ROUNDS = 3, REPS = 5;
@@ -258,12 +271,13 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
         apx_kernel_destroy(c.kern);
         ++tried;
         if (used < (int)sizeof table - 64)
-            used += snprintf(table + used, sizeof table - used, " [W_block %d core %d impl %d: %.2f ps/output]",
-                             c.wb, c.core, c.variant, c.ps);
+            used += snprintf(table + used, sizeof table - used, " [W_block %d core %d impl %d tile %d: %.2f ps/output]",
+                             c.wb, c.core, c.variant, c.tile, c.ps);
         if (c.ps < best.ps_per_output) {
             best.core = c.core;
             best.fft_variant = c.variant;
             best.W_block = c.wb;
+            best.tile = c.tile;
             best.ps_per_output = c.ps;
         }
     }
@@ -274,7 +288,7 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
     if (e != hipSuccess) return apx::set_error(APX_E_DEVICE, "tuning buffers: %s", hipGetErrorString(e));
     if (tried == 0) return apx::set_error(APX_E_UNSUPPORTED, "no core runs N = %d at the block sizes tried", N);
     ctx->tuned[apx::TuneKey{N_odd, op, params->mode, W_block}] =
-        apx::TuneVal{best.core, best.fft_variant, best.W_block, best.ps_per_output};
+        apx::TuneVal{best.core, best.fft_variant, best.W_block, best.ps_per_output, best.tile};
     save(ctx);
     *out = best;
     ctx->last_tune = table;
@@ -286,9 +300,10 @@ apx_status apx_tune_describe(apx_ctx ctx, char* buf, int32_t size) {
     std::string s = "device " + ctx->arch + ", table " + tune_path() + ":";
     for (const auto& kv : ctx->tuned) {
         char line[160];
-        snprintf(line, sizeof line, "\n  N=%d op=%d mode=%d W_block=%d -> core %d impl %d W_block %d (%.2f ps/output)",
+        snprintf(line, sizeof line,
+                 "\n  N=%d op=%d mode=%d W_block=%d -> core %d impl %d W_block %d tile %d (%.2f ps/output)",
                  kv.first.N_odd, kv.first.op, kv.first.mode, kv.first.W_block, kv.second.core, kv.second.variant,
-                 kv.second.W_block, kv.second.ps_per_output);
+                 kv.second.W_block, kv.second.tile, kv.second.ps_per_output);
         s += line;
     }
     if (!ctx->last_tune.empty()) s += "\nlast tuning:" + ctx->last_tune;

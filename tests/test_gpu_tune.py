@@ -44,6 +44,10 @@ def test_tune_choose_block_and_core(tmp_path, monkeypatch):
     assert kern.W_block == res["W_block"]
     core_name = {apx.APX_CORE_TIME: "core=time", apx.APX_CORE_INT8: "core=int8", apx.APX_CORE_FFT: "core=fft"}
     assert kern.describe().startswith(core_name[res["core"]]), kern.describe()
+    if res["core"] == apx.APX_CORE_INT8:  # the tuned count of output tiles per pass is used
+        assert res["tile"] in (1, 2, 3) and f"tiles_per_pass={res['tile']}" in kern.describe(), kern.describe()
+    else:
+        assert res["tile"] == 0
     s = synth.gaussian(50000, 1001)
     out = torch.full((s.size + N - 1,), float("nan"), dtype=torch.float32, device=DEV)
     kern.run(_dev(s), out=out)
@@ -71,6 +75,40 @@ def test_tune_choose_block_and_core(tmp_path, monkeypatch):
     assert out.returncode == 0, out.stderr
     assert f"N=65 op=0 mode={apx.APX_ASYM2} W_block=0" in out.stdout
     assert "N=1025 op=0 mode=4 W_block=4096" in out.stdout
+
+
+@pytest.mark.parametrize("mode,S", [(O.SYM, 0), (O.ASYM2, 300), (O.ASYM3, 0)])
+@pytest.mark.parametrize("L,N,Wb", [(50000, 256, 4096), (20001, 65, 1024)])
+def test_int8_tiles_per_pass_from_table(tmp_path, monkeypatch, mode, S, L, N, Wb):
+    """The integer core with one, two and three output tiles per pass over the taps, each taken
+    from a table entry (the way a tuned choice reaches a kernel), equal to the oracle bit for bit:
+    blocks of four tiles (passes of 1, 2 and 3 + 1 tiles) and of one tile, one-digit and two-digit
+    operands."""
+    No = N if N % 2 else N + 1
+    Sq = S or O.max_q(mode, No)
+    ctx = apx.Context(0)
+    arch = apx.apx_tune_describe(ctx.h).split(",")[0].split()[1]
+    ctx.close()
+    s, k = synth.ar1(L, 17 + N), synth.hann_lowpass(N, 0.3)
+    ref = O.conv_blocked(s, k, Wb, O.fixed_params(s, k, Wb, mode, Sq, Sq))
+    amode = {O.SYM: apx.APX_SYM, O.ASYM2: apx.APX_ASYM2, O.ASYM3: apx.APX_ASYM3}[mode]
+    for tile in (1, 2, 3):
+        path = str(tmp_path / f"tune{tile}.txt")
+        with open(path, "w") as f:
+            f.write(f"{arch} {No} {apx.APX_CONV} {amode} {Wb} {apx.APX_CORE_INT8} 0 {Wb} 1.000 {tile}\n")
+        monkeypatch.setenv("APX_TUNE_FILE", path)
+        ctx = apx.Context(0)
+        kern = apx.Kernel(ctx, _dev(k), Wb, mode=amode, Sq=Sq, Kq=Sq)
+        desc = kern.describe()
+        print("case: int8 tiles per pass", tile, mode, Sq, L, N, Wb, desc, flush=True)
+        assert desc.startswith("core=int8") and f"tiles_per_pass={tile}" in desc, desc
+        out = torch.full((L + N - 1,), float("nan"), dtype=torch.float32, device=DEV)
+        kern.run(_dev(s), out=out)
+        got = out.cpu().numpy()
+        bad = np.nonzero(got.view(np.int32) != ref.view(np.int32))[0]
+        assert bad.size == 0, f"tiles {tile}: {bad.size} outputs differ, first at {bad[:8]}"
+        kern.close()
+        ctx.close()
 
 
 def test_tune_errors():
