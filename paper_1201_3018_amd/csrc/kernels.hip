@@ -47,6 +47,43 @@ __device__ __forceinline__ int wave_or(int v) {
     return v;
 }
 
+// Wave reductions by DPP lane moves (VALU only, no LDS round trips), the result read from lane
+// 63 into a scalar: pairs and quads by quad permutes, rows of 16 by rotations of 4 and 8, then
+// row 0 into row 1 and row 2 into row 3 (broadcast of lane 15 of each), then rows 0-1 into rows
+// 2-3 (broadcast of lane 31).  Lanes outside a move's row mask take 0, the identity of both
+// operations here (the maximum is over non-negative values).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL, ROWS>((int)(b & 0xffffffffLL)), hi = dpp_i<CTRL, ROWS>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_d<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_d<0x124, 0xf>(v);  // row_ror:4
+    v += dpp_d<0x128, 0xf>(v);  // row_ror:8
+    v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// maximum of non-negative floats
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    v = fmaxf(v, __int_as_float(dpp_i<0xb1, 0xf>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i<0x4e, 0xf>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i<0x124, 0xf>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i<0x128, 0xf>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i<0x142, 0xa>(__float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i<0x143, 0xc>(__float_as_int(v))));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 struct BlockStats {
     double smax, sumsq;
     int nonfinite;
@@ -166,9 +203,10 @@ struct Choice {
     int flags;
 };
 
-__device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st) {
+// ks_in: the taps' state (*a.ks), which a kernel may load early
+__device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st, const KState& ks_in) {
     Choice c;
-    KState ks = *a.ks;
+    KState ks = ks_in;
     // eq. (18)'s sigmas: each block's and the taps' root second moments, or source-level values
     const double rms = a.sigma_s > 0.0 ? a.sigma_s : sqrt(st.sumsq / (double)a.W_block);
     // the block's mean square (rms^2) for the division-free comparison below
@@ -225,6 +263,8 @@ __device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st)
     if (st.smax == 0.0 || ks.kmax == 0.0) c.flags |= APX_FLAG_ZERO;
     return c;
 }
+
+__device__ __forceinline__ Choice choose(const RunArgs& a, const BlockStats& st) { return choose(a, st, *a.ks); }
 
 __device__ __forceinline__ void write_info(const RunArgs& a, const Item& it, const Choice& c, const BlockStats& st,
                                            bool is_report, bool lead = threadIdx.x == 0) {
@@ -1991,6 +2031,14 @@ hipError_t launch_fit_marginal(const float* x, int64_t n, int32_t model, double*
 // ------------------------------------------------------------------------------------------
 typedef int i8x16 __attribute__((ext_vector_type(4)));   // 16 int8 per lane
 typedef int i32x16 __attribute__((ext_vector_type(16)));
+// device-memory views of the signal, output and debug pointers: global (not flat) loads and
+// stores, and copies taken once, since a store through a generic pointer could in the
+// compiler's view rewrite a signal's arguments in the multi-signal table
+typedef __attribute__((address_space(1))) const float gcfloat;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const f32x2 gcf32x2;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) double gdouble;
 
 constexpr int I8_TILE = 1024;  // outputs per 32 x 32 tile
 
@@ -2037,10 +2085,11 @@ __global__ void __launch_bounds__(NT) k_i8_frag(const float* __restrict__ kf, co
 // blocks per workgroup (fewer workgroups to launch); the waves share nothing and never wait for each
 // other.  A wave's LDS region holds the block's companded samples as two digit planes of plane_len bytes (byte i + N - 1 of a plane is
 // digit p of s~[i], zero outside [0, nvalid)), so every A fragment is one aligned 16-byte read,
-// and behind them the raw window (W_block floats) that the planes are built from.  The taps'
-// B fragments stream from L2 in chunks of I8_KC k-steps, the next chunk in flight while the
-// current one runs.
+// and behind them, for a window longer than I8_REG_WIN samples, the window in the same order,
+// zero-padded to plane_len floats, that the planes are built from.  The taps' B fragments stream from L2 in chunks of I8_KC k-steps, the next
+// chunk in flight while the current one runs.
 constexpr int I8_KC = 4;
+constexpr int I8_REG_WIN = 1024;  // longest window held in registers (a multiple of 128)
 constexpr int I8_WPB = 1;  // most waves (blocks) per workgroup (2 measured no faster)
 
 // LDS order point between the lanes of one wave (the LDS unit runs a wave's instructions in
@@ -2056,50 +2105,106 @@ __device__ __forceinline__ void wave_lds_sync() {
 // tiles per pass over the taps (more tiles reuse each fragment load, fewer keep fewer accumulators
 // and do no work for a block that has fewer tiles)
 template <bool SS, bool SK, bool MANY, int TM>
-__global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* __restrict__ frag, int ksteps,
+__global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i8(RunArgs a0, const i8x16* __restrict__ frag, int ksteps,
                                                        int plane_len, int region) {
     extern __shared__ __attribute__((aligned(16))) char lds_all[];
     const int lane = threadIdx.x & 63;
-    int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // the wave's block index is uniform: its lookups (the signal's arguments) are scalar loads
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    int64_t blk = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
     if (blk >= a0.nitems) return;
     const RunArgs& a = item_args<MANY>(a0, blk);
-    char* lds_i8 = lds_all + (size_t)(threadIdx.x >> 6) * region;
+    char* lds_i8 = lds_all + (size_t)wv * region;
     const Item it = make_item(a, blk, false);
-    float* win = reinterpret_cast<float*>(lds_i8 + 2 * plane_len);
-    // window into LDS with its statistics; start is even and s_in 8-byte aligned (float2 loads)
+    const int off = a.N - 1;
+    const KState ksv = *a0.ks;  // one taps' state for every signal of the launch
+    // A window of at most I8_REG_WIN samples stays in registers (one load step) and its digits go
+    // straight to the planes; a longer one passes through zw, where zw[j] = sample j - (N - 1)
+    // of the window, zero outside [0, nwin): the planes' byte order, so that every companded
+    // digit comes from one aligned 16-byte read of four samples.
+    const bool inreg = a.W_block <= I8_REG_WIN;
+    float* zw = reinterpret_cast<float*>(lds_i8 + 2 * plane_len);
+    int* p0 = reinterpret_cast<int*>(lds_i8);
+    int* p1 = reinterpret_cast<int*>(lds_i8 + plane_len);
+    if (inreg) {  // zero planes: the digits of the window overwrite their part
+        for (int w = lane; w < plane_len / 16; w += 64) {
+            reinterpret_cast<int4*>(p0)[w] = make_int4(0, 0, 0, 0);
+            if (SS) reinterpret_cast<int4*>(p1)[w] = make_int4(0, 0, 0, 0);
+        }
+    }
+    // window with its statistics; start is even and s_in 8-byte aligned (float2 loads).  The
+    // maximum is taken in FP32 (exact), and x * 0 accumulated in z stays zero while every
+    // sample is finite; a lane that meets a non-finite sample takes its partials again with the
+    // exact per-sample rule (non-finite samples count as zero and set the flag).
+    constexpr int CH = I8_REG_WIN / 128;
+    float2 f[CH];  // the last load step's samples: the whole window when inreg
     BlockStats st;
     {
-        double m = 0.0, q = 0.0;
+        float m = 0.0f;
+        double q = 0.0;
         int nf = 0;
-        const float* p = a.s + it.start;
-        constexpr int CH = 16;
+        gcfloat* p = (gcfloat*)(a.s + it.start);
         for (int base = 0; base < a.W_block; base += 128 * CH) {
-            float2 f[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int i = base + 2 * lane + 128 * c;
                 f[c] = make_float2(0.0f, 0.0f);
-                if (i + 1 < it.nwin) f[c] = *reinterpret_cast<const float2*>(p + i);
-                else if (i < it.nwin) f[c].x = p[i];
+                if (base + 128 * c < it.nwin) {  // uniform: the chunk holds samples
+                    if (i + 1 < it.nwin) {
+                        const f32x2 v = *(gcf32x2*)(p + i);
+                        f[c] = make_float2(v.x, v.y);
+                    } else if (i < it.nwin) {
+                        f[c].x = p[i];
+                    }
+                }
             }
+            float z = 0.0f;
+            float mc = 0.0f;
+            double qc = 0.0;
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int i = base + 2 * lane + 128 * c;
-                if (i < a.W_block) {
+                if (base + 128 * c < a.W_block && i < a.W_block) {
                     const float x0 = f[c].x, x1 = f[c].y;
-                    if (!isfinite(x0) || !isfinite(x1)) nf = 1;
-                    const double d0 = isfinite(x0) ? (double)x0 : 0.0, d1 = isfinite(x1) ? (double)x1 : 0.0;
-                    m = fmax(m, fmax(fabs(d0), fabs(d1)));
-                    q += d0 * d0 + d1 * d1;
-                    *reinterpret_cast<float2*>(win + i) = f[c];
+                    mc = fmaxf(mc, fmaxf(fabsf(x0), fabsf(x1)));
+                    z = fmaf(x0, 0.0f, z);
+                    z = fmaf(x1, 0.0f, z);
+                    qc = fma((double)x0, (double)x0, qc);
+                    qc = fma((double)x1, (double)x1, qc);
+                    if (!inreg) *reinterpret_cast<float2*>(zw + off + i) = f[c];
                 }
             }
+            if (z != 0.0f) {  // a non-finite sample in this lane's part
+                mc = 0.0f;
+                qc = 0.0;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int i = base + 2 * lane + 128 * c;
+                    if (i < a.W_block) {
+                        const float x0 = f[c].x, x1 = f[c].y;
+                        if (!isfinite(x0) || !isfinite(x1)) nf = 1;
+                        const float y0 = isfinite(x0) ? x0 : 0.0f, y1 = isfinite(x1) ? x1 : 0.0f;
+                        mc = fmaxf(mc, fmaxf(fabsf(y0), fabsf(y1)));
+                        qc = fma((double)y0, (double)y0, qc);
+                        qc = fma((double)y1, (double)y1, qc);
+                    }
+                }
+            }
+            m = fmaxf(m, mc);
+            q += qc;
         }
-        st.smax = wave_max(m);
-        st.sumsq = wave_sum(q);
-        st.nonfinite = wave_or(nf);
+        if (!inreg) {  // zeros before and after the window in zw
+            for (int j = lane; j < off; j += 64) zw[j] = 0.0f;
+            for (int j = off + a.W_block + lane; j < plane_len; j += 64) zw[j] = 0.0f;
+        }
+        st.smax = (double)wave_max_dpp(m);
+        st.sumsq = wave_sum_dpp(q);
+        st.nonfinite = __ballot(nf) != 0;
     }
-    const Choice c = choose(a, st);
+    const Choice c = choose(a, st, ksv);
+    gfloat* const outp = (gfloat*)a.out;
+    gdouble* const fldp = (gdouble*)a.fields;
+    const int64_t ob = it.o0 - it.j_lo;  // r_out index of local output m: ob + m
     write_info(a, it, c, st, true, lane == 0);
     if ((c.flags & APX_FLAG_NONFINITE) || (c.flags & APX_FLAG_ZERO)) {
         const float v = (c.flags & APX_FLAG_NONFINITE) ? NAN : 0.0f;
@@ -2109,31 +2214,54 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
         }
         return;
     }
-    // companded samples (eq. 2, as sq_at), as digit planes
+    // Blocks walk the k-steps from different starting chunks (the integer sums do not depend on
+    // the order), so the waves of the GPU do not all read the same fragment rows at once.  The
+    // fragments load during the companding, not beside the window: registers held through the
+    // window's phase would cost a wave per SIMD.
+    const int kpad = (ksteps + I8_KC - 1) / I8_KC * I8_KC;
+    const int nchunk = kpad / I8_KC;
+    const int c_first = (int)(blk % nchunk);
+    i8x16 bc[I8_KC][SK ? 2 : 1], bn[I8_KC][SK ? 2 : 1];
+#pragma unroll
+    for (int kk = 0; kk < I8_KC; ++kk) {
+        bc[kk][0] = frag[(c_first * I8_KC + kk) * 64 + lane];
+        if constexpr (SK) bc[kk][SK ? 1 : 0] = frag[(kpad + c_first * I8_KC + kk) * 64 + lane];
+    }
+    // companded samples (eq. 2, as sq_at), as digit planes: byte j of a plane is a digit of
+    // s~[j - (N - 1)], zero wherever that sample is outside [0, nvalid) (samples past nwin
+    // were loaded as zeros)
     const bool split_s = SS;
-    const int off = a.N - 1;
-    int* p0 = reinterpret_cast<int*>(lds_i8);
-    int* p1 = reinterpret_cast<int*>(lds_i8 + plane_len);
-    // branch-free: every read is a clamped in-window index, samples outside [0, nvalid) select 0
-    const int wmax = a.W_block - 1;
-#pragma unroll 4
-    for (int w4 = lane; w4 < plane_len / 4; w4 += 64) {
-        int lo4 = 0, hi4 = 0;
-        float x[4];
+    if (inreg) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[e] = win[min(max(4 * w4 + e - off, 0), wmax)];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = 4 * w4 + e - off;
-            const int q = (int)rint(c.cs * (double)x[e]);
-            const int v = (i >= 0 && i < it.nvalid) ? q : 0;
-            int lo, hi;
-            i8_digits(v, split_s, lo, hi);
-            lo4 |= (lo & 255) << (8 * e);
-            hi4 |= (hi & 255) << (8 * e);
+        for (int c2 = 0; c2 < CH; ++c2) {
+            const int i = 2 * lane + 128 * c2;
+            if (128 * c2 < a.W_block && i < a.W_block) {
+                int lo0, hi0, lo1, hi1;
+                i8_digits((int)rint(c.cs * (double)f[c2].x), split_s, lo0, hi0);
+                i8_digits((int)rint(c.cs * (double)f[c2].y), split_s, lo1, hi1);
+                *reinterpret_cast<unsigned short*>(lds_i8 + off + i) = (unsigned short)((lo0 & 255) | ((lo1 & 255) << 8));
+                if (split_s)
+                    *reinterpret_cast<unsigned short*>(lds_i8 + plane_len + off + i) =
+                        (unsigned short)((hi0 & 255) | ((hi1 & 255) << 8));
+            }
         }
-        p0[w4] = lo4;
-        if (split_s) p1[w4] = hi4;
+    } else {
+#pragma unroll 2
+        for (int w4 = lane; w4 < plane_len / 4; w4 += 64) {
+            const float4 x4 = *reinterpret_cast<const float4*>(zw + 4 * w4);
+            const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+            int lo4 = 0, hi4 = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int v = (int)rint(c.cs * (double)x[e]);
+                int lo, hi;
+                i8_digits(v, split_s, lo, hi);
+                lo4 |= (lo & 255) << (8 * e);
+                hi4 |= (hi & 255) << (8 * e);
+            }
+            p0[w4] = lo4;
+            if (split_s) p1[w4] = hi4;
+        }
     }
     wave_lds_sync();
     const int j0 = it.j_lo & ~15;
@@ -2143,46 +2271,35 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
     const char* a1p = a0p + plane_len;
     // every pass computes TM tiles over kpad k-steps (the planes and the zero-padded fragment
     // rows cover them); a last pass with fewer tiles repeats the last tile, and outputs past j_hi
-    // are not stored.  Blocks walk the k-steps from different starting chunks (the integer sums
-    // do not depend on the order), so the waves of the GPU do not all read the same fragment
-    // rows of the table at once.
-    const int kpad = (ksteps + I8_KC - 1) / I8_KC * I8_KC;
-    const int nchunk = kpad / I8_KC;
-    const int c_first = (int)(blk % nchunk);
+    // are not stored.  A pass ends with the next pass's first chunk in bc.
     constexpr int NACC = SS && SK ? 3 : (SS || SK ? 2 : 1);
-    // one-digit operands: two accumulator sets (even and odd k-steps) for independent MFMA chains
-    constexpr int AS = NACC == 1 ? 2 : 1;
+    // one accumulator set per digit product: a second set for independent MFMA chains measured
+    // slower, the registers it takes costing a wave per SIMD
     for (int t0 = 0; t0 < ntiles; t0 += TM) {
-        i32x16 acc[NACC * AS][TM];
+        i32x16 acc[NACC][TM];
 #pragma unroll
-        for (int g = 0; g < NACC * AS; ++g)
+        for (int g = 0; g < NACC; ++g)
 #pragma unroll
             for (int u = 0; u < TM; ++u)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[g][u][r] = 0;
-        i8x16 bc[I8_KC][SK ? 2 : 1], bn[I8_KC][SK ? 2 : 1];
         int tofs[TM];  // tile origin in the planes
 #pragma unroll
         for (int u = 0; u < TM; ++u) tofs[u] = j0 + min(t0 + u, ntiles - 1) * I8_TILE;
-        {
-            const int kc = c_first * I8_KC;
-#pragma unroll
-            for (int kk = 0; kk < I8_KC; ++kk) {
-                bc[kk][0] = frag[(kc + kk) * 64 + lane];
-                if constexpr (SK) bc[kk][SK ? 1 : 0] = frag[(kpad + kc + kk) * 64 + lane];
-            }
-        }
         for (int ci = 0; ci < nchunk; ++ci) {
             int c = c_first + ci;
             if (c >= nchunk) c -= nchunk;
             const int k0 = c * I8_KC;
             int cn = c + 1;
             if (cn >= nchunk) cn -= nchunk;
-            const int kn = cn * I8_KC;  // next chunk (after the last one: the first again, unused)
+            const int kn = cn * I8_KC;  // next chunk (after the last one: the next pass's first)
+            const bool pre = ci + 1 < nchunk || t0 + TM < ntiles;
+            if (pre) {
 #pragma unroll
-            for (int kk = 0; kk < I8_KC; ++kk) {
-                bn[kk][0] = frag[(kn + kk) * 64 + lane];
-                if constexpr (SK) bn[kk][SK ? 1 : 0] = frag[(kpad + kn + kk) * 64 + lane];
+                for (int kk = 0; kk < I8_KC; ++kk) {
+                    bn[kk][0] = frag[(kn + kk) * 64 + lane];
+                    if constexpr (SK) bn[kk][SK ? 1 : 0] = frag[(kpad + kn + kk) * 64 + lane];
+                }
             }
 #pragma unroll
             for (int kk = 0; kk < I8_KC; ++kk) {
@@ -2190,8 +2307,7 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
                 for (int u = 0; u < TM; ++u) {
                     const int ofs = tofs[u] + 32 * (k0 + kk);
                     const i8x16 x0 = *reinterpret_cast<const i8x16*>(a0p + ofs);
-                    const int g0 = AS == 2 ? (kk & 1) : 0;  // static once the k-step loop is unrolled
-                    acc[g0][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x0, bc[kk][0], acc[g0][u], 0, 0, 0);
+                    acc[0][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x0, bc[kk][0], acc[0][u], 0, 0, 0);
                     if constexpr (SK)
                         acc[1][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x0, bc[kk][SK ? 1 : 0], acc[SK ? 1 : 0][u],
                                                                           0, 0, 0);
@@ -2205,10 +2321,12 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
                     }
                 }
             }
+            if (pre) {
 #pragma unroll
-            for (int kk = 0; kk < I8_KC; ++kk) {
-                bc[kk][0] = bn[kk][0];
-                if constexpr (SK) bc[kk][SK ? 1 : 0] = bn[kk][SK ? 1 : 0];
+                for (int kk = 0; kk < I8_KC; ++kk) {
+                    bc[kk][0] = bn[kk][0];
+                    if constexpr (SK) bc[kk][SK ? 1 : 0] = bn[kk][SK ? 1 : 0];
+                }
             }
         }
         // D[r] of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
@@ -2220,11 +2338,13 @@ __global__ void __launch_bounds__(64 * I8_WPB, 2) k_i8(RunArgs a0, const i8x16* 
             for (int r = 0; r < 16; ++r) {
                 const int m = m0 + 32 * (8 * (r >> 2) + 4 * half + (r & 3)) + row;
                 if (m >= it.j_lo && m < it.j_hi) {
-                    long long v = (long long)acc[0][u][r];
-                    if constexpr (AS == 2) v += (long long)acc[AS - 1][u][r];
-                    if constexpr (NACC > 1) v += 128LL * (long long)acc[NACC > 1 ? 1 : 0][u][r];
-                    if constexpr (NACC > 2) v += 16384LL * (long long)acc[NACC - 1][u][r];
-                    put(a, it, m, (double)v, c.inv);  // eq. (16)
+                    // exact in FP64: every partial sum stays below 2^53 in magnitude
+                    double v = (double)acc[0][u][r];
+                    if constexpr (NACC > 1) v = fma(128.0, (double)acc[NACC > 1 ? 1 : 0][u][r], v);
+                    if constexpr (NACC > 2) v = fma(16384.0, (double)acc[NACC - 1][u][r], v);
+                    v += 0.0;  // a zero digit is +0, as the integer it stands for
+                    if (fldp) fldp[ob + m] = v;
+                    outp[ob + m] = (float)(c.inv * v);  // eq. (16)
                 }
             }
         }
@@ -2284,10 +2404,12 @@ hipError_t i8_set_lds(int bytes) {
     return hipSuccess;
 }
 
-// LDS region of one block: two digit planes and the raw window.  A workgroup holds I8_WPB
+// LDS region of one block: two digit planes and, for a window longer than I8_REG_WIN, the
+// zero-padded window.  A workgroup holds I8_WPB
 // regions while that leaves room for two workgroups per CU, else one.
 static size_t i8_region(int plane_len, int W_block) {
-    return ((size_t)2 * plane_len + 4 * (size_t)W_block + 15) & ~(size_t)15;
+    // a longer window passes through LDS zero-padded to plane_len samples
+    return ((size_t)(W_block <= I8_REG_WIN ? 2 : 6) * plane_len + 15) & ~(size_t)15;
 }
 static int i8_wpb(size_t region) { return I8_WPB * region <= 81920 ? I8_WPB : 1; }
 size_t i8_lds_bytes(int plane_len, int W_block) {
