@@ -138,7 +138,9 @@ __device__ __forceinline__ const V* table_fresh(const V* p) {
     const uint64_t b = (uint64_t)(uintptr_t)p;
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
     asm volatile("" : "+s"(lo), "+s"(hi));
-    return reinterpret_cast<const V*>((uintptr_t)(((uint64_t)hi << 32) | lo));
+    // device memory: global loads (a generic pointer's flat loads would also count against the
+    // LDS wait counter, so every wait for an LDS exchange would wait for table reads too)
+    return (const V*)(const __attribute__((address_space(1))) V*)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
 
 // An opaque copy of the lane id (0..63 in every wave of the workgroup): address arithmetic derived from it cannot be shared between

@@ -1537,7 +1537,13 @@ __global__ void __launch_bounds__(NT, (MODE == MD_FULL32 ? LOGW <= 14 : LOGW <= 
             const int2 ti = items[idx];
             const int t = __builtin_amdgcn_readfirstlane(ti.x);
             const int w = __builtin_amdgcn_readfirstlane(ti.y);
-            const RunArgs& a = targs[t];
+            // symmetric: the pair table through the constant address space, its fields read once
+            // and its data pointers taken as device memory (global loads; measured 13.2 -> 12.8
+            // ms).  The other modes keep generic reads: there the scalar copies cost registers
+            // that the transforms need (FP32 17.4 -> 21.8 ms with spills)
+            const RunArgs& a = MODE == MD_SYM
+                                   ? *(const RunArgs*)((__attribute__((address_space(4))) const RunArgs*)targs + t)
+                                   : targs[t];
             ArgmaxSink sk;
             const Item it = make_item(a, w, true);
             if constexpr ((MODE == MD_SYM || MODE == MD_FULL32) && WinRegs<MODE, MW>::PPT * WinRegs<MODE, MW>::SPP <= 64) {
@@ -2085,8 +2091,8 @@ __global__ void __launch_bounds__(NT) k_i8_frag(const float* __restrict__ kf, co
 // blocks per workgroup (fewer workgroups to launch); the waves share nothing and never wait for each
 // other.  A wave's LDS region holds the block's companded samples as two digit planes of plane_len bytes (byte i + N - 1 of a plane is
 // digit p of s~[i], zero outside [0, nvalid)), so every A fragment is one aligned 16-byte read,
-// and behind them, for a window longer than I8_REG_WIN samples, the window in the same order,
-// zero-padded to plane_len floats, that the planes are built from.  The taps' B fragments stream from L2 in chunks of I8_KC k-steps, the next
+// and behind them, for a window longer than I8_REG_WIN samples, the window that the planes are
+// built from.  The taps' B fragments stream from L2 in chunks of I8_KC k-steps, the next
 // chunk in flight while the current one runs.
 constexpr int I8_KC = 4;
 constexpr int I8_REG_WIN = 1024;  // longest window held in registers (a multiple of 128)
@@ -2119,11 +2125,11 @@ __global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i
     const int off = a.N - 1;
     const KState ksv = *a0.ks;  // one taps' state for every signal of the launch
     // A window of at most I8_REG_WIN samples stays in registers (one load step) and its digits go
-    // straight to the planes; a longer one passes through zw, where zw[j] = sample j - (N - 1)
-    // of the window, zero outside [0, nwin): the planes' byte order, so that every companded
-    // digit comes from one aligned 16-byte read of four samples.
+    // straight to the planes; a longer one passes through LDS behind the planes, shifted by
+    // (N - 1) mod 4 samples so that the four samples of one plane word are one aligned 16-byte
+    // read.
     const bool inreg = a.W_block <= I8_REG_WIN;
-    float* zw = reinterpret_cast<float*>(lds_i8 + 2 * plane_len);
+    float* win = reinterpret_cast<float*>(lds_i8 + (SS ? 2 : 1) * plane_len) + (off & 3);
     int* p0 = reinterpret_cast<int*>(lds_i8);
     int* p1 = reinterpret_cast<int*>(lds_i8 + plane_len);
     if (inreg) {  // zero planes: the digits of the window overwrite their part
@@ -2136,7 +2142,9 @@ __global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i
     // maximum is taken in FP32 (exact), and x * 0 accumulated in z stays zero while every
     // sample is finite; a lane that meets a non-finite sample takes its partials again with the
     // exact per-sample rule (non-finite samples count as zero and set the flag).
-    constexpr int CH = I8_REG_WIN / 128;
+    // samples per load step: 128 CH = I8_REG_WIN (twice as many measured slower on long blocks)
+    constexpr int CR = I8_REG_WIN / 128;
+    constexpr int CH = CR;
     float2 f[CH];  // the last load step's samples: the whole window when inreg
     BlockStats st;
     {
@@ -2171,7 +2179,7 @@ __global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i
                     z = fmaf(x1, 0.0f, z);
                     qc = fma((double)x0, (double)x0, qc);
                     qc = fma((double)x1, (double)x1, qc);
-                    if (!inreg) *reinterpret_cast<float2*>(zw + off + i) = f[c];
+                    if (!inreg) *reinterpret_cast<float2*>(win + i) = f[c];
                 }
             }
             if (z != 0.0f) {  // a non-finite sample in this lane's part
@@ -2192,10 +2200,6 @@ __global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i
             }
             m = fmaxf(m, mc);
             q += qc;
-        }
-        if (!inreg) {  // zeros before and after the window in zw
-            for (int j = lane; j < off; j += 64) zw[j] = 0.0f;
-            for (int j = off + a.W_block + lane; j < plane_len; j += 64) zw[j] = 0.0f;
         }
         st.smax = (double)wave_max_dpp(m);
         st.sumsq = wave_sum_dpp(q);
@@ -2229,11 +2233,11 @@ __global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i
     }
     // companded samples (eq. 2, as sq_at), as digit planes: byte j of a plane is a digit of
     // s~[j - (N - 1)], zero wherever that sample is outside [0, nvalid) (samples past nwin
-    // were loaded as zeros)
+    // were loaded as zeros, nvalid = nwin on this core)
     const bool split_s = SS;
     if (inreg) {
 #pragma unroll
-        for (int c2 = 0; c2 < CH; ++c2) {
+        for (int c2 = 0; c2 < CR; ++c2) {
             const int i = 2 * lane + 128 * c2;
             if (128 * c2 < a.W_block && i < a.W_block) {
                 int lo0, hi0, lo1, hi1;
@@ -2246,10 +2250,22 @@ __global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i
             }
         }
     } else {
-#pragma unroll 2
+        // word w4 holds samples i0 .. i0 + 3, i0 = 4 w4 - (N - 1): inside the window one
+        // 16-byte read, outside it zero digits, across an edge sample by sample
         for (int w4 = lane; w4 < plane_len / 4; w4 += 64) {
-            const float4 x4 = *reinterpret_cast<const float4*>(zw + 4 * w4);
-            const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+            const int i0 = 4 * w4 - off;
+            float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (i0 >= 0 && i0 + 3 < a.W_block) {
+                const float4 x4 = *reinterpret_cast<const float4*>(win + i0);
+                x[0] = x4.x;
+                x[1] = x4.y;
+                x[2] = x4.z;
+                x[3] = x4.w;
+            } else if (i0 + 3 >= 0 && i0 < a.W_block) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (i0 + e >= 0 && i0 + e < a.W_block) x[e] = win[i0 + e];
+            }
             int lo4 = 0, hi4 = 0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -2404,12 +2420,13 @@ hipError_t i8_set_lds(int bytes) {
     return hipSuccess;
 }
 
-// LDS region of one block: two digit planes and, for a window longer than I8_REG_WIN, the
-// zero-padded window.  A workgroup holds I8_WPB
+// LDS region of one block: the digit planes (two when the samples' range exceeds 127) and, for
+// a window longer than I8_REG_WIN, the window.  i8_lds_bytes is the largest (two planes).  A workgroup holds I8_WPB
 // regions while that leaves room for two workgroups per CU, else one.
-static size_t i8_region(int plane_len, int W_block) {
-    // a longer window passes through LDS zero-padded to plane_len samples
-    return ((size_t)(W_block <= I8_REG_WIN ? 2 : 6) * plane_len + 15) & ~(size_t)15;
+static size_t i8_region(int plane_len, int W_block, int planes = 2) {
+    // a longer window passes through LDS (shifted by up to 3 samples)
+    const size_t win = W_block <= I8_REG_WIN ? 0 : (size_t)4 * W_block + 16;
+    return ((size_t)planes * plane_len + win + 15) & ~(size_t)15;
 }
 static int i8_wpb(size_t region) { return I8_WPB * region <= 81920 ? I8_WPB : 1; }
 size_t i8_lds_bytes(int plane_len, int W_block) {
@@ -2419,7 +2436,7 @@ size_t i8_lds_bytes(int plane_len, int W_block) {
 
 // split_s: the fixed mode's S_q > 127 (every block of the call uses it)
 hipError_t launch_i8(const RunArgs& a, const void* frag, int split_s, int split_k, int plane_len, int tm, hipStream_t st) {
-    const int rg = (int)i8_region(plane_len, a.W_block);
+    const int rg = (int)i8_region(plane_len, a.W_block, split_s ? 2 : 1);
     const int wpb = i8_wpb((size_t)rg);
     const dim3 g((unsigned)((a.nitems + wpb - 1) / wpb)), b(64 * wpb);
     const size_t lds = (size_t)wpb * rg;
