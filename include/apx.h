@@ -193,9 +193,9 @@ apx_status apx_run_auto_noalloc(apx_ctx ctx, apx_kernel kern, const float* s_in,
 
 /* ---- Autotuning ---------------------------------------------------------------------------
  * apx_tune: for taps k (device, N FP32), the operation and params->mode (and its companding and
- * SNR settings), prepares the kernel on every core that can run the shape (time-domain, integer
- * matrix cores for fixed packed modes, with one to three output tiles per pass over the taps,
- * FFT core with LDS passes / one wavefront per block / a
+ * SNR settings), prepares the kernel on every core that can run the shape (time-domain core
+ * with 4 and 8 outputs per thread, integer matrix cores for fixed packed modes with one to three
+ * output tiles per pass over the taps, FFT core with LDS passes / one wavefront per block / a
  * group of wavefronts per block, each with its own radix plan) at W_block, or, for W_block = 0,
  * at the three smallest power-of-two block sizes with W >= 2 N; times each on a synthetic signal
  * of L_hint samples (0: 64 blocks, at least 2^16 samples; the number of blocks a call has decides
@@ -216,7 +216,8 @@ typedef struct {
     int32_t core;         /* apx_core */
     int32_t fft_variant;  /* as apx_params.fft_variant (FFT core) */
     int32_t W_block;
-    int32_t tile;         /* integer core: output tiles per pass over the taps (0: other cores) */
+    int32_t tile;         /* integer core: output tiles per pass over the taps; time-domain core:
+                             outputs per thread, 4 or 8 (0: FFT core) */
     double ps_per_output; /* measured time per output sample, picoseconds */
 } apx_tuned;
 apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t W_block, const apx_params* params,

@@ -315,7 +315,7 @@ apx_status launch_block_kernel(apx_kernel k, const RunArgs& a, hipStream_t st) {
     } else if (k->core == APX_CORE_FFT) {
         HIPCHK(launch_fft(a, k->logF, st));
     } else {
-        HIPCHK(launch_td(a, k->td_lds, st));
+        HIPCHK(launch_td(a, k->td_lds, k->td_tile, st));
     }
     return APX_OK;
 }
@@ -616,6 +616,12 @@ apx_status init_kernel(apx_kernel k, apx_ctx ctx, const float* k_in, int32_t N, 
             return fail(APX_E_UNSUPPORTED, "time-domain block needs %zu bytes of LDS (> %d); use the FFT core",
                         k->td_lds, ctx->max_lds);
         }
+        // outputs per thread: 4 while one pass of the workgroup's threads covers the longest
+        // range the block convolves (outputs, or packed words), else 8
+        int range = W_block;  // FP32 / FP64 outputs
+        if (p.mode == MD_SYM) range = W_block / 2 + 1;
+        if (p.mode == MD_ASYM2 || p.mode == MD_ASYM3) range = k->T[p.mode] + N_odd;
+        k->td_tile = range <= 4 * NT ? 4 : 8;
     }
     // device state
     hipStream_t st = (hipStream_t)stream;
@@ -734,6 +740,7 @@ apx_status apx_kernel_create(apx_ctx ctx, const float* k_in, int32_t N, int32_t 
         return r;
     }
     if (tile > 0 && k->core == APX_CORE_INT8) k->i8_tm = tile;
+    if ((tile == 4 || tile == 8) && k->core == APX_CORE_TIME) k->td_tile = tile;
     *out = k;
     return APX_OK;
 }
@@ -939,7 +946,7 @@ apx_status apx_kernel_describe(apx_kernel k, char* buf, int32_t size) {
     char tmp[512];
     int n;
     if (k->core == APX_CORE_TIME) {
-        n = snprintf(tmp, sizeof tmp, "core=time kernel=k_td lds=%zu", k->td_lds);
+        n = snprintf(tmp, sizeof tmp, "core=time kernel=k_td lds=%zu outputs_per_thread=%d", k->td_lds, k->td_tile);
     } else if (k->core == APX_CORE_INT8) {
         n = snprintf(tmp, sizeof tmp, "core=int8 kernel=k_i8 ksteps=%d lds=%zu split_k=%d tiles_per_pass=%d",
                      i8_ksteps(k->N_odd), i8_lds_bytes(k->i8_plane, k->W_block), k->i8_splitk, k->i8_tm);

@@ -50,7 +50,8 @@ struct TuneKey {
 struct TuneVal {
     int32_t core, variant, W_block;
     double ps_per_output;
-    int32_t tile = 0;  // integer core: output tiles per pass (0: the shape's default)
+    int32_t tile = 0;  // integer core: output tiles per pass; time-domain core: outputs per thread
+                       // (0: the shape's default)
 };
 }  // namespace apx
 
@@ -86,6 +87,7 @@ struct apx_kernel_s {
     int i8_plane = 0;
     int i8_splitk = 0;
     int i8_tm = 3;  // output tiles per pass (1 to 3)
+    int td_tile = 8;  // time-domain core: outputs per thread (4 or 8)
     int32_t S[4] = {0, 0, 0, 0}, K[4] = {0, 0, 0, 0};
     int64_t R[4] = {0, 0, 0, 0};
     int32_t T[4] = {0, 0, 0, 0};

@@ -93,7 +93,7 @@ hipError_t launch_spectrum(const double* taps, int32_t ntaps, int32_t Fw, const 
                            double2* spec, hipStream_t st);
 hipError_t launch_spectrum32(const float* taps, int32_t ntaps, int32_t Fw, const float2* twf,
                              float2* spec, hipStream_t st);
-hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_td(const RunArgs& a, size_t lds_bytes, int tile, hipStream_t st);  // tile: 4 or 8 outputs per thread
 hipError_t launch_fft(const RunArgs& a, int logF, hipStream_t st);
 hipError_t launch_calib(const RunArgs& a, int64_t block, int32_t Q, double* partial, int32_t nparts,
                         hipStream_t st);

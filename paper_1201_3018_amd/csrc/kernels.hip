@@ -424,56 +424,58 @@ __device__ __forceinline__ void asym_unpack_store(const RunArgs& a, const Item& 
 // ------------------------------------------------------------------------------------------
 // Time-domain core
 // ------------------------------------------------------------------------------------------
-constexpr int RB = 8;    // consecutive outputs per thread
-constexpr int KUN = 8;   // taps per unrolled step (tap arrays are zero padded to a multiple)
+constexpr int RB = 8;    // most consecutive outputs per thread (margins of the LDS buffers)
+constexpr int KUN = 8;   // tap arrays are zero padded to a multiple of 8
 
 // r[m - mlo] = sum_n x[m - n] kt[n] for m in [mlo, mhi).  x: LDS, logical index i at x[i],
-// valid (zero filled) for i in [mlo - npad - 8, mhi + RB).  Each thread owns RB = 8 consecutive
-// outputs m0 .. m0+7 and walks the taps in steps of 8: step n0 reads x[m0 - n0 - 8 .. m0 - n0 + 7],
-// the chunk x[m0 - n0 .. m0 - n0 + 7] it shares with the previous step stays in registers, so one
-// chunk of 8 samples is read per 64 FMAs (the two chunk registers swap roles every step).  The
-// FMA order per output is n = 0, 1, 2, ... as in the plain sum.
-template <typename T>
+// valid (zero filled) for i in [mlo - npad - 8, mhi + RB).  Each thread owns C consecutive
+// outputs m0 .. m0+C-1 (the tile, 4 or 8) and walks the taps in steps of C: step n0 reads
+// x[m0 - n0 - C .. m0 - n0 + C - 1], the chunk x[m0 - n0 .. m0 - n0 + C - 1] it shares with the
+// previous step stays in registers, so one chunk of C samples is read per C^2 FMAs (the two chunk
+// registers swap roles every step).  C = 8 reads less LDS per FMA; C = 4 keeps twice as many
+// threads busy on a block of fewer than 8 NT outputs.  The FMA order per output is n = 0, 1, 2,
+// ... as in the plain sum.
+template <typename T, int C>
 __device__ __forceinline__ void td_step(const T* hi, const T* lo, const T* kt, int n0, T* acc) {
-    // hi[e] = x[m0 - n0 + e], lo[e] = x[m0 - n0 - 8 + e]; output i, tap n0 + t reads x[m0 + i - n0 - t]
+    // hi[e] = x[m0 - n0 + e], lo[e] = x[m0 - n0 - C + e]; output i, tap n0 + t reads x[m0 + i - n0 - t]
 #pragma unroll
-    for (int t = 0; t < KUN; ++t) {
+    for (int t = 0; t < C; ++t) {
         const T kv = ld_uniform(kt, n0 + t);
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
+        for (int i = 0; i < C; ++i) {
             const int e = i - t;
-            acc[i] = fma(e >= 0 ? hi[e] : lo[8 + e], kv, acc[i]);
+            acc[i] = fma(e >= 0 ? hi[e] : lo[C + e], kv, acc[i]);
         }
     }
 }
 
-template <typename T>
+template <typename T, int C>
 __device__ __forceinline__ void td_core(const T* x, const T* kt, int npad, int mlo, int mhi, T* r) {
-    static_assert(RB == 8 && KUN == 8, "the chunk walk assumes 8 outputs and 8 taps per step");
-    for (int m0 = mlo + RB * threadIdx.x; m0 < mhi; m0 += RB * NT) {
-        T acc[RB];
+    static_assert((C == 4 || C == 8) && C <= RB && KUN % C == 0, "tiles of 4 or 8 outputs");
+    for (int m0 = mlo + C * threadIdx.x; m0 < mhi; m0 += C * NT) {
+        T acc[C];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) acc[i] = (T)0;
+        for (int i = 0; i < C; ++i) acc[i] = (T)0;
         const T* xp = x + m0;
-        T c0[8], c1[8];
+        T c0[C], c1[C];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) c0[e] = xp[e];
+        for (int e = 0; e < C; ++e) c0[e] = xp[e];
         int n0 = 0;
-        for (; n0 + 2 * KUN <= npad; n0 += 2 * KUN) {
+        for (; n0 + 2 * C <= npad; n0 += 2 * C) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) c1[e] = xp[e - n0 - 8];
-            td_step<T>(c0, c1, kt, n0, acc);
+            for (int e = 0; e < C; ++e) c1[e] = xp[e - n0 - C];
+            td_step<T, C>(c0, c1, kt, n0, acc);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) c0[e] = xp[e - n0 - 16];
-            td_step<T>(c1, c0, kt, n0 + KUN, acc);
+            for (int e = 0; e < C; ++e) c0[e] = xp[e - n0 - 2 * C];
+            td_step<T, C>(c1, c0, kt, n0 + C, acc);
         }
-        if (n0 < npad) {  // npad is a multiple of 8: one step left
+        if (n0 < npad) {  // npad is a multiple of 8, so of C: one step left
 #pragma unroll
-            for (int e = 0; e < 8; ++e) c1[e] = xp[e - n0 - 8];
-            td_step<T>(c0, c1, kt, n0, acc);
+            for (int e = 0; e < C; ++e) c1[e] = xp[e - n0 - C];
+            td_step<T, C>(c0, c1, kt, n0, acc);
         }
 #pragma unroll
-        for (int i = 0; i < RB; ++i)
+        for (int i = 0; i < C; ++i)
             if (m0 + i < mhi) r[m0 + i - mlo] = acc[i];
     }
 }
@@ -494,7 +496,7 @@ size_t td_lds_bytes(int mode, int N, int W_block, int T2, int T3) {
     return b;
 }
 
-template <int MODE>
+template <int MODE, int C>
 __device__ void td_item(const RunArgs& a, const Item& it, const Choice& c, char* lds) {
     const int N = a.N;
     if constexpr (MODE == MD_FULL32 || MODE == MD_FULL64) {
@@ -512,7 +514,7 @@ __device__ void td_item(const RunArgs& a, const Item& it, const Choice& c, char*
         }
         __syncthreads();
         const T* kt = (MODE == MD_FULL32) ? (const T*)a.kf : (const T*)a.kd;
-        td_core<T>(x, kt, npad, it.j_lo, it.j_hi, res);
+        td_core<T, C>(x, kt, npad, it.j_lo, it.j_hi, res);
         __syncthreads();
         for (int j = it.j_lo + threadIdx.x; j < it.j_hi; j += NT) {
             const int64_t o = it.o0 + (j - it.j_lo);
@@ -541,7 +543,7 @@ __device__ void td_item(const RunArgs& a, const Item& it, const Choice& c, char*
         if (mlo < 0) mlo = 0;
         const int mhi = (it.j_hi + 1) >> 1;
         (void)nk;
-        td_core<double>(x, a.kq[MD_SYM], npad, mlo, mhi, res);
+        td_core<double, C>(x, a.kq[MD_SYM], npad, mlo, mhi, res);
         __syncthreads();
         sym_unpack_store(a, it, c, [&](int m) -> double { return m < mlo ? 0.0 : res[m - mlo]; });
     } else {
@@ -573,14 +575,15 @@ __device__ void td_item(const RunArgs& a, const Item& it, const Choice& c, char*
         }
         __syncthreads();
         const int m_first0 = (it.w == 0) ? 0 : N - 1;
-        td_core<double>(x, a.kq[MODE], npad, m_first0, lw, res);
+        td_core<double, C>(x, a.kq[MODE], npad, m_first0, lw, res);
         __syncthreads();
         asym_unpack_store<MM>(a, it, c, T, base_off, m_first0, N - 1, lw,
                               [&](int m) -> double { return res[m - m_first0]; });
     }
 }
 
-template <bool MANY>
+// C: outputs per thread (the tile of td_core)
+template <bool MANY, int C>
 __global__ void __launch_bounds__(NT) k_td(RunArgs a0) {
     extern __shared__ char lds_td[];
     int64_t item = blockIdx.x;
@@ -598,23 +601,31 @@ __global__ void __launch_bounds__(NT) k_td(RunArgs a0) {
         return;
     }
     switch (c.mode) {
-        case MD_SYM: td_item<MD_SYM>(a, it, c, lds_td); break;
-        case MD_ASYM2: td_item<MD_ASYM2>(a, it, c, lds_td); break;
-        case MD_ASYM3: td_item<MD_ASYM3>(a, it, c, lds_td); break;
-        case MD_FULL64: td_item<MD_FULL64>(a, it, c, lds_td); break;
-        default: td_item<MD_FULL32>(a, it, c, lds_td); break;
+        case MD_SYM: td_item<MD_SYM, C>(a, it, c, lds_td); break;
+        case MD_ASYM2: td_item<MD_ASYM2, C>(a, it, c, lds_td); break;
+        case MD_ASYM3: td_item<MD_ASYM3, C>(a, it, c, lds_td); break;
+        case MD_FULL64: td_item<MD_FULL64, C>(a, it, c, lds_td); break;
+        default: td_item<MD_FULL32, C>(a, it, c, lds_td); break;
     }
 }
 
-hipError_t launch_td(const RunArgs& a, size_t lds_bytes, hipStream_t st) {
+// tile: outputs per thread, 4 or 8
+hipError_t launch_td(const RunArgs& a, size_t lds_bytes, int tile, hipStream_t st) {
     if (lds_bytes > 65536) {
-        for (const void* f : {(const void*)k_td<false>, (const void*)k_td<true>}) {
+        for (const void* f : {(const void*)k_td<false, 4>, (const void*)k_td<true, 4>, (const void*)k_td<false, 8>,
+                              (const void*)k_td<true, 8>}) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
             if (e != hipSuccess) return e;
         }
     }
-    if (a.many) hipLaunchKernelGGL(k_td<true>, dim3((unsigned)a.nitems), dim3(NT), lds_bytes, st, a);
-    else hipLaunchKernelGGL(k_td<false>, dim3((unsigned)a.nitems), dim3(NT), lds_bytes, st, a);
+    const dim3 g((unsigned)a.nitems), b(NT);
+    if (tile == 4) {
+        if (a.many) hipLaunchKernelGGL((k_td<true, 4>), g, b, lds_bytes, st, a);
+        else hipLaunchKernelGGL((k_td<false, 4>), g, b, lds_bytes, st, a);
+    } else {
+        if (a.many) hipLaunchKernelGGL((k_td<true, 8>), g, b, lds_bytes, st, a);
+        else hipLaunchKernelGGL((k_td<false, 8>), g, b, lds_bytes, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -50,8 +50,9 @@ std::string arch_of(int device) {
 }
 
 // Table line: arch, N_odd, op, mode, W_block asked for (0: chosen too), then core, FFT
-// implementation, W_block, picoseconds per output measured and the integer core's output tiles
-// per pass (a line without the last field reads as 0: the shape's default).
+// implementation, W_block, picoseconds per output measured and the tile (integer core: output
+// tiles per pass, time-domain core: outputs per thread; a line without the field reads as 0,
+// the shape's default).
 bool parse(const char* line, std::string* arch, apx::TuneKey* k, apx::TuneVal* v) {
     char a[128];
     double us = 0.0;
@@ -61,7 +62,8 @@ bool parse(const char* line, std::string* arch, apx::TuneKey* k, apx::TuneVal* v
     if (got < 9) return false;
     *arch = a;
     v->ps_per_output = us;
-    v->tile = (got == 10 && tile >= 1 && tile <= 3) ? tile : 0;
+    const bool ok = v->core == APX_CORE_INT8 ? (tile >= 1 && tile <= 3) : v->core == APX_CORE_TIME && (tile == 4 || tile == 8);
+    v->tile = (got == 10 && ok) ? tile : 0;
     return true;
 }
 
@@ -207,9 +209,10 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
     char table[4096];
     int used = 0;
     table[0] = 0;
-    // candidates: time-domain core, integer core (fixed packed modes) with each count of output
-    // tiles per pass up to the tiles a block has, FFT core in each of its implementations (LDS
-    // passes; one wave per block; a group of waves per block).  Every
+    // candidates: time-domain core with 4 and 8 outputs per thread, integer core (fixed packed
+    // modes) with each count of output tiles per pass up to the tiles a block has, FFT core in
+    // each of its implementations (LDS passes; one wave per block; a group of waves per block).
+    // Every
     // candidate that runs the shape is prepared first; then rounds of timed runs visit them in
     // turn and each keeps its fastest round, so that a slow moment of the device (another
     // process, a profiler) does not decide the choice.
@@ -227,12 +230,21 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
             apx_params p = *params;
             p.core = cv[0];
             p.fft_variant = cv[1];
-            const int ntile =
-                cv[0] == APX_CORE_INT8 ? std::min(3, std::max(1, apx::i8_tiles(N_odd, wb - N_odd - 1))) : 1;
-            for (int t = 1; t <= ntile; ++t) {
+            int tiles[3] = {0, 0, 0}, ntile = 1;
+            if (cv[0] == APX_CORE_INT8) {
+                ntile = std::min(3, std::max(1, apx::i8_tiles(N_odd, wb - N_odd - 1)));
+                for (int t = 0; t < ntile; ++t) tiles[t] = t + 1;
+            } else if (cv[0] == APX_CORE_TIME) {
+                ntile = 2;
+                tiles[0] = 4;
+                tiles[1] = 8;
+            }
+            for (int ti = 0; ti < ntile; ++ti) {
+                const int t = tiles[ti];
                 apx_kernel kern = nullptr;
                 if (apx_kernel_create(ctx, k, N, op, wb, &p, stream, &kern) != APX_OK) break;  // cannot run it
                 if (cv[0] == APX_CORE_INT8) kern->i8_tm = t;
+                if (cv[0] == APX_CORE_TIME) kern->td_tile = t;
                 bool ok = true;
                 for (int i = 0; i < 2 && ok; ++i)
                     ok = apx_run(ctx, kern, sig(i), L, res(i), nullptr, stream) == APX_OK;
@@ -240,7 +252,7 @@ apx_status apx_tune(apx_ctx ctx, const float* k, int32_t N, int32_t op, int32_t 
                     apx_kernel_destroy(kern);
                     break;
                 }
-                cands.push_back(Cand{wb, cv[0], cv[1], cv[0] == APX_CORE_INT8 ? t : 0, kern, INFINITY});
+                cands.push_back(Cand{wb, cv[0], cv[1], t, kern, INFINITY});
             }
         }
     }

@@ -46,6 +46,8 @@ def test_tune_choose_block_and_core(tmp_path, monkeypatch):
     assert kern.describe().startswith(core_name[res["core"]]), kern.describe()
     if res["core"] == apx.APX_CORE_INT8:  # the tuned count of output tiles per pass is used
         assert res["tile"] in (1, 2, 3) and f"tiles_per_pass={res['tile']}" in kern.describe(), kern.describe()
+    elif res["core"] == apx.APX_CORE_TIME:  # and the tuned outputs per thread
+        assert res["tile"] in (4, 8) and f"outputs_per_thread={res['tile']}" in kern.describe(), kern.describe()
     else:
         assert res["tile"] == 0
     s = synth.gaussian(50000, 1001)
@@ -109,6 +111,50 @@ def test_int8_tiles_per_pass_from_table(tmp_path, monkeypatch, mode, S, L, N, Wb
         assert bad.size == 0, f"tiles {tile}: {bad.size} outputs differ, first at {bad[:8]}"
         kern.close()
         ctx.close()
+
+
+@pytest.mark.parametrize("mode,S", [(O.SYM, 0), (O.ASYM2, 0), (O.ASYM3, 0), (O.FULL, 0)])
+@pytest.mark.parametrize("L,N,Wb", [(50000, 256, 1024), (30001, 33, 4096), (20001, 65, 2048)])
+def test_td_outputs_per_thread_from_table(tmp_path, monkeypatch, mode, S, L, N, Wb):
+    """The time-domain core with 4 and with 8 outputs per thread, each taken from a table entry:
+    packed modes equal the oracle bit for bit, FP32 lies within the FP32 bound of the FP64 sum
+    (the FMA order per output is the same for both tiles, so their FP32 outputs are equal too)."""
+    from gpu_checks import fp32_bound
+    No = N if N % 2 else N + 1
+    ctx = apx.Context(0)
+    arch = apx.apx_tune_describe(ctx.h).split(",")[0].split()[1]
+    ctx.close()
+    s, k = synth.ar1(L, 23 + N), synth.hann_lowpass(N, 0.25)
+    amode = {O.SYM: apx.APX_SYM, O.ASYM2: apx.APX_ASYM2, O.ASYM3: apx.APX_ASYM3, O.FULL: apx.APX_FULL_FP32}[mode]
+    Sq = S or (O.max_q(mode, No) if mode != O.FULL else 0)
+    if mode != O.FULL:
+        ref = O.conv_blocked(s, k, Wb, O.fixed_params(s, k, Wb, mode, Sq, Sq))
+    else:
+        ref64, bound = O.conv_direct(s, k), fp32_bound(s, k, Wb, "td")
+    outs = []
+    for tile in (4, 8):
+        path = str(tmp_path / f"tune{tile}.txt")
+        with open(path, "w") as f:
+            f.write(f"{arch} {No} {apx.APX_CONV} {amode} {Wb} {apx.APX_CORE_TIME} 0 {Wb} 1.000 {tile}\n")
+        monkeypatch.setenv("APX_TUNE_FILE", path)
+        ctx = apx.Context(0)
+        kern = apx.Kernel(ctx, _dev(k), Wb, mode=amode, Sq=Sq, Kq=Sq)
+        desc = kern.describe()
+        print("case: time-domain outputs per thread", tile, mode, Sq, L, N, Wb, desc, flush=True)
+        assert desc.startswith("core=time") and f"outputs_per_thread={tile}" in desc, desc
+        out = torch.full((L + N - 1,), float("nan"), dtype=torch.float32, device=DEV)
+        kern.run(_dev(s), out=out)
+        got = out.cpu().numpy()
+        if mode != O.FULL:
+            bad = np.nonzero(got.view(np.int32) != ref.view(np.int32))[0]
+            assert bad.size == 0, f"tile {tile}: {bad.size} outputs differ, first at {bad[:8]}"
+        else:
+            err = np.abs(got.astype(np.float64) - ref64)
+            assert np.all(err <= bound), float(np.nanmax(err - bound))
+        outs.append(got)
+        kern.close()
+        ctx.close()
+    assert np.array_equal(outs[0].view(np.int32), outs[1].view(np.int32))
 
 
 def test_tune_errors():
