@@ -1132,7 +1132,7 @@ def bench_calib(args, wl):
 
 
 # rocprofv3 counter summary per workload and the kernel sources its figures hold for
-TRAFFIC_SUMMARIES = {"c2": ("fft_c2_hbm_counters.md", ("fftw.hip", "fft.h", "internal.h")),
+TRAFFIC_SUMMARIES = {"c2": ("fft_c2_hbm_counters.md", ("fftw.hip", "fft.h", "internal.h", "items.h")),
                      "c3": ("batch_c3_hbm_counters.md", ("kernels.hip", "fft.h", "internal.h")),
                      "c1": ("int8_c1_hbm_counters.md", ("kernels.hip", "items.h", "internal.h"))}
 

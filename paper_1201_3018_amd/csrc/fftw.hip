@@ -661,7 +661,7 @@ __device__ __forceinline__ void wave_item(const RunArgs& a, const WItem& it, con
     const float* src = st + sbase;
     float* dst = a.out + it.o0;
 #pragma unroll 4
-    for (int s = l; s < nout; s += 64) dst[s] = src[s];
+    for (int s = l; s < nout; s += 64) out_store(&dst[s], src[s]);
 }
 
 // LDS slice of one wave: the padded FFT layout (M + M/E points) and Z[M] of the spectral step.
@@ -1242,7 +1242,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
     const int nout = it.j_hi - it.j_lo;
     if constexpr (MODE == MD_FULL32) {
         for (int s = threadIdx.x; s < nout; s += NTH) {
-            out[s] = (float)wd[it.j_lo + s];
+            out_store(&out[s], (float)wd[it.j_lo + s]);
             if (FIELDS) a.fields[it.o0 + s] = 0.0;
         }
     } else if constexpr (MODE == MD_SYM) {
@@ -1282,7 +1282,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
             }
         }
         __syncthreads();
-        for (int s = threadIdx.x; s < nout; s += NTH) out[s] = stg[it.j_lo + s];
+        for (int s = threadIdx.x; s < nout; s += NTH) out_store(&out[s], stg[it.j_lo + s]);
     } else {
         // word N - 1 + u (u < Tit) holds digit q of local output base_off + q Tit + N - 1 + u, i.e.
         // of output s = q Tit + u of the item: one word per thread, its MM digits in turn
@@ -1296,7 +1296,7 @@ __device__ __forceinline__ void group_item(const RunArgs& a, const WItem& it, co
                 const int s = q * Tit + u;
                 if (s < nout) {
                     const double d = dq + 0.0;  // a zero digit is +0
-                    out[s] = (float)(c.inv * d);
+                    out_store(&out[s], (float)(c.inv * d));
                     if (FIELDS) a.fields[it.o0 + s] = d;
                 }
             }

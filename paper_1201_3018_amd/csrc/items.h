@@ -28,4 +28,12 @@ __device__ __forceinline__ const RunArgs& item_args(const RunArgs& a0, int64_t& 
     }
 }
 
+// An output sample r_out[.] = v, stored with the non-temporal hint: outputs are written once and
+// no kernel of the call reads them, so they stream past the caches instead of filling them.  The
+// FFT cores' outputs go out as whole rows of consecutive samples (on the FFT-block workload the
+// multi-wave core ran 24.5 -> 22.2 us with the hint).  The integer and time-domain cores store
+// 128-byte pieces at unaligned offsets and keep plain stores: there the hint raised the HBM write
+// bytes by 8-17% and saved no time.
+__device__ __forceinline__ void out_store(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 }  // namespace apx
