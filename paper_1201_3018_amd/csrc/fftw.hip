@@ -998,6 +998,16 @@ __device__ __forceinline__ void gjoin_spectral_split(cx<T>* reg, const typename 
 // its statistics from the same loads; per-wave partials are combined through `red` in the same
 // order by every thread.  CH float2 loads per thread and step (with four waves and CH = 8 a
 // 4096-sample window is one step: all of its loads in flight together, C2 -0.7 us).
+// Two samples as one 8-byte load with the non-temporal hint (a builtin vector type: the hint
+// takes no struct).  An interior window is read once by its block; the N + 1 samples it shares
+// with the next window come from L2 all the same, and the hint keeps the rest from displacing
+// the tables every block reads (measured 1-3% faster).
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_stream2(const float* p) {
+    const f32x2_t v = __builtin_nontemporal_load(reinterpret_cast<const f32x2_t*>(p));
+    return make_float2(v.x, v.y);
+}
+
 template <int NTH, int CH>
 __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WItem& it, float* win, double* red) {
     double m = 0.0, q = 0.0;
@@ -1015,21 +1025,21 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
     // samples as they are, and x * 0 (NaN exactly for a NaN or infinite x) marks a non-finite
     // one; a thread that met one takes its partials again below, over its finite samples only.
     const bool interior = it.nwin >= a.W_block && it.nvalid >= a.W_block;
-    float z = 0.0f;
+    float z = 0.0f, mf = 0.0f;
     for (int base = 0; base < a.W_block; base += 2 * NTH * CH) {
         float2 f[CH];
         if (interior) {
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int i = base + 2 * ((int)threadIdx.x + NTH * c);  // even, as W_block is
-                if (i < a.W_block) f[c] = *reinterpret_cast<const float2*>(p + i);
+                if (i < a.W_block) f[c] = ld_stream2(p + i);
             }
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int i = base + 2 * ((int)threadIdx.x + NTH * c);
                 if (i < a.W_block) {
                     const double d0 = (double)f[c].x, d1 = (double)f[c].y;
-                    m = fmax(m, fmax(fabs(d0), fabs(d1)));
+                    mf = fmaxf(mf, fmaxf(fabsf(f[c].x), fabsf(f[c].y)));  // exact in FP32
                     q += d0 * d0 + d1 * d1;
                     z = fmaf(f[c].y, 0.0f, fmaf(f[c].x, 0.0f, z));
                     *reinterpret_cast<float2*>(win + i) = f[c];
@@ -1054,6 +1064,7 @@ __device__ __forceinline__ WStats group_load_window(const RunArgs& a, const WIte
             }
         }
     }
+    m = fmax(m, (double)mf);
     if (interior && z != z) {  // this thread's own samples, back from LDS, as take() counts them
         m = 0.0;
         q = 0.0;
