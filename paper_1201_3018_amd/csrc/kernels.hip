@@ -2332,8 +2332,12 @@ __global__ void __launch_bounds__(64 * I8_WPB, (SS || SK || TM > 1) ? 2 : 7) k_i
             const int k0 = c * I8_KC;
             int cn = c + 1;
             if (cn >= nchunk) cn -= nchunk;
-            const int kn = cn * I8_KC;  // next chunk (after the last one: the next pass's first)
-            const bool pre = ci + 1 < nchunk || t0 + TM < ntiles;
+            const int kn = cn * I8_KC;
+            // the next chunk's fragments, or the next pass's first.  One-tile passes (short blocks,
+            // where a block has one chunk and one pass) skip the load that nothing would use; the
+            // others load unconditionally, which lets the compiler keep the two register sets
+            // without copies (measured 4-7% faster there, and 2% slower for one-tile blocks)
+            const bool pre = TM > 1 || ci + 1 < nchunk || t0 + TM < ntiles;
             if (pre) {
 #pragma unroll
                 for (int kk = 0; kk < I8_KC; ++kk) {
