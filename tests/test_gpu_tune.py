@@ -157,6 +157,31 @@ def test_td_outputs_per_thread_from_table(tmp_path, monkeypatch, mode, S, L, N, 
     assert np.array_equal(outs[0].view(np.int32), outs[1].view(np.int32))
 
 
+def test_table_lines_without_or_with_invalid_tile(tmp_path, monkeypatch):
+    """A table line without the tile field (the older format), or with a tile the core does not
+    take, gives the shape's default tile; the core and block size still come from the line."""
+    ctx = apx.Context(0)
+    arch = apx.apx_tune_describe(ctx.h).split(",")[0].split()[1]
+    ctx.close()
+    k = _dev(synth.hann_lowpass(65, 0.3))
+    cases = [(f"{arch} 65 {apx.APX_CONV} {apx.APX_ASYM2} 1024 {apx.APX_CORE_INT8} 0 1024 1.000\n", "core=int8", "tiles_per_pass=1"),
+             (f"{arch} 65 {apx.APX_CONV} {apx.APX_ASYM2} 1024 {apx.APX_CORE_INT8} 0 1024 1.000 7\n", "core=int8", "tiles_per_pass=1"),
+             (f"{arch} 65 {apx.APX_CONV} {apx.APX_ASYM2} 1024 {apx.APX_CORE_TIME} 0 1024 1.000 5\n", "core=time", "outputs_per_thread=4"),
+             (f"{arch} 65 {apx.APX_CONV} {apx.APX_ASYM2} 1024 {apx.APX_CORE_TIME} 0 1024 1.000 8\n", "core=time", "outputs_per_thread=8")]
+    for i, (line, core, tile) in enumerate(cases):
+        path = str(tmp_path / f"t{i}.txt")
+        with open(path, "w") as f:
+            f.write(line)
+        monkeypatch.setenv("APX_TUNE_FILE", path)
+        ctx = apx.Context(0)
+        kern = apx.Kernel(ctx, k, 1024, mode=apx.APX_ASYM2)
+        desc = kern.describe()
+        print("case: table line", i, desc, flush=True)
+        assert desc.startswith(core) and tile in desc, desc
+        kern.close()
+        ctx.close()
+
+
 def test_tune_errors():
     ctx = apx.Context(0)
     with pytest.raises(apx.ApxError) as e:
